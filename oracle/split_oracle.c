@@ -1,0 +1,284 @@
+/*
+ * split_oracle.c -- CPU oracle for the scenario-batched split recursion.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path links, loads or
+ * calls this file; only the tests, the smoke check and the benchmark's CPU
+ * baseline leg do.  It shares no code, header, table or helper with the HIP
+ * library.
+ *
+ * What it computes (paper Sec. 2.3, "Forward DP recursion and matrix form",
+ * and the worked 3-customer example of App. A):
+ *
+ *   For a giant tour sigma = (sigma_1..sigma_n) and one demand scenario w,
+ *     W(p,i)  = c[0][sigma_{p+1}] + sum_{k=p+1}^{i-1} c[sigma_k][sigma_{k+1}]
+ *               + c[sigma_i][depot]                     (route p+1..i)
+ *     A(p,i)  = W(p,i) if p < i and sum_{k=p+1}^{i} q_w(sigma_k) <= Q,
+ *               +inf otherwise                          (capacity mask)
+ *     J(0)    = 0,  J(i) = min_{p<i} J(p) + A(p,i),  i = 1..n.
+ *   The second-stage cost of scenario w is J(n); the sample-average
+ *   estimate is (1/|Omega|) sum_w J_w(n) with equal weights (App. A,
+ *   extensive-form objective).
+ *
+ * Readings where the paper is silent (each one is listed in the design
+ * notes): the destination depot n+1 is the depot, node 0; demands are
+ * indexed by customer id; load equal to Q is feasible (the worked example
+ * accepts a route of load exactly Q); the fleet is unlimited; a scenario in
+ * which no split exists (some customer's demand exceeds Q) has cost +inf,
+ * reported as INT32_MAX per scenario, INT64_MAX as the tour's sum and +inf
+ * as its mean; an empty tour costs 0.
+ *
+ * This is the plain O(n^2) Bellman loop: for every i it walks the
+ * predecessors p = i-1, i-2, ..., 0 while accumulating the route's load and
+ * its inner arc length.  Because demands are non-negative the load only
+ * grows as p decreases, so once it exceeds Q every smaller p is infeasible
+ * too; `use_break` stops the walk there (an exact shortcut), and with
+ * use_break = 0 the walk visits every p and masks the infeasible ones.  All
+ * arithmetic is int64, so there is no overflow question here at all.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_INF INT64_MAX
+
+/* One scenario.  q[k] = demand of tour position k (1-based, q[0] unused),
+ * V must hold n+1 entries.  Returns J(n) or OR_INF; adds the number of
+ * capacity-feasible (p,i) relaxations to *cells. */
+static int64_t split_one(const int32_t *tour, int32_t n, const int32_t *dist, int32_t N1,
+                         const int64_t *q, int64_t Q, int use_break, int64_t *V, int64_t *cells)
+{
+    V[0] = 0;
+    for (int32_t i = 1; i <= n; ++i) {
+        const int32_t last = tour[i - 1];                 /* sigma_i */
+        const int64_t back = dist[(int64_t)last * N1 + 0];  /* c[sigma_i][depot] */
+        int64_t best = OR_INF;
+        int64_t load = 0;
+        int64_t inner = 0; /* sum_{k=p+1}^{i-1} c[sigma_k][sigma_{k+1}] */
+        for (int32_t p = i - 1; p >= 0; --p) {
+            const int32_t first = tour[p];                /* sigma_{p+1} */
+            load += q[p + 1];
+            if (p + 1 <= i - 1) {
+                const int32_t nxt = tour[p + 1];          /* sigma_{p+2} */
+                inner += dist[(int64_t)first * N1 + nxt];
+            }
+            if (load > Q) {
+                if (use_break)
+                    break;
+                continue;
+            }
+            *cells += 1;
+            const int64_t w = dist[first] /* c[0][sigma_{p+1}] */ + inner + back;
+            if (V[p] != OR_INF && V[p] + w < best)
+                best = V[p] + w;
+        }
+        V[i] = best;
+    }
+    return V[n];
+}
+
+typedef struct {
+    const int32_t *tour;
+    int32_t n;
+    const int32_t *dist;
+    int32_t N;
+    const int16_t *demands;
+    int64_t s_begin, s_end;
+    int64_t Q;
+    int use_break;
+    int32_t *costs;     /* indexed by scenario */
+    int64_t sum;        /* exact sum of finite costs */
+    int64_t n_inf;
+    int64_t cells;
+    int status;
+} job_t;
+
+static void *run_job(void *arg)
+{
+    job_t *jb = (job_t *)arg;
+    const int32_t N1 = jb->N + 1;
+    int64_t *V = (int64_t *)malloc(sizeof(int64_t) * ((size_t)jb->n + 1));
+    int64_t *q = (int64_t *)malloc(sizeof(int64_t) * ((size_t)jb->n + 1));
+    if (!V || !q) {
+        jb->status = -2;
+        free(V);
+        free(q);
+        return NULL;
+    }
+    for (int64_t s = jb->s_begin; s < jb->s_end; ++s) {
+        const int16_t *row = jb->demands + s * (int64_t)jb->N;
+        q[0] = 0;
+        for (int32_t k = 1; k <= jb->n; ++k)
+            q[k] = row[jb->tour[k - 1] - 1];
+        const int64_t v = split_one(jb->tour, jb->n, jb->dist, N1, q, jb->Q, jb->use_break, V,
+                                    &jb->cells);
+        if (v == OR_INF) {
+            jb->costs[s] = INT32_MAX;
+            jb->n_inf += 1;
+        } else {
+            jb->costs[s] = (int32_t)v;
+            jb->sum += v;
+        }
+    }
+    free(V);
+    free(q);
+    return NULL;
+}
+
+/* Validate the call the same way the library's contract states. */
+static int check_args(const int32_t *tours, const int32_t *lens, int32_t num_tours, const int32_t *dist,
+                      int32_t N, const int16_t *demands, int64_t S, int32_t Q)
+{
+    if (!tours || !lens || !dist || !demands || num_tours < 1 || N < 1 || S < 1 || Q < 0)
+        return -1;
+    int64_t off = 0;
+    for (int32_t t = 0; t < num_tours; ++t) {
+        if (lens[t] < 0)
+            return -1;
+        for (int32_t k = 0; k < lens[t]; ++k)
+            if (tours[off + k] < 1 || tours[off + k] > N)
+                return -1;
+        off += lens[t];
+    }
+    return 0;
+}
+
+/*
+ * Evaluate every tour on every scenario.
+ *   costs  [num_tours * S] int32 : J_w(n_t), INT32_MAX where no split exists
+ *   sums   [num_tours]     int64 : exact sum over scenarios, INT64_MAX if any +inf
+ *   means  [num_tours]     double: sum / S (one IEEE division), +inf if any +inf
+ *   cells  [num_tours]     int64 : number of capacity-feasible relaxations
+ * nthreads >= 1 splits each tour's scenarios into contiguous blocks.
+ * Returns 0, -1 on invalid arguments, -2 on allocation failure.
+ */
+int oracle_split_eval(const int32_t *tours, const int32_t *lens, int32_t num_tours, const int32_t *dist,
+                      int32_t N, const int16_t *demands, int64_t S, int32_t Q, int32_t *costs,
+                      int64_t *sums, double *means, int64_t *cells, int use_break, int nthreads)
+{
+    if (check_args(tours, lens, num_tours, dist, N, demands, S, Q) != 0)
+        return -1;
+    if (nthreads < 1)
+        nthreads = 1;
+    if ((int64_t)nthreads > S)
+        nthreads = (int)S;
+    job_t *jobs = (job_t *)calloc((size_t)nthreads, sizeof(job_t));
+    pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
+    if (!jobs || !th) {
+        free(jobs);
+        free(th);
+        return -2;
+    }
+    int rc = 0;
+    int64_t off = 0;
+    for (int32_t t = 0; t < num_tours && rc == 0; ++t) {
+        for (int k = 0; k < nthreads; ++k) {
+            job_t *jb = &jobs[k];
+            memset(jb, 0, sizeof(*jb));
+            jb->tour = tours + off;
+            jb->n = lens[t];
+            jb->dist = dist;
+            jb->N = N;
+            jb->demands = demands;
+            jb->s_begin = S * k / nthreads;
+            jb->s_end = S * (k + 1) / nthreads;
+            jb->Q = Q;
+            jb->use_break = use_break;
+            jb->costs = costs + (int64_t)t * S;
+        }
+        if (nthreads == 1) {
+            run_job(&jobs[0]);
+        } else {
+            for (int k = 0; k < nthreads; ++k)
+                pthread_create(&th[k], NULL, run_job, &jobs[k]);
+            for (int k = 0; k < nthreads; ++k)
+                pthread_join(th[k], NULL);
+        }
+        int64_t sum = 0, n_inf = 0, c = 0;
+        for (int k = 0; k < nthreads; ++k) {
+            if (jobs[k].status)
+                rc = jobs[k].status;
+            sum += jobs[k].sum;
+            n_inf += jobs[k].n_inf;
+            c += jobs[k].cells;
+        }
+        if (sums)
+            sums[t] = n_inf ? INT64_MAX : sum;
+        if (means)
+            means[t] = n_inf ? INFINITY : (double)sum / (double)S;
+        if (cells)
+            cells[t] = c;
+        off += lens[t];
+    }
+    free(jobs);
+    free(th);
+    return rc;
+}
+
+/*
+ * Costs of selected scenarios of one tour (for spot checks at sizes where
+ * evaluating every scenario would take too long).  idx[k] in [0, S).
+ */
+int oracle_split_sample(const int32_t *tour, int32_t n, const int32_t *dist, int32_t N,
+                        const int16_t *demands, int64_t S, int32_t Q, const int64_t *idx, int64_t k,
+                        int32_t *costs_out, int64_t *cells_out)
+{
+    int32_t lens = n;
+    if (check_args(tour, &lens, 1, dist, N, demands, S, Q) != 0)
+        return -1;
+    int64_t *V = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+    int64_t *q = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+    if (!V || !q) {
+        free(V);
+        free(q);
+        return -2;
+    }
+    for (int64_t r = 0; r < k; ++r) {
+        const int64_t s = idx[r];
+        if (s < 0 || s >= S) {
+            free(V);
+            free(q);
+            return -1;
+        }
+        const int16_t *row = demands + s * (int64_t)N;
+        q[0] = 0;
+        for (int32_t m = 1; m <= n; ++m)
+            q[m] = row[tour[m - 1] - 1];
+        int64_t c = 0;
+        const int64_t v = split_one(tour, n, dist, N + 1, q, Q, 1, V, &c);
+        costs_out[r] = v == OR_INF ? INT32_MAX : (int32_t)v;
+        if (cells_out)
+            cells_out[r] = c;
+    }
+    free(V);
+    free(q);
+    return 0;
+}
+
+/*
+ * Full value vector J(0..n) of one scenario given demands in visiting
+ * order (qvis[k-1] = demand of sigma_k).  Entries with no split are
+ * INT64_MAX.  Used by the pin tests on tiny worked examples.
+ */
+int oracle_split_values(const int32_t *tour, int32_t n, const int32_t *dist, int32_t N,
+                        const int64_t *qvis, int64_t Q, int use_break, int64_t *V_out, int64_t *cells_out)
+{
+    if (!tour || !dist || !qvis || !V_out || n < 0 || N < 1 || Q < 0)
+        return -1;
+    for (int32_t k = 0; k < n; ++k)
+        if (tour[k] < 1 || tour[k] > N || qvis[k] < 0)
+            return -1;
+    int64_t *q = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+    if (!q)
+        return -2;
+    q[0] = 0;
+    for (int32_t k = 1; k <= n; ++k)
+        q[k] = qvis[k - 1];
+    int64_t c = 0;
+    split_one(tour, n, dist, N + 1, q, Q, use_break, V_out, &c);
+    if (cells_out)
+        *cells_out = c;
+    free(q);
+    return 0;
+}
