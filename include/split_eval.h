@@ -1,0 +1,157 @@
+/*
+ * split_eval.h -- C ABI of the MI355X scenario-batched split evaluator.
+ *
+ * Operation (paper Sec. 2.3, "Forward DP recursion and matrix form"; the
+ * sample-average objective of App. A):
+ *
+ *   For a giant tour sigma = (sigma_1..sigma_n) of customer ids, a travel
+ *   cost matrix c (node 0 = depot, which is also the destination depot) and
+ *   one demand scenario w, the route serving tour positions p+1..i costs
+ *     W(p,i) = c[0][sigma_{p+1}] + sum_{k=p+1}^{i-1} c[sigma_k][sigma_{k+1}]
+ *              + c[sigma_i][0]
+ *   and is admissible when its load sum_{k=p+1}^{i} q_w(sigma_k) <= Q.
+ *     V_w(0) = 0,   V_w(i) = min over admissible p < i of V_w(p) + W(p,i).
+ *   The second-stage cost of scenario w is V_w(n); the tour's SAA estimate
+ *   is the equal-weight mean of V_w(n) over all scenarios.
+ *
+ * Conventions (all integers little-endian, arrays row-major):
+ *   - customers are 1..N, node 0 is the depot; fleet size is unlimited;
+ *   - a route whose load equals Q is admissible;
+ *   - a scenario with no admissible split (some demand > Q) costs SPLIT_INF;
+ *     the tour's sum is then INT64_MAX and its mean +infinity;
+ *   - an empty tour (n = 0) costs 0 in every scenario;
+ *   - all tours of one call share the scenario set (common random numbers).
+ *
+ * Input limits (violations give SPLIT_EINVAL):
+ *   N >= 1, S >= 1, num_tours >= 1, 0 <= lens[t] <= max_len, Q >= 0,
+ *   tour ids in [1, N], every cost on a tour's route legs (depot legs and
+ *   consecutive arcs) in [0, SPLIT_MAX_COST], and
+ *   3 * n_t * (largest such cost) < 2^29 so that all int32 arithmetic is
+ *   exact; demands in [0, 32767] (int16, negative values are rejected).
+ *
+ * Results are bit-exact: per-scenario costs are int32, the sum is an exact
+ * int64, the mean is that int64 divided by S in one IEEE double division.
+ */
+#ifndef SPLIT_EVAL_H
+#define SPLIT_EVAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPLIT_OK 0
+#define SPLIT_EINVAL (-1)  /* bad argument; see the limits above */
+#define SPLIT_ENOMEM (-2)  /* device allocation failed or over the memory budget */
+#define SPLIT_EDEVICE (-3) /* HIP runtime error; text in split_last_error() */
+#define SPLIT_EAGAIN (-4)  /* served form: result not ready yet */
+
+#define SPLIT_INF INT32_MAX             /* per-scenario cost when no split exists */
+#define SPLIT_SUM_INVALID INT64_MIN     /* device-form sum of a tour whose inputs were invalid */
+#define SPLIT_MAX_COST (1 << 24)        /* largest admissible single travel cost */
+
+/* Opaque handles. */
+typedef struct split_plan split_plan;
+typedef struct split_server split_server;
+/* HIP stream handle (hipStream_t), passed as an opaque pointer. */
+typedef void *split_stream_t;
+
+/*
+ * Text of the last error on the calling thread ("" if none).  The pointer
+ * stays valid until the next library call on the same thread.
+ */
+const char *split_last_error(void);
+
+/*
+ * split_eval -- evaluate num_tours giant tours on S demand scenarios.
+ * Every pointer is HOST memory; the call is synchronous and keeps no
+ * pointer after it returns.  The caller owns all buffers.
+ *
+ *   tours   int32 [sum(lens)]   concatenated tours (customer ids 1..N)
+ *   lens    int32 [num_tours]   tour lengths n_t >= 0
+ *   dist    int32 [(N+1)*(N+1)] dist[a*(N+1)+b] = cost of arc a -> b
+ *   demands int16 [S*N]         scenario-major: demands[s*N + (c-1)]
+ *   Q       vehicle capacity
+ *   costs   out int32 [num_tours*S]  costs[t*S + s] = V_s(n_t) or SPLIT_INF
+ *   sums    out int64 [num_tours]    exact sums (INT64_MAX if any SPLIT_INF); may be NULL
+ *   means   out double [num_tours]   sums/S (+inf if any SPLIT_INF); may be NULL
+ *
+ * Returns SPLIT_OK, or an error code with the outputs left untouched.
+ */
+int split_eval(const int32_t *tours, const int32_t *lens, int32_t num_tours, const int32_t *dist,
+               int32_t N, const int16_t *demands, int64_t S, int32_t Q, int32_t *costs,
+               int64_t *sums, double *means);
+
+/*
+ * Device-memory workspace needed by split_eval_device for these sizes.
+ */
+size_t split_workspace_bytes(int32_t num_tours, int32_t max_len, int32_t N, int64_t S);
+
+/*
+ * split_eval_device -- same operation on DEVICE pointers, enqueued on
+ * `stream`; returns once the work is enqueued (nothing is allocated, no
+ * host synchronisation, no memset or copy: safe to capture in a HIP graph).
+ *
+ *   d_tours, d_lens, d_dist, d_demands : device inputs as in split_eval;
+ *       d_demands must be 16-byte aligned.
+ *   max_len   host-side upper bound on every lens[t] (sizes the workspace)
+ *   d_costs, d_sums, d_means : device outputs as in split_eval (none NULL)
+ *   d_workspace, ws_bytes : caller-owned device scratch of at least
+ *       split_workspace_bytes(num_tours, max_len, N, S) bytes, 256-aligned.
+ *
+ * Host-checkable arguments (sizes, Q, alignment, workspace size) are
+ * validated before anything is enqueued.  Per-tour contents (ids, costs,
+ * lengths, demands) are validated on the device: a tour that fails gets
+ * SPLIT_INF costs, SPLIT_SUM_INVALID as its sum and NaN as its mean.
+ * The library reads the inputs and writes the outputs and workspace only
+ * until the enqueued work completes.  Two calls sharing a workspace must
+ * be ordered on one stream.
+ */
+int split_eval_device(const int32_t *d_tours, const int32_t *d_lens, int32_t num_tours,
+                      int32_t max_len, const int32_t *d_dist, int32_t N,
+                      const int16_t *d_demands, int64_t S, int32_t Q, int32_t *d_costs,
+                      int64_t *d_sums, double *d_means, void *d_workspace, size_t ws_bytes,
+                      split_stream_t stream);
+
+/*
+ * split_count_cells_device -- Bellman-cell counter (measurement utility).
+ * For each tour writes the number of capacity-admissible relaxations
+ * (s, p, i), i.e. sum over scenarios and positions i of the number of
+ * predecessors p < i whose route p+1..i has load <= Q.  Device pointers,
+ * enqueued on `stream`; d_cells is int64 [num_tours].  Tours must already
+ * be valid (no device-side validation).
+ */
+int split_count_cells_device(const int32_t *d_tours, const int32_t *d_lens, int32_t num_tours,
+                             int32_t N, const int16_t *d_demands, int64_t S, int32_t Q,
+                             int64_t *d_cells, split_stream_t stream);
+
+/*
+ * split_set_ring -- schedule override for every later call in the process:
+ * ring = 32 or 64 forces the register-ring length of the main kernel
+ * (windows longer than the ring are recomputed by the exact fallback, so
+ * results never depend on it), 0 restores the automatic choice.  Returns
+ * SPLIT_EINVAL for other values.  Not thread-safe against concurrent calls.
+ */
+int split_set_ring(int32_t ring);
+
+/*
+ * Plans: the batched form.  A plan binds one set of device buffers and
+ * sizes, owns its workspace, and captures the evaluation into a HIP graph
+ * once; split_plan_launch replays it.  Rewriting the contents of d_tours,
+ * d_lens (within max_len), d_demands between launches is allowed (the GA
+ * pattern: new candidate tours, same shapes).
+ */
+int split_plan_create(split_plan **plan, const int32_t *d_tours, const int32_t *d_lens,
+                      int32_t num_tours, int32_t max_len, const int32_t *d_dist, int32_t N,
+                      const int16_t *d_demands, int64_t S, int32_t Q, int32_t *d_costs,
+                      int64_t *d_sums, double *d_means, split_stream_t stream);
+int split_plan_launch(split_plan *plan, split_stream_t stream);
+int split_plan_destroy(split_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPLIT_EVAL_H */

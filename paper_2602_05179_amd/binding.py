@@ -1,0 +1,219 @@
+"""Thin ctypes binding of libsplit_eval.so (C ABI in include/split_eval.h).
+
+Argument marshalling only: every step of the evaluation runs in the HIP
+kernels of the library.  PyTorch is used for device memory and streams.
+Importing this module raises if the shared library has not been built:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from .build_lib import LIB as LIB_PATH
+
+SPLIT_OK = 0
+SPLIT_EINVAL = -1
+SPLIT_ENOMEM = -2
+SPLIT_EDEVICE = -3
+SPLIT_EAGAIN = -4
+SPLIT_INF = np.iinfo(np.int32).max
+SPLIT_SUM_INVALID = np.iinfo(np.int64).min
+
+EXPORTED = (
+    "split_last_error",
+    "split_eval",
+    "split_workspace_bytes",
+    "split_eval_device",
+    "split_count_cells_device",
+    "split_plan_create",
+    "split_plan_launch",
+    "split_plan_destroy",
+    "split_set_ring",
+)
+
+
+class SplitError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("split library error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _load():
+    # PyTorch-ROCm ships its own HIP runtime under the same soname; loading it
+    # first makes this library bind to that one copy instead of a second one.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libsplit_eval.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    lib.split_last_error.restype = ctypes.c_char_p
+    lib.split_last_error.argtypes = []
+    lib.split_eval.restype = ctypes.c_int
+    lib.split_eval.argtypes = [P, P, i32, P, i32, P, i64, i32, P, P, P]
+    lib.split_workspace_bytes.restype = sz
+    lib.split_workspace_bytes.argtypes = [i32, i32, i32, i64]
+    lib.split_eval_device.restype = ctypes.c_int
+    lib.split_eval_device.argtypes = [P, P, i32, i32, P, i32, P, i64, i32, P, P, P, P, sz, P]
+    lib.split_count_cells_device.restype = ctypes.c_int
+    lib.split_count_cells_device.argtypes = [P, P, i32, i32, P, i64, i32, P, P]
+    lib.split_plan_create.restype = ctypes.c_int
+    lib.split_plan_create.argtypes = [ctypes.POINTER(P), P, P, i32, i32, P, i32, P, i64, i32, P, P, P, P]
+    lib.split_plan_launch.restype = ctypes.c_int
+    lib.split_plan_launch.argtypes = [P, P]
+    lib.split_plan_destroy.restype = ctypes.c_int
+    lib.split_plan_destroy.argtypes = [P]
+    lib.split_set_ring.restype = ctypes.c_int
+    lib.split_set_ring.argtypes = [i32]
+    return lib
+
+
+lib = _load()
+
+
+def last_error() -> str:
+    return lib.split_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != SPLIT_OK:
+        raise SplitError(rc, last_error())
+
+
+def set_ring(ring: int):
+    """Force the register-ring length (32 or 64); 0 = automatic."""
+    _check(lib.split_set_ring(int(ring)))
+
+
+def _np_ptr(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+# ---------------------------------------------------------------------------
+# host form
+# ---------------------------------------------------------------------------
+def split_eval(tours, lens, dist, demands, Q):
+    """Host arrays in, host arrays out (synchronous).
+
+    Returns dict(costs=int32[T, S], sums=int64[T], means=float64[T])."""
+    tours = np.ascontiguousarray(tours, np.int32)
+    lens = np.ascontiguousarray(lens, np.int32)
+    dist = np.ascontiguousarray(dist, np.int32)
+    demands = np.ascontiguousarray(demands, np.int16)
+    T = int(lens.size)
+    N = int(dist.shape[0] - 1)
+    S = int(demands.shape[0])
+    if demands.ndim != 2 or demands.shape[1] != N or dist.shape != (N + 1, N + 1):
+        raise SplitError(SPLIT_EINVAL, "shape mismatch: dist %s demands %s" % (dist.shape, demands.shape))
+    if int(lens.sum()) != tours.size:
+        raise SplitError(SPLIT_EINVAL, "sum(lens) != len(tours)")
+    costs = np.empty((T, S), np.int32)
+    sums = np.empty(T, np.int64)
+    means = np.empty(T, np.float64)
+    _check(lib.split_eval(_np_ptr(tours), _np_ptr(lens), T, _np_ptr(dist), N, _np_ptr(demands), S, int(Q),
+                          _np_ptr(costs), _np_ptr(sums), _np_ptr(means)))
+    return dict(costs=costs, sums=sums, means=means)
+
+
+# ---------------------------------------------------------------------------
+# device form (torch tensors on the GPU)
+# ---------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def workspace_bytes(num_tours: int, max_len: int, N: int, S: int) -> int:
+    return int(lib.split_workspace_bytes(int(num_tours), int(max_len), int(N), int(S)))
+
+
+class DeviceOutputs:
+    def __init__(self, T: int, S: int, device):
+        torch = _torch()
+        self.costs = torch.empty((T, S), dtype=torch.int32, device=device)
+        self.sums = torch.empty(T, dtype=torch.int64, device=device)
+        self.means = torch.empty(T, dtype=torch.float64, device=device)
+
+
+def split_eval_device(tours, lens, dist, demands, Q, *, max_len=None, out=None, workspace=None,
+                      stream=None):
+    """Enqueue an evaluation on device tensors; returns DeviceOutputs.
+
+    tours int32 [sum(lens)], lens int32 [T], dist int32 [N+1, N+1],
+    demands int16 [S, N] (16-byte aligned), all on the same GPU."""
+    torch = _torch()
+    T = int(lens.numel())
+    N = int(dist.shape[0] - 1)
+    S = int(demands.shape[0])
+    for name, t, dt in (("tours", tours, torch.int32), ("lens", lens, torch.int32),
+                        ("dist", dist, torch.int32), ("demands", demands, torch.int16)):
+        if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+            raise SplitError(SPLIT_EINVAL, "%s must be a contiguous %s CUDA tensor" % (name, dt))
+    if max_len is None:
+        max_len = int(lens.max().item()) if T else 0
+    if out is None:
+        out = DeviceOutputs(T, S, demands.device)
+    need = workspace_bytes(T, max_len, N, S)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=demands.device)
+    _check(lib.split_eval_device(_dptr(tours), _dptr(lens), T, int(max_len), _dptr(dist), N, _dptr(demands), S,
+                                 int(Q), _dptr(out.costs), _dptr(out.sums), _dptr(out.means), _dptr(workspace),
+                                 int(workspace.numel()), _stream_handle(stream)))
+    out.workspace = workspace
+    return out
+
+
+def split_count_cells_device(tours, lens, demands, N, Q, *, stream=None):
+    """Number of capacity-admissible relaxations per tour (int64 tensor)."""
+    torch = _torch()
+    T = int(lens.numel())
+    S = int(demands.shape[0])
+    cells = torch.empty(T, dtype=torch.int64, device=demands.device)
+    _check(lib.split_count_cells_device(_dptr(tours), _dptr(lens), T, int(N), _dptr(demands), S, int(Q),
+                                        _dptr(cells), _stream_handle(stream)))
+    return cells
+
+
+class Plan:
+    """Batched form: workspace + captured HIP graph over fixed device buffers."""
+
+    def __init__(self, tours, lens, dist, demands, Q, max_len, out=None, stream=None):
+        T = int(lens.numel())
+        N = int(dist.shape[0] - 1)
+        S = int(demands.shape[0])
+        self.out = out if out is not None else DeviceOutputs(T, S, demands.device)
+        self._keep = (tours, lens, dist, demands)
+        self._h = ctypes.c_void_p()
+        _check(lib.split_plan_create(ctypes.byref(self._h), _dptr(tours), _dptr(lens), T, int(max_len), _dptr(dist),
+                                     N, _dptr(demands), S, int(Q), _dptr(self.out.costs), _dptr(self.out.sums),
+                                     _dptr(self.out.means), _stream_handle(stream)))
+
+    def launch(self, stream=None):
+        _check(lib.split_plan_launch(self._h, _stream_handle(stream)))
+        return self.out
+
+    def close(self):
+        if self._h:
+            lib.split_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,384 @@
+// split_api.cpp -- host side of the C ABI declared in include/split_eval.h.
+//
+// Argument checking, device buffer management for the synchronous host
+// form, the device form, and plans (HIP-graph capture of the batched form).
+// All compute runs in the kernels of split_kernels.hip.
+
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+#include <vector>
+
+#include "split_eval.h"
+#include "split_internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    if (e == hipErrorOutOfMemory)
+        return fail(SPLIT_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+    return fail(SPLIT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                                                                      \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return hip_fail(e_, what);                                                           \
+    } while (0)
+
+// Checks that need only scalars (shared by every form).
+int check_scalars(int32_t num_tours, int32_t N, int64_t S, int32_t Q, int32_t max_len)
+{
+    if (num_tours < 1)
+        return fail(SPLIT_EINVAL, "num_tours must be >= 1 (got %d)", num_tours);
+    if (N < 1)
+        return fail(SPLIT_EINVAL, "N must be >= 1 (got %d)", N);
+    if (S < 1)
+        return fail(SPLIT_EINVAL, "S must be >= 1 (got %lld)", (long long)S);
+    if (Q < 0)
+        return fail(SPLIT_EINVAL, "Q must be >= 0 (got %d)", Q);
+    if (max_len < 0 || max_len > splitk::kMaxLen)
+        return fail(SPLIT_EINVAL, "tour length must be in [0, %d] (got %d)", splitk::kMaxLen,
+                    max_len);
+    const int64_t tiles = splitk::num_tiles(S);
+    if ((int64_t)num_tours * tiles > (int64_t)INT32_MAX)
+        return fail(SPLIT_EINVAL, "num_tours * ceil(S/64) exceeds 2^31-1");
+    return SPLIT_OK;
+}
+
+// Host-side validation of tours and the cost legs they use (host form).
+int check_tours_host(const int32_t *tours, const int32_t *lens, int32_t T, const int32_t *dist,
+                     int32_t N, int32_t *max_len_out, int64_t *total_out)
+{
+    const int64_t N1 = (int64_t)N + 1;
+    int64_t off = 0;
+    int32_t max_len = 0;
+    for (int32_t t = 0; t < T; ++t) {
+        const int32_t n = lens[t];
+        if (n < 0 || n > splitk::kMaxLen)
+            return fail(SPLIT_EINVAL, "lens[%d] = %d outside [0, %d]", t, n, splitk::kMaxLen);
+        int64_t maxc = 0;
+        for (int32_t k = 0; k < n; ++k) {
+            const int32_t c = tours[off + k];
+            if (c < 1 || c > N)
+                return fail(SPLIT_EINVAL, "tour %d position %d: customer id %d outside [1, %d]", t,
+                            k + 1, c, N);
+            const int32_t legs[3] = {dist[c], dist[c * N1],
+                                     k + 1 < n ? dist[c * N1 + tours[off + k + 1]] : 0};
+            if (k + 1 < n && (tours[off + k + 1] < 1 || tours[off + k + 1] > N))
+                return fail(SPLIT_EINVAL, "tour %d position %d: customer id %d outside [1, %d]",
+                            t, k + 2, tours[off + k + 1], N);
+            for (int32_t v : legs) {
+                if (v < 0 || v > SPLIT_MAX_COST)
+                    return fail(SPLIT_EINVAL, "tour %d: travel cost %d outside [0, %d]", t, v,
+                                SPLIT_MAX_COST);
+                if (v > maxc)
+                    maxc = v;
+            }
+        }
+        if (3 * (int64_t)n * maxc >= (int64_t)1 << 29)
+            return fail(SPLIT_EINVAL,
+                        "tour %d: 3 * n * max cost = %lld >= 2^29 (int32 exactness guard)", t,
+                        (long long)(3 * (int64_t)n * maxc));
+        if (n > max_len)
+            max_len = n;
+        off += n;
+    }
+    *max_len_out = max_len;
+    *total_out = off;
+    return SPLIT_OK;
+}
+
+// Device buffers of the synchronous host form, grown on demand.
+struct HostCtx {
+    std::mutex mu;
+    int device = -1;
+    hipStream_t stream = nullptr;
+    struct Buf {
+        void *p = nullptr;
+        size_t cap = 0;
+    };
+    Buf tours, lens, dist, demands, costs, sums, means, ws;
+    ~HostCtx() = default; // buffers live until process exit
+};
+
+HostCtx g_ctx;
+
+int g_ring_override = 0; // 0 = automatic
+
+splitk::Schedule pick_schedule(int32_t N, int64_t S, int32_t Q)
+{
+    splitk::Schedule s = splitk::default_schedule(N, S, Q);
+    if (g_ring_override)
+        s.ring = g_ring_override;
+    return s;
+}
+
+hipError_t ensure(HostCtx::Buf &b, size_t bytes)
+{
+    if (bytes == 0)
+        bytes = 256;
+    if (b.cap >= bytes)
+        return hipSuccess;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        if (e != hipSuccess)
+            return e;
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e == hipSuccess)
+        b.cap = bytes;
+    return e;
+}
+
+} // namespace
+
+extern "C" {
+
+const char *split_last_error(void) { return g_err; }
+
+int split_set_ring(int32_t ring)
+{
+    g_err[0] = 0;
+    if (ring != 0 && ring != 32 && ring != 64)
+        return fail(SPLIT_EINVAL, "ring must be 0, 32 or 64 (got %d)", ring);
+    g_ring_override = ring;
+    return SPLIT_OK;
+}
+
+size_t split_workspace_bytes(int32_t num_tours, int32_t max_len, int32_t N, int64_t S)
+{
+    (void)N;
+    if (num_tours < 1 || max_len < 0 || S < 1)
+        return 0;
+    return splitk::workspace_bytes(num_tours, max_len, S);
+}
+
+int split_eval_device(const int32_t *d_tours, const int32_t *d_lens, int32_t num_tours,
+                      int32_t max_len, const int32_t *d_dist, int32_t N,
+                      const int16_t *d_demands, int64_t S, int32_t Q, int32_t *d_costs,
+                      int64_t *d_sums, double *d_means, void *d_workspace, size_t ws_bytes,
+                      split_stream_t stream)
+{
+    g_err[0] = 0;
+    int rc = check_scalars(num_tours, N, S, Q, max_len);
+    if (rc)
+        return rc;
+    if (!d_tours || !d_lens || !d_dist || !d_demands || !d_costs || !d_sums || !d_means ||
+        !d_workspace)
+        return fail(SPLIT_EINVAL, "null pointer argument");
+    if (reinterpret_cast<uintptr_t>(d_demands) % 16)
+        return fail(SPLIT_EINVAL, "demands must be 16-byte aligned");
+    if (reinterpret_cast<uintptr_t>(d_workspace) % 256)
+        return fail(SPLIT_EINVAL, "workspace must be 256-byte aligned");
+    const size_t need = splitk::workspace_bytes(num_tours, max_len, S);
+    if (ws_bytes < need)
+        return fail(SPLIT_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+    const splitk::Workspace ws = splitk::carve_workspace(d_workspace, num_tours, max_len, S);
+    const splitk::Schedule sched = pick_schedule(N, S, Q);
+    HIP_TRY(splitk::launch_eval(d_tours, d_lens, num_tours, max_len, d_dist, N, d_demands, S, Q,
+                                d_costs, d_sums, d_means, ws, static_cast<hipStream_t>(stream),
+                                sched),
+            "launch");
+    return SPLIT_OK;
+}
+
+int split_eval(const int32_t *tours, const int32_t *lens, int32_t num_tours, const int32_t *dist,
+               int32_t N, const int16_t *demands, int64_t S, int32_t Q, int32_t *costs,
+               int64_t *sums, double *means)
+{
+    g_err[0] = 0;
+    if (!tours || !lens || !dist || !demands || !costs)
+        return fail(SPLIT_EINVAL, "null pointer argument");
+    int rc = check_scalars(num_tours, N, S, Q, 0);
+    if (rc)
+        return rc;
+    int32_t max_len = 0;
+    int64_t total = 0;
+    rc = check_tours_host(tours, lens, num_tours, dist, N, &max_len, &total);
+    if (rc)
+        return rc;
+
+    std::lock_guard<std::mutex> lock(g_ctx.mu);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (g_ctx.stream == nullptr || g_ctx.device != dev) {
+        HIP_TRY(hipStreamCreateWithFlags(&g_ctx.stream, hipStreamNonBlocking), "stream");
+        g_ctx.device = dev;
+    }
+    hipStream_t st = g_ctx.stream;
+    const size_t n1sq = ((size_t)N + 1) * ((size_t)N + 1);
+    const size_t ws_bytes = splitk::workspace_bytes(num_tours, max_len, S);
+    HIP_TRY(ensure(g_ctx.tours, (size_t)total * 4), "alloc tours");
+    HIP_TRY(ensure(g_ctx.lens, (size_t)num_tours * 4), "alloc lens");
+    HIP_TRY(ensure(g_ctx.dist, n1sq * 4), "alloc dist");
+    HIP_TRY(ensure(g_ctx.demands, (size_t)S * N * 2), "alloc demands");
+    HIP_TRY(ensure(g_ctx.costs, (size_t)num_tours * S * 4), "alloc costs");
+    HIP_TRY(ensure(g_ctx.sums, (size_t)num_tours * 8), "alloc sums");
+    HIP_TRY(ensure(g_ctx.means, (size_t)num_tours * 8), "alloc means");
+    HIP_TRY(ensure(g_ctx.ws, ws_bytes), "alloc workspace");
+
+    if (total)
+        HIP_TRY(hipMemcpyAsync(g_ctx.tours.p, tours, (size_t)total * 4, hipMemcpyHostToDevice, st),
+                "copy tours");
+    HIP_TRY(hipMemcpyAsync(g_ctx.lens.p, lens, (size_t)num_tours * 4, hipMemcpyHostToDevice, st),
+            "copy lens");
+    HIP_TRY(hipMemcpyAsync(g_ctx.dist.p, dist, n1sq * 4, hipMemcpyHostToDevice, st), "copy dist");
+    HIP_TRY(hipMemcpyAsync(g_ctx.demands.p, demands, (size_t)S * N * 2, hipMemcpyHostToDevice, st),
+            "copy demands");
+    const splitk::Workspace ws =
+        splitk::carve_workspace(g_ctx.ws.p, num_tours, max_len, S);
+    const splitk::Schedule sched = pick_schedule(N, S, Q);
+    HIP_TRY(splitk::launch_eval(static_cast<int32_t *>(g_ctx.tours.p),
+                                static_cast<int32_t *>(g_ctx.lens.p), num_tours, max_len,
+                                static_cast<int32_t *>(g_ctx.dist.p), N,
+                                static_cast<int16_t *>(g_ctx.demands.p), S, Q,
+                                static_cast<int32_t *>(g_ctx.costs.p),
+                                static_cast<int64_t *>(g_ctx.sums.p),
+                                static_cast<double *>(g_ctx.means.p), ws, st, sched),
+            "launch");
+    std::vector<int64_t> hs(num_tours);
+    std::vector<double> hm(num_tours);
+    HIP_TRY(hipMemcpyAsync(hs.data(), g_ctx.sums.p, (size_t)num_tours * 8, hipMemcpyDeviceToHost,
+                           st),
+            "copy sums");
+    HIP_TRY(hipMemcpyAsync(hm.data(), g_ctx.means.p, (size_t)num_tours * 8,
+                           hipMemcpyDeviceToHost, st),
+            "copy means");
+    HIP_TRY(hipStreamSynchronize(st), "synchronize");
+    for (int32_t t = 0; t < num_tours; ++t)
+        if (hs[t] == SPLIT_SUM_INVALID)
+            return fail(SPLIT_EINVAL, "tour %d: invalid input found on the device "
+                                      "(negative demand)", t);
+    HIP_TRY(hipMemcpy(costs, g_ctx.costs.p, (size_t)num_tours * S * 4, hipMemcpyDeviceToHost),
+            "copy costs");
+    if (sums)
+        memcpy(sums, hs.data(), (size_t)num_tours * 8);
+    if (means)
+        memcpy(means, hm.data(), (size_t)num_tours * 8);
+    return SPLIT_OK;
+}
+
+int split_count_cells_device(const int32_t *d_tours, const int32_t *d_lens, int32_t num_tours,
+                             int32_t N, const int16_t *d_demands, int64_t S, int32_t Q,
+                             int64_t *d_cells, split_stream_t stream)
+{
+    g_err[0] = 0;
+    int rc = check_scalars(num_tours, N, S, Q, 0);
+    if (rc)
+        return rc;
+    if (!d_tours || !d_lens || !d_demands || !d_cells)
+        return fail(SPLIT_EINVAL, "null pointer argument");
+    HIP_TRY(splitk::launch_count_cells(d_tours, d_lens, num_tours, N, d_demands, S, Q, d_cells,
+                                       static_cast<hipStream_t>(stream)),
+            "launch");
+    return SPLIT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// plans: workspace + captured graph
+// ---------------------------------------------------------------------------
+struct split_plan {
+    void *ws = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+int split_plan_create(split_plan **plan, const int32_t *d_tours, const int32_t *d_lens,
+                      int32_t num_tours, int32_t max_len, const int32_t *d_dist, int32_t N,
+                      const int16_t *d_demands, int64_t S, int32_t Q, int32_t *d_costs,
+                      int64_t *d_sums, double *d_means, split_stream_t stream)
+{
+    g_err[0] = 0;
+    if (!plan)
+        return fail(SPLIT_EINVAL, "null plan pointer");
+    int rc = check_scalars(num_tours, N, S, Q, max_len);
+    if (rc)
+        return rc;
+    split_plan *p = new split_plan();
+    const size_t bytes = splitk::workspace_bytes(num_tours, max_len, S);
+    hipError_t e = hipMalloc(&p->ws, bytes);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "plan workspace");
+    }
+    hipStream_t cap = nullptr;
+    e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        (void)hipFree(p->ws);
+        delete p;
+        return hip_fail(e, "capture stream");
+    }
+    (void)stream;
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        rc = split_eval_device(d_tours, d_lens, num_tours, max_len, d_dist, N, d_demands, S, Q,
+                               d_costs, d_sums, d_means, p->ws, bytes, cap);
+        hipError_t e2 = hipStreamEndCapture(cap, &p->graph);
+        if (rc == SPLIT_OK && e2 != hipSuccess)
+            rc = hip_fail(e2, "end capture");
+    } else {
+        rc = hip_fail(e, "begin capture");
+    }
+    if (rc == SPLIT_OK) {
+        e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess)
+            rc = hip_fail(e, "graph instantiate");
+    }
+    (void)hipStreamDestroy(cap);
+    if (rc != SPLIT_OK) {
+        if (p->exec)
+            (void)hipGraphExecDestroy(p->exec);
+        if (p->graph)
+            (void)hipGraphDestroy(p->graph);
+        (void)hipFree(p->ws);
+        delete p;
+        return rc;
+    }
+    *plan = p;
+    return SPLIT_OK;
+}
+
+int split_plan_launch(split_plan *plan, split_stream_t stream)
+{
+    g_err[0] = 0;
+    if (!plan || !plan->exec)
+        return fail(SPLIT_EINVAL, "null plan");
+    HIP_TRY(hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream)), "graph launch");
+    return SPLIT_OK;
+}
+
+int split_plan_destroy(split_plan *plan)
+{
+    g_err[0] = 0;
+    if (!plan)
+        return SPLIT_OK;
+    if (plan->exec)
+        (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph)
+        (void)hipGraphDestroy(plan->graph);
+    if (plan->ws)
+        (void)hipFree(plan->ws);
+    delete plan;
+    return SPLIT_OK;
+}
+
+} // extern "C"

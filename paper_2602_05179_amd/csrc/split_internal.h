@@ -1,0 +1,56 @@
+// split_internal.h -- types shared by the kernels and the host side of the
+// library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace splitk {
+
+// Per-tour constants produced by the prep kernel.
+struct TourRec {
+    int n;      // tour length
+    int f0;     // first potential: V(0) + a_1 = c[0][sigma_1]
+    int bn;     // b_n = D_n + c[sigma_n][0]; V(n) = m_n + b_n
+    int status; // 0 ok, else a bit set of validation failures
+};
+
+// Device scratch carved from one caller- or library-owned allocation.
+struct Workspace {
+    int2 *st;              // [T * max_len] {customer index, c_j}
+    int2 *ab;              // [T * max_len] {a_j, b_j} (exact fallback)
+    TourRec *rec;          // [T]
+    long long *tile_sum;   // [units] exact sum of finite costs of a unit
+    int *tile_inf;         // [units] number of SPLIT_INF costs of a unit
+    int *list;             // [units] units handed to the exact fallback
+    int *list_count;       // [1]
+    int *vscratch;         // [fallback blocks * 64 * (max_len + 1)] value history
+    int max_len;
+};
+
+// How the main kernel runs.
+struct Schedule {
+    int ring; // register ring length R (32 or 64)
+};
+
+constexpr int kTile = 64;            // scenarios per unit (one wave)
+constexpr int kMaxLen = 65535;       // longest tour the library accepts
+constexpr int kLdsLimit = 160 * 1024; // LDS bytes one workgroup may use on gfx950
+
+int64_t num_tiles(int64_t S);
+size_t workspace_bytes(int32_t T, int32_t max_len, int64_t S);
+Workspace carve_workspace(void *base, int32_t T, int32_t max_len, int64_t S);
+
+hipError_t launch_eval(const int32_t *tours, const int32_t *lens, int32_t T, int32_t max_len,
+                       const int32_t *dist, int32_t N, const int16_t *demands, int64_t S,
+                       int32_t Q, int32_t *costs, int64_t *sums, double *means,
+                       const Workspace &ws, hipStream_t stream, const Schedule &sched);
+
+hipError_t launch_count_cells(const int32_t *tours, const int32_t *lens, int32_t T, int32_t N,
+                              const int16_t *demands, int64_t S, int32_t Q, int64_t *cells,
+                              hipStream_t stream);
+
+Schedule default_schedule(int32_t N, int64_t S, int32_t Q);
+
+} // namespace splitk

@@ -1,0 +1,743 @@
+// split_kernels.hip -- gfx950 kernels of the scenario-batched split evaluator.
+//
+// The recursion (paper Sec. 2.3): V(0) = 0,
+//   V(i) = min over admissible p < i of V(p) + W(p,i),
+// with W(p,i) the cost of the route depot -> sigma_{p+1} .. sigma_i -> depot
+// and "admissible" meaning the route's load is at most Q.
+//
+// Potential form used on the GPU.  With out_k = c[0][sigma_k],
+// in_k = c[sigma_k][0], arc_k = c[sigma_k][sigma_{k+1}] and
+// D_k = sum_{m<k} arc_m, the route cost splits into two one-index terms,
+//   W(p,i) = a_{p+1} + b_i,   a_k = out_k - D_k,   b_i = D_i + in_i,
+// so V(i) = b_i + min_{p in window(i)} f_p with f_p = V(p) + a_{p+1}.
+// Writing m_i = min_{p in window(i)} f_p, the next potential is
+//   f_i = m_i + c_i,   c_i = b_i + a_{i+1} = in_i + out_{i+1} - arc_i,
+// and V(n) = m_n + b_n.  The window of admissible predecessors is a
+// contiguous range [p_min(i), i-1] because demands are non-negative, and
+// both of its ends are non-decreasing in i (the monotone structure the
+// paper's deque kernel relies on, App. A "Pseudo-code for 2D kernel").
+//
+// Lane layout: one scenario per lane, a tile of 64 scenarios per wave.  A
+// tile's demand rows (int16, scenario-major, contiguous in HBM) are streamed
+// into LDS with 16-byte coalesced loads and narrowed to bytes when every
+// value of the tile fits (the common case); each lane then gathers its
+// demands through the tour from its own LDS row.  The last R potentials
+// f_p and thresholds L_p + Q of a lane live in registers; the j loop is
+// unrolled R times so every ring slot is a compile-time register.  The
+// masked window minimum runs in two regimes:
+//   head: while every lane of the wave admits predecessor d+1 (one compare,
+//         one ballot), two potentials are folded per v_min3 with no mask;
+//   tail: beyond that, each predecessor is masked per lane and the scan
+//         stops when no lane admits it any more.
+// A lane whose window reaches past the ring, and any tile whose demands do
+// not fit a byte, are recomputed by an exact fallback kernel.
+//
+// Infeasible scenarios (some demand > Q) need no special case: an empty
+// window leaves m = INF, and every later value stays >= INF because all
+// route costs are non-negative, while feasible values stay < 2^29 under the
+// documented cost guard; V(n) >= INF is reported as SPLIT_INF.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <utility>
+
+#include "split_eval.h"
+#include "split_internal.h"
+
+namespace splitk {
+
+constexpr int kWave = 64;
+constexpr int kInf = 1 << 30;    // "+inf" potential sentinel
+constexpr int kNeg = -(1 << 30); // threshold of ring slots before the tour start
+
+enum : int { ST_OK = 0, ST_BAD_TOUR = 1, ST_BAD_DEMAND = 2 };
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+__device__ __forceinline__ int min3i(int a, int b, int c) { return min(a, min(b, c)); }
+
+__device__ __forceinline__ long long wave_sum_i64(long long v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum_i32(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// prep: per-tour constants (state table), validation, counter reset
+// grid = num_tours blocks of 256 threads
+// ---------------------------------------------------------------------------
+constexpr int kPrepThreads = 256;
+
+__global__ __launch_bounds__(kPrepThreads) void prep_kernel(
+    const int32_t *__restrict__ tours, const int32_t *__restrict__ lens, int32_t num_tours,
+    int32_t max_len, const int32_t *__restrict__ dist, int32_t N, Workspace ws)
+{
+    __shared__ long long s_red[kPrepThreads / kWave];
+    __shared__ int s_redi[kPrepThreads / kWave];
+    __shared__ long long s_carry;
+    __shared__ long long s_scan[kPrepThreads / kWave];
+
+    const int t = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1), wid = tid / kWave;
+    const int64_t N1 = (int64_t)N + 1;
+
+    if (t == 0 && tid == 0)
+        *ws.list_count = 0;
+
+    // offset of this tour in the concatenated array; an invalid earlier
+    // length makes the layout ambiguous, so this tour is rejected too
+    long long off = 0;
+    int prev_bad = 0;
+    for (int i = tid; i < t; i += kPrepThreads) {
+        const int li = lens[i];
+        prev_bad |= (li < 0 || li > max_len) ? 1 : 0;
+        off += li;
+    }
+    off = wave_sum_i64(off);
+    prev_bad = wave_sum_i32(prev_bad);
+    if (lane == 0) {
+        s_red[wid] = off;
+        s_redi[wid] = prev_bad;
+    }
+    __syncthreads();
+    off = 0;
+    prev_bad = 0;
+#pragma unroll
+    for (int w = 0; w < kPrepThreads / kWave; ++w) {
+        off += s_red[w];
+        prev_bad += s_redi[w];
+    }
+    __syncthreads();
+
+    const int n = lens[t];
+    int bad = (n < 0 || n > max_len || prev_bad) ? 1 : 0;
+    const int nn = bad ? 0 : n;
+    int maxc = 0;
+    if (tid == 0)
+        s_carry = 0;
+    __syncthreads();
+
+    int2 *st = ws.st + (int64_t)t * max_len;
+    int2 *ab = ws.ab + (int64_t)t * max_len;
+    for (int base = 0; base < nn; base += kPrepThreads) {
+        const int k = base + tid; // tour position k+1 (0-based k)
+        long long arc = 0;
+        int c = 0, out = 0, in = 0, cn = 0, outn = 0, a = 0;
+        if (k < nn) {
+            c = tours[off + k];
+            if (c < 1 || c > N) {
+                bad = 1;
+                c = 1;
+            }
+            out = dist[c];
+            in = dist[(int64_t)c * N1];
+            if (k + 1 < nn) {
+                cn = tours[off + k + 1];
+                if (cn < 1 || cn > N) {
+                    bad = 1;
+                    cn = 1;
+                }
+                a = dist[(int64_t)c * N1 + cn];
+                outn = dist[cn];
+                arc = a;
+            }
+            if (out < 0 || in < 0 || a < 0 || out > SPLIT_MAX_COST || in > SPLIT_MAX_COST ||
+                a > SPLIT_MAX_COST)
+                bad = 1;
+            maxc = max(maxc, max(out, max(in, a)));
+        }
+        // exclusive prefix of arc over positions: D_{k+1} = sum_{m<k} arc_m
+        long long incl = arc;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            long long y = __shfl_up(incl, o, kWave);
+            if (lane >= o)
+                incl += y;
+        }
+        if (lane == kWave - 1)
+            s_scan[wid] = incl;
+        __syncthreads();
+        long long pre = s_carry;
+        for (int w = 0; w < wid; ++w)
+            pre += s_scan[w];
+        const long long Dk = pre + incl - arc;
+        __syncthreads();
+        if (tid == kPrepThreads - 1)
+            s_carry = pre + incl;
+        if (k < nn) {
+            const long long ak = (long long)out - Dk;
+            const long long bk = Dk + in;
+            const int ck = (k + 1 < nn) ? (in + outn - (int)arc) : 0;
+            st[k] = make_int2(c - 1, ck);
+            ab[k] = make_int2((int)ak, (int)bk);
+        }
+        __syncthreads();
+    }
+
+    // reduce bad flag and largest cost
+    int b = bad, mc = maxc;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        b |= __shfl_xor(b, o, kWave);
+        mc = max(mc, __shfl_xor(mc, o, kWave));
+    }
+    if (lane == 0)
+        s_redi[wid] = b ? -1 : mc;
+    __syncthreads();
+    if (tid == 0) {
+        int allbad = 0, allmax = 0;
+        for (int w = 0; w < kPrepThreads / kWave; ++w) {
+            if (s_redi[w] < 0)
+                allbad = 1;
+            else
+                allmax = max(allmax, s_redi[w]);
+        }
+        // exactness guard: 3 * n * max cost < 2^29
+        if ((long long)3 * nn * allmax >= (1LL << 29))
+            allbad = 1;
+        TourRec r;
+        r.n = nn;
+        r.f0 = nn > 0 ? ab[0].x : 0;
+        r.bn = nn > 0 ? ab[nn - 1].y : 0;
+        r.status = allbad ? ST_BAD_TOUR : ST_OK;
+        ws.rec[t] = r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// tile staging: int16 rows [rows x N] (contiguous) -> LDS bytes [rows x N]
+// returns false (uniformly) when some value is outside [0, 255]
+// ---------------------------------------------------------------------------
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ bool stage_tile_u8(const int16_t *__restrict__ src, uint8_t *lds,
+                                              int64_t elems, int lane)
+{
+    const int64_t chunks = elems >> 3; // full 8-element (16-byte) chunks
+    uint32_t bad = 0;
+    const u32x4 *src4 = reinterpret_cast<const u32x4 *>(src);
+    uint2 *dst8 = reinterpret_cast<uint2 *>(lds);
+    int64_t i = lane;
+    for (; i + 3 * kWave < chunks; i += 4 * kWave) {
+        u32x4 v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            v[r] = __builtin_nontemporal_load(&src4[i + r * kWave]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t x0 = v[r].x, x1 = v[r].y, x2 = v[r].z, x3 = v[r].w;
+            bad |= (x0 | x1 | x2 | x3) & 0xFF00FF00u;
+            uint2 o;
+            o.x = __builtin_amdgcn_perm(x1, x0, 0x06040200u);
+            o.y = __builtin_amdgcn_perm(x3, x2, 0x06040200u);
+            dst8[i + r * kWave] = o;
+        }
+    }
+    for (; i < chunks; i += kWave) {
+        const u32x4 v = __builtin_nontemporal_load(&src4[i]);
+        const uint32_t x0 = v.x, x1 = v.y, x2 = v.z, x3 = v.w;
+        bad |= (x0 | x1 | x2 | x3) & 0xFF00FF00u;
+        uint2 o;
+        o.x = __builtin_amdgcn_perm(x1, x0, 0x06040200u);
+        o.y = __builtin_amdgcn_perm(x3, x2, 0x06040200u);
+        dst8[i] = o;
+    }
+    for (int64_t e = (chunks << 3) + lane; e < elems; e += kWave) {
+        const int v = src[e];
+        bad |= (v < 0 || v > 255) ? 1u : 0u;
+        lds[e] = (uint8_t)v;
+    }
+    return ballot(bad != 0) == 0;
+}
+
+// ---------------------------------------------------------------------------
+// the per-lane recursion, ring of R potentials in registers
+//
+// One DpState<R, U>::run advances every lane of the wave by one tour
+// position j (j = R*block + U); ring slot (j - d) mod R = (U - d) mod R holds
+// predecessor p = j - d, so every slot is a compile-time register.  The
+// masked window minimum is the inline-assembly block of window_min_asm.inc:
+//   head: pair (d, d+1) is folded with one v_min3 while every active lane
+//         admits d+1 (hence d, the window being contiguous);
+//   tail: from the first pair some lane rejects, v_cmpx narrows EXEC to the
+//         lanes still admitting d and the scan ends when EXEC is empty.
+// Loads are software-pipelined: the demand of j+1 and the table entry of
+// j+2 are in flight while position j is relaxed.
+// ---------------------------------------------------------------------------
+#include "window_min_asm.inc"
+
+struct DpRegs {
+    int L;    // load of positions 1..j
+    int q;    // demand of the current position (arrived)
+    int qn;   // demand of the next position (in flight)
+    int2 tn;  // table entry of the next position {customer, c}
+    int2 tnn; // table entry of the position after next (in flight)
+    int mres; // m of the last position relaxed (m_n after the loop)
+    int ovf;  // 1 when a window reached past the ring
+};
+
+template <int R, int U> struct DpState {
+    static_assert(R == 32 || R == 64, "ring of 32 or 64 potentials");
+    __device__ __forceinline__ static bool run(int (&f)[R], int (&lq)[R], DpRegs &r,
+                                               const uint8_t *row, const int2 *tab, int j0,
+                                               int n, int Q)
+    {
+        const int j = j0 + U;
+        if (j == 0)
+            return true;
+        if (j > n)
+            return false;
+        r.q = r.qn;
+        const int cj = r.tn.y;
+        r.tn = r.tnn;
+        r.qn = row[r.tn.x];
+        r.tnn = tab[j + 2];
+        r.L += r.q;
+        int m;
+        uint64_t sv, c;
+        if constexpr (R == 32) {
+            asm volatile(SPLIT_WINDOW_ASM_R32
+                         : [m] "=&v"(m), [ov] "+v"(r.ovf), [sv] "=&s"(sv), [c] "=&s"(c)
+                         : [L] "v"(r.L), [j] "s"(j), SPLIT_WINDOW_OPERANDS_R32(f, lq, U)
+                         : "vcc", "scc");
+        } else {
+            asm volatile(SPLIT_WINDOW_ASM_R64
+                         : [m] "=&v"(m), [ov] "+v"(r.ovf), [sv] "=&s"(sv), [c] "=&s"(c)
+                         : [L] "v"(r.L), [j] "s"(j), SPLIT_WINDOW_OPERANDS_R64(f, lq, U)
+                         : "vcc", "scc");
+        }
+        r.mres = m; // the last position relaxed is j = n
+        f[U] = m + cj;
+        lq[U] = r.L + Q;
+        return true;
+    }
+};
+
+template <int R, int... Us>
+__device__ __forceinline__ bool dp_block(int (&f)[R], int (&lq)[R], DpRegs &r, const uint8_t *row,
+                                         const int2 *tab, int j0, int n, int Q,
+                                         std::integer_sequence<int, Us...>)
+{
+    return (DpState<R, Us>::run(f, lq, r, row, tab, j0, n, Q) && ...);
+}
+
+// tab[j] = {customer index of position j, c_j} for j = 1..n (tab[0] unused,
+// two padding entries after n); returns m_n.
+template <int R>
+__device__ __forceinline__ int dp_lane(const uint8_t *row, const int2 *tab, int n, int f0, int Q,
+                                       bool &ovf)
+{
+    int f[R], lq[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        f[i] = kInf;
+        lq[i] = kNeg;
+    }
+    f[0] = f0; // p = 0: V(0) + a_1
+    lq[0] = Q; // L_0 + Q
+    DpRegs r;
+    r.L = 0;
+    r.mres = kInf;
+    r.ovf = 0;
+    r.tn = tab[1];
+    r.qn = row[r.tn.x];
+    r.tnn = tab[2];
+    for (int j0 = 0; j0 <= n; j0 += R) {
+        if (!dp_block<R>(f, lq, r, row, tab, j0, n, Q, std::make_integer_sequence<int, R>{}))
+            break;
+    }
+    ovf = r.ovf != 0;
+    return r.mres;
+}
+
+// ---------------------------------------------------------------------------
+// main evaluation kernel: one wave per (tile, tour) unit
+// unit u -> tile k = u / T, tour t = u % T  (all tours of a tile run close
+// together in time, so a shared demand tile is read from HBM once per XCD)
+//
+// LDS: [64 x N demand bytes, 16-aligned][table: (max_len + 3) int2]
+// ---------------------------------------------------------------------------
+template <int R>
+__global__ __launch_bounds__(kWave) void split_tile_kernel(const int16_t *__restrict__ demands,
+                                                           int32_t N, int64_t S, int32_t Q,
+                                                           int32_t T, int32_t *__restrict__ costs,
+                                                           Workspace ws, int32_t use_lds)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    const int64_t u = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t k = u / T;
+    const int t = (int)(u - k * T);
+    const int64_t s0 = k * kWave;
+    const int rows = (int)min<int64_t>(kWave, S - s0);
+    const TourRec rec = ws.rec[t];
+    int32_t *out = costs + (int64_t)t * S + s0;
+
+    if (rec.status != ST_OK) {
+        if (lane < rows)
+            out[lane] = SPLIT_INF;
+        if (lane == 0) {
+            ws.tile_sum[u] = 0;
+            ws.tile_inf[u] = 0;
+        }
+        return;
+    }
+    if (rec.n == 0) {
+        if (lane < rows)
+            out[lane] = 0;
+        if (lane == 0) {
+            ws.tile_sum[u] = 0;
+            ws.tile_inf[u] = 0;
+        }
+        return;
+    }
+
+    bool redo = true;
+    if (use_lds) {
+        const int n = rec.n;
+        const size_t rows_bytes = ((size_t)kWave * N + 15) & ~(size_t)15;
+        int2 *tab = reinterpret_cast<int2 *>(lds + rows_bytes);
+        const int2 *st = ws.st + (int64_t)t * ws.max_len;
+        for (int i = lane; i < n + 3; i += kWave) {
+            int2 e = make_int2(0, 0);
+            if (i >= 1 && i <= n)
+                e = st[i - 1];
+            tab[i] = e;
+        }
+        const bool ok = stage_tile_u8(demands + s0 * N, lds, (int64_t)rows * N, lane);
+        __syncthreads();
+        if (ok) {
+            bool ovf = false;
+            int v = 0;
+            if (lane < rows) {
+                const int m = dp_lane<R>(lds + (int64_t)lane * N, tab, n, rec.f0, Q, ovf);
+                v = m + rec.bn;
+            }
+            redo = ballot(ovf) != 0;
+            if (!redo) {
+                const bool fin = lane < rows && v < kInf;
+                const bool inf = lane < rows && v >= kInf;
+                if (lane < rows)
+                    out[lane] = inf ? SPLIT_INF : v;
+                const long long s = wave_sum_i64(fin ? (long long)v : 0LL);
+                const int ni = wave_sum_i32(inf ? 1 : 0);
+                if (lane == 0) {
+                    ws.tile_sum[u] = s;
+                    ws.tile_inf[u] = ni;
+                }
+            }
+        }
+    }
+    if (redo && lane == 0) {
+        const int slot = atomicAdd(ws.list_count, 1);
+        ws.list[slot] = (int)u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// exact fallback: listed units, straight from the definition
+// (any window length, any demand value), V history in global scratch
+// ---------------------------------------------------------------------------
+constexpr int kFallbackBlocks = 64;
+
+__global__ __launch_bounds__(kWave) void split_fallback_kernel(const int16_t *__restrict__ demands,
+                                                               int32_t N, int64_t S, int32_t Q,
+                                                               int32_t T,
+                                                               int32_t *__restrict__ costs,
+                                                               Workspace ws)
+{
+    const int lane = threadIdx.x;
+    const int count = *ws.list_count;
+    int *V = ws.vscratch + (int64_t)blockIdx.x * kWave * (ws.max_len + 1);
+    for (int li = blockIdx.x; li < count; li += gridDim.x) {
+        const int64_t u = ws.list[li];
+        const int64_t k = u / T;
+        const int t = (int)(u - k * T);
+        const int64_t s0 = k * kWave;
+        const int rows = (int)min<int64_t>(kWave, S - s0);
+        const TourRec rec = ws.rec[t];
+        const int2 *st = ws.st + (int64_t)t * ws.max_len;
+        const int2 *ab = ws.ab + (int64_t)t * ws.max_len;
+        const int n = rec.n;
+        int v = 0;
+        bool negq = false;
+        if (lane < rows) {
+            const int16_t *qrow = demands + (s0 + lane) * N;
+            V[lane] = 0; // V(0), laid out [j][lane]
+            for (int j = 1; j <= n; ++j) {
+                const int bj = ab[j - 1].y;
+                int best = kInf;
+                int load = 0;
+                for (int p = j - 1; p >= 0; --p) {
+                    const int q = qrow[st[p].x];
+                    negq = negq || q < 0;
+                    load += q;
+                    if (load > Q)
+                        break;
+                    const int vp = V[(int64_t)p * kWave + lane];
+                    if (vp < kInf)
+                        best = min(best, vp + ab[p].x + bj);
+                }
+                V[(int64_t)j * kWave + lane] = best;
+            }
+            v = V[(int64_t)n * kWave + lane];
+        }
+        if (ballot(negq) != 0) {
+            if (lane == 0)
+                atomicOr(&ws.rec[t].status, ST_BAD_DEMAND);
+        }
+        const bool fin = lane < rows && v < kInf;
+        const bool inf = lane < rows && v >= kInf;
+        if (lane < rows)
+            costs[(int64_t)t * S + s0 + lane] = inf ? SPLIT_INF : v;
+        const long long s = wave_sum_i64(fin ? (long long)v : 0LL);
+        const int ni = wave_sum_i32(inf ? 1 : 0);
+        if (lane == 0) {
+            ws.tile_sum[u] = s;
+            ws.tile_inf[u] = ni;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// finalize: per-tour exact sum over tiles, mean = sum / S
+// ---------------------------------------------------------------------------
+constexpr int kFinThreads = 256;
+
+__global__ __launch_bounds__(kFinThreads) void finalize_kernel(int64_t S, int32_t T,
+                                                               int64_t tiles, int32_t *costs,
+                                                               int64_t *sums, double *means,
+                                                               Workspace ws)
+{
+    __shared__ long long s_sum[kFinThreads / kWave];
+    __shared__ int s_inf[kFinThreads / kWave];
+    const int t = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    long long s = 0;
+    int ni = 0;
+    for (int64_t k = tid; k < tiles; k += kFinThreads) {
+        s += ws.tile_sum[k * T + t];
+        ni += ws.tile_inf[k * T + t];
+    }
+    s = wave_sum_i64(s);
+    ni = wave_sum_i32(ni);
+    if (lane == 0) {
+        s_sum[wid] = s;
+        s_inf[wid] = ni;
+    }
+    __syncthreads();
+    const int status = ws.rec[t].status;
+    if (status != ST_OK) {
+        // invalid inputs: every cost SPLIT_INF, the sum marks the error
+        for (int64_t i = tid; i < S; i += kFinThreads)
+            costs[(int64_t)t * S + i] = SPLIT_INF;
+    }
+    if (tid == 0) {
+        long long tot = 0;
+        int totinf = 0;
+        for (int w = 0; w < kFinThreads / kWave; ++w) {
+            tot += s_sum[w];
+            totinf += s_inf[w];
+        }
+        if (status != ST_OK) {
+            sums[t] = SPLIT_SUM_INVALID;
+            means[t] = __builtin_nan("");
+        } else if (totinf) {
+            sums[t] = INT64_MAX;
+            means[t] = __builtin_inf();
+        } else {
+            sums[t] = tot;
+            means[t] = (double)tot / (double)S;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Bellman-cell counter: per lane, two running loads bracket the window
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWave) void count_cells_kernel(const int32_t *__restrict__ tours,
+                                                            const int32_t *__restrict__ lens,
+                                                            int32_t T, int32_t N,
+                                                            const int16_t *__restrict__ demands,
+                                                            int64_t S, int32_t Q,
+                                                            unsigned long long *__restrict__ cells)
+{
+    const int lane = threadIdx.x;
+    const int64_t u = blockIdx.x;
+    const int64_t k = u / T;
+    const int t = (int)(u - k * T);
+    const int64_t s = k * kWave + lane;
+    long long off = 0;
+    for (int i = 0; i < t; ++i)
+        off += lens[i];
+    const int n = lens[t];
+    const int32_t *tour = tours + off;
+    long long cnt = 0;
+    if (s < S) {
+        const int16_t *qrow = demands + s * N;
+        int L = 0, Ll = 0, l = 0; // window [l, j-1]; Ll = load of positions 1..l
+        auto q_at = [&](int pos) { // demand of tour position pos (ids clamped into range)
+            const int c = min(max(tour[pos - 1], 1), N);
+            return (int)qrow[c - 1];
+        };
+        for (int j = 1; j <= n; ++j) {
+            L += q_at(j);
+            while (l < j && L - Ll > Q) {
+                ++l;
+                Ll += q_at(l);
+            }
+            cnt += j - l;
+        }
+    }
+    cnt = wave_sum_i64(cnt);
+    if (lane == 0)
+        atomicAdd(&cells[t], (unsigned long long)cnt);
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------
+__global__ void zero_i64_kernel(int64_t *p, int32_t n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = 0;
+}
+
+int64_t num_tiles(int64_t S) { return (S + kTile - 1) / kTile; }
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t workspace_bytes(int32_t T, int32_t max_len, int64_t S)
+{
+    const size_t units = (size_t)T * (size_t)num_tiles(S);
+    size_t b = 0;
+    b += align256((size_t)T * max_len * sizeof(int2));
+    b += align256((size_t)T * max_len * sizeof(int2));
+    b += align256((size_t)T * sizeof(TourRec));
+    b += align256(units * sizeof(long long));
+    b += align256(units * sizeof(int));
+    b += align256(units * sizeof(int));
+    b += align256(sizeof(int));
+    b += align256((size_t)kFallbackBlocks * kWave * ((size_t)max_len + 1) * sizeof(int));
+    return b;
+}
+
+Workspace carve_workspace(void *base, int32_t T, int32_t max_len, int64_t S)
+{
+    const size_t units = (size_t)T * (size_t)num_tiles(S);
+    char *p = static_cast<char *>(base);
+    Workspace ws;
+    ws.st = reinterpret_cast<int2 *>(p);
+    p += align256((size_t)T * max_len * sizeof(int2));
+    ws.ab = reinterpret_cast<int2 *>(p);
+    p += align256((size_t)T * max_len * sizeof(int2));
+    ws.rec = reinterpret_cast<TourRec *>(p);
+    p += align256((size_t)T * sizeof(TourRec));
+    ws.tile_sum = reinterpret_cast<long long *>(p);
+    p += align256(units * sizeof(long long));
+    ws.tile_inf = reinterpret_cast<int *>(p);
+    p += align256(units * sizeof(int));
+    ws.list = reinterpret_cast<int *>(p);
+    p += align256(units * sizeof(int));
+    ws.list_count = reinterpret_cast<int *>(p);
+    p += align256(sizeof(int));
+    ws.vscratch = reinterpret_cast<int *>(p);
+    ws.max_len = max_len;
+    return ws;
+}
+
+Schedule default_schedule(int32_t N, int64_t S, int32_t Q)
+{
+    (void)N;
+    (void)S;
+    Schedule s;
+    s.ring = Q > 200 ? 64 : 32;
+    return s;
+}
+
+template <int R>
+static hipError_t launch_tiles(const int16_t *demands, int32_t N, int64_t S, int32_t Q, int32_t T,
+                               int32_t *costs, const Workspace &ws, hipStream_t stream)
+{
+    const int64_t units = (int64_t)T * num_tiles(S);
+    const size_t lds = (((size_t)kTile * (size_t)N + 15) & ~(size_t)15) +
+                       ((size_t)ws.max_len + 3) * sizeof(int2);
+    static int lds_limit = -1;
+    if (lds_limit < 0) {
+        int dev = 0, lim = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess)
+            e = hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (e != hipSuccess)
+            return e;
+        lim = lim < kLdsLimit ? lim : kLdsLimit;
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&split_tile_kernel<R>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        if (e != hipSuccess)
+            return e;
+        lds_limit = lim;
+    }
+    const int use_lds = lds <= (size_t)lds_limit ? 1 : 0;
+    const size_t lds_bytes = use_lds ? lds : 0;
+    hipLaunchKernelGGL(split_tile_kernel<R>, dim3((unsigned)units), dim3(kWave), lds_bytes, stream,
+                       demands, N, S, Q, T, costs, ws, use_lds);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval(const int32_t *tours, const int32_t *lens, int32_t T, int32_t max_len,
+                       const int32_t *dist, int32_t N, const int16_t *demands, int64_t S,
+                       int32_t Q, int32_t *costs, int64_t *sums, double *means,
+                       const Workspace &ws, hipStream_t stream, const Schedule &sched)
+{
+    hipLaunchKernelGGL(prep_kernel, dim3(T), dim3(kPrepThreads), 0, stream, tours, lens, T,
+                       max_len, dist, N, ws);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    if (sched.ring == 64)
+        e = launch_tiles<64>(demands, N, S, Q, T, costs, ws, stream);
+    else
+        e = launch_tiles<32>(demands, N, S, Q, T, costs, ws, stream);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(split_fallback_kernel, dim3(kFallbackBlocks), dim3(kWave), 0, stream,
+                       demands, N, S, Q, T, costs, ws);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(finalize_kernel, dim3(T), dim3(kFinThreads), 0, stream, S, T, num_tiles(S),
+                       costs, sums, means, ws);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_cells(const int32_t *tours, const int32_t *lens, int32_t T, int32_t N,
+                              const int16_t *demands, int64_t S, int32_t Q, int64_t *cells,
+                              hipStream_t stream)
+{
+    hipLaunchKernelGGL(zero_i64_kernel, dim3((T + 255) / 256), dim3(256), 0, stream, cells, T);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    const int64_t units = (int64_t)T * num_tiles(S);
+    hipLaunchKernelGGL(count_cells_kernel, dim3((unsigned)units), dim3(kWave), 0, stream, tours,
+                       lens, T, N, demands, S, Q, reinterpret_cast<unsigned long long *>(cells));
+    return hipGetLastError();
+}
+
+} // namespace splitk

@@ -1,0 +1,97 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol
+the public header declares, and rejects host-checkable bad arguments before
+touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2602_05179_amd import binding
+from paper_2602_05179_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"\b(split_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_expected_entry_points():
+    decl = _declared_functions()
+    assert "split_eval" in decl and "split_eval_device" in decl
+    assert set(decl) == set(binding.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(binding.LIB_PATH)
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_workspace_size_is_positive_and_monotone():
+    a = binding.workspace_bytes(1, 200, 200, 1_000_000)
+    b = binding.workspace_bytes(2, 200, 200, 1_000_000)
+    c = binding.workspace_bytes(1, 400, 200, 1_000_000)
+    assert 0 < a < b and a < c
+    assert binding.workspace_bytes(0, 10, 10, 10) == 0
+
+
+def _small():
+    inst = W.plain_small(1, S=64)
+    return W.as_arrays(inst) + (inst.Q,)
+
+
+@pytest.mark.parametrize("mutate, msg", [
+    (lambda a: a.update(Q=-1), "Q must be"),
+    (lambda a: a["tours"].__setitem__(0, 0), "outside [1"),
+    (lambda a: a["tours"].__setitem__(3, 99), "outside [1"),
+    (lambda a: a["dist"].__setitem__((0, a["tours"][0]), -5), "travel cost"),
+    (lambda a: a["dist"].__setitem__((a["tours"][2], a["tours"][3]), 1 << 25), "travel cost"),
+])
+def test_host_form_rejects_bad_arguments_before_device_work(mutate, msg):
+    tours, lens, dist, dem, Q = _small()
+    args = dict(tours=tours.copy(), lens=lens, dist=dist.copy(), demands=dem, Q=Q)
+    mutate(args)
+    with pytest.raises(binding.SplitError) as e:
+        binding.split_eval(**args)
+    assert e.value.code == binding.SPLIT_EINVAL
+    assert msg in str(e.value)
+
+
+def test_exactness_guard_is_enforced():
+    tours, lens, dist, dem, Q = _small()
+    big = dist.copy()
+    big[big > 0] = 1 << 24  # 3 * 20 * 2^24 >= 2^29
+    with pytest.raises(binding.SplitError) as e:
+        binding.split_eval(tours, lens, big, dem, Q)
+    assert e.value.code == binding.SPLIT_EINVAL and "guard" in str(e.value)
+
+
+def test_device_form_rejects_bad_scalars_before_device_work():
+    P = ctypes.c_void_p
+    fake = P(256)
+    for T, N, S, Q, maxlen in ((0, 5, 10, 3, 5), (1, 0, 10, 3, 5), (1, 5, 0, 3, 5), (1, 5, 10, -2, 5),
+                               (1, 5, 10, 3, 70000)):
+        rc = binding.lib.split_eval_device(fake, fake, T, maxlen, fake, N, fake, S, Q, fake, fake, fake, fake,
+                                           1 << 20, None)
+        assert rc == binding.SPLIT_EINVAL, (T, N, S, Q, maxlen)
+    # misaligned demands and too-small workspace
+    rc = binding.lib.split_eval_device(fake, fake, 1, 5, fake, 5, P(258), 10, 3, fake, fake, fake, fake, 1 << 20,
+                                       None)
+    assert rc == binding.SPLIT_EINVAL and "aligned" in binding.last_error()
+    rc = binding.lib.split_eval_device(fake, fake, 1, 5, fake, 5, fake, 10, 3, fake, fake, fake, fake, 16, None)
+    assert rc == binding.SPLIT_EINVAL and "workspace" in binding.last_error()
+
+
+def test_shape_mismatch_is_rejected_in_the_binding():
+    tours, lens, dist, dem, Q = _small()
+    with pytest.raises(binding.SplitError):
+        binding.split_eval(tours, lens, dist, np.zeros((4, 3), np.int16), Q)
