@@ -1,0 +1,257 @@
+#!/usr/bin/env python
+"""Benchmark of the scenario-batched split evaluator on one MI355X.
+
+Headline (one JSON line on stdout): Bellman cells/s of the plain split at
+the paper's scale -- one giant tour of n=200 customers, S=10^6 demand
+scenarios, Q=150 -- with all inputs resident in HBM before timing starts.
+A step is one full evaluation (per-tour constants, the window recursion for
+every scenario, exact fallback, per-tour sum and mean).
+
+Also reported on the same line: scenarios/s, the main kernel's roofline
+(int32 VALU ops, one per Bellman cell, against the chip's VALU peak), the
+CPU oracle's throughput on a bounded sample of the same workload, and the
+batched form (256 ragged tours in one captured graph vs one launch per
+tour).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Bellman cells/s & scenarios/s at n=200,S=1e6; batched vs plain; p99 latency"
+# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz plain 32-bit VALU lane-ops/s
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_2602_05179_amd/csrc/split_kernels.hip",
+                  "paper_2602_05179_amd/csrc/window_min_asm.inc",
+                  "paper_2602_05179_amd/csrc/split_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_split_tile_n200_S1e6.txt")
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha1()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:12]
+
+
+def read_traffic():
+    """HBM bytes per launch of the main kernel from the committed rocprofv3
+    counter summary, or None if absent or taken on a different kernel."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_hash") != kernel_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def timed_steps(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def cpu_baseline(inst):
+    """The oracle (as it stands) on a bounded sample of the same workload."""
+    import oracle
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    S_all = min(inst.S, 400_000)
+    dem = inst.demands[:S_all]
+    t0 = time.perf_counter()
+    r = oracle.split_eval(inst.tours, inst.lens, inst.dist, dem, inst.Q, nthreads=cores)
+    t_all = time.perf_counter() - t0
+    S_one = min(inst.S, 50_000)
+    t0 = time.perf_counter()
+    r1 = oracle.split_eval(inst.tours, inst.lens, inst.dist, inst.demands[:S_one], inst.Q, nthreads=1)
+    t_one = time.perf_counter() - t0
+    return {
+        "value": float(r["cells"].sum()) / t_all,
+        "unit": "cells/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": "first %d of the %d scenarios on %d threads (%.2f s wall); scenarios/s %.4g; "
+                  "1 thread: first %d scenarios, %.4g cells/s" % (
+                      S_all, inst.S, cores, t_all, S_all / t_all, S_one, float(r1["cells"].sum()) / t_one),
+        "cells_per_scenario_sample": float(r["cells"].sum()) / S_all,
+    }
+
+
+def batched_vs_plain(torch, binding, W, reps):
+    """256 ragged tours on 10^4 shared scenarios: one graph vs one launch per tour."""
+    inst = W.batched_ragged(4)
+    tours, lens, dist, dem = W.as_arrays(inst)
+    dev = torch.device("cuda:0")
+    t = torch.from_numpy(tours).to(dev)
+    l = torch.from_numpy(lens).to(dev)
+    d = torch.from_numpy(dist).to(dev)
+    q = torch.from_numpy(dem).to(dev)
+    T, max_len = inst.num_tours, int(lens.max())
+    cells = int(binding.split_count_cells_device(t, l, q, inst.N, inst.Q).sum().item())
+    plan = binding.Plan(t, l, d, q, inst.Q, max_len=max_len)
+    t_graph = timed_steps(torch, plan.launch, reps, 2)
+    ws = torch.empty(binding.workspace_bytes(T, max_len, inst.N, inst.S), dtype=torch.uint8, device=dev)
+    out = binding.DeviceOutputs(T, inst.S, dev)
+    t_eager = timed_steps(torch, lambda: binding.split_eval_device(t, l, d, q, inst.Q, max_len=max_len, out=out,
+                                                                   workspace=ws), reps, 2)
+    offs = [0]
+    for n in lens:
+        offs.append(offs[-1] + int(n))
+    singles = []
+    for k in range(T):
+        n = int(lens[k])
+        singles.append((t[offs[k]:offs[k] + n], l[k:k + 1], binding.DeviceOutputs(1, inst.S, dev),
+                        torch.empty(binding.workspace_bytes(1, max(n, 1), inst.N, inst.S), dtype=torch.uint8,
+                                    device=dev), max(n, 1)))
+
+    def plain():
+        for tt, ll, oo, ww, ml in singles:
+            binding.split_eval_device(tt, ll, d, q, inst.Q, max_len=ml, out=oo, workspace=ww)
+
+    t_plain = timed_steps(torch, plain, max(1, reps // 4), 1)
+    same = all(torch.equal(singles[k][2].costs[0], plan.out.costs[k]) for k in range(0, T, 17))
+    plan.close()
+    return {
+        "workload": inst.name,
+        "cells": cells,
+        "batched_graph_ms": t_graph * 1e3,
+        "batched_graph_cells_per_s": cells / t_graph,
+        "batched_eager_ms": t_eager * 1e3,
+        "plain_per_tour_ms": t_plain * 1e3,
+        "plain_per_tour_cells_per_s": cells / t_plain,
+        "speedup_batched_vs_plain": t_plain / t_graph,
+        "batched_equals_plain": bool(same),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--scenarios", type=int, default=1_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="also run a plain device copy of the demand tensor (HBM counter scale)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build evaluates on one GPU; --gpus %d is not supported (use --gpus 1)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2602_05179_amd import binding
+    from paper_2602_05179_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    log("generating n=200 S=%d Q=150 (seed %d)" % (args.scenarios, args.seed))
+    inst = W.plain_paper_scale(args.seed, S=args.scenarios)
+    tours, lens, dist, dem = W.as_arrays(inst)
+    t = torch.from_numpy(tours).to(dev)
+    l = torch.from_numpy(lens).to(dev)
+    d = torch.from_numpy(dist).to(dev)
+    q = torch.from_numpy(dem).to(dev)
+    T, N, S, n = inst.num_tours, inst.N, inst.S, int(lens.max())
+    ws = torch.empty(binding.workspace_bytes(T, n, N, S), dtype=torch.uint8, device=dev)
+    out = binding.DeviceOutputs(T, S, dev)
+    cells = int(binding.split_count_cells_device(t, l, q, N, inst.Q).sum().item())
+    torch.cuda.synchronize()
+    log("inputs resident (%.1f MB demands); %d Bellman cells per step" % (dem.nbytes / 1e6, cells))
+
+    def step():
+        binding.split_eval_device(t, l, d, q, inst.Q, max_len=n, out=out, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    binding.profile_read()
+    binding.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    kms, launches = binding.profile_read()
+    binding.profile_enable(False)
+    kernel_s = kms / 1e3 / max(launches, 1)
+    log("timed %d steps: %.3f ms/step, main kernel %.3f ms" % (args.steps, sec * 1e3, kernel_s * 1e3))
+
+    if args.calibration_copy:
+        for _ in range(3):
+            q.clone()
+        torch.cuda.synchronize()
+        log("calibration copies: 3 x %d bytes read + written" % dem.nbytes)
+
+    alg_bytes = dem.nbytes + S * 4
+    achieved = cells / kernel_s / 1e12
+    traffic = read_traffic()
+    result = {
+        "metric": METRIC,
+        "value": cells / sec,
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "plain split, 1 giant tour n=200, S=%d scenarios, Q=150, demands "
+                               "round(Normal(mu,0.3mu))>=1 int16 scenario-major, int32 rounded Euclidean costs" % S,
+                   "n": n, "S": S, "Q": inst.Q, "seed": args.seed, "cells_per_step": cells},
+        "scenarios_per_s": S / sec,
+        "roofline": {
+            "bound": "alu",
+            "kernel": "split_tile_kernel",
+            "achieved": achieved,
+            "peak": VALU_PEAK_TOPS,
+            "unit": "TOP/s",
+            "frac": achieved / VALU_PEAK_TOPS,
+            "traffic": traffic,
+            "algorithmic_bytes": alg_bytes,
+            "achieved_gbs": alg_bytes / kernel_s / 1e9,
+            "hbm_frac": alg_bytes / kernel_s / 1e9 / HBM_PEAK_GBS,
+            "kernel_ms": kernel_s * 1e3,
+            "kernel_hash": kernel_hash(),
+        },
+    }
+    if not args.no_batched:
+        log("batched vs plain (256 ragged tours, S=10^4)")
+        result["batched"] = batched_vs_plain(torch, binding, W, reps=20)
+    if not args.no_cpu_baseline:
+        log("CPU oracle baseline on a bounded sample")
+        result["cpu_baseline"] = cpu_baseline(inst)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -128,13 +128,27 @@ int split_count_cells_device(const int32_t *d_tours, const int32_t *d_lens, int3
                              int64_t *d_cells, split_stream_t stream);
 
 /*
- * split_set_ring -- schedule override for every later call in the process:
- * ring = 32 or 64 forces the register-ring length of the main kernel
- * (windows longer than the ring are recomputed by the exact fallback, so
- * results never depend on it), 0 restores the automatic choice.  Returns
- * SPLIT_EINVAL for other values.  Not thread-safe against concurrent calls.
+ * split_set_schedule -- schedule override for every later call in the
+ * process (the tuner uses it).  ring = 32 or 64 is the register-ring length
+ * of the main kernel (longer windows are recomputed by the exact fallback,
+ * so results never depend on it); first = cells of the first head group
+ * validated with a single check (0 = pairs only); every = tail cells
+ * between exits on an empty lane mask.  ring = 0 restores the automatic
+ * choice.  Unsupported triples return SPLIT_EINVAL.  Not thread-safe
+ * against concurrent evaluations.
  */
-int split_set_ring(int32_t ring);
+int split_set_schedule(int32_t ring, int32_t first, int32_t every);
+
+/*
+ * Measurement.  While enabled, every launch of the main evaluation kernel
+ * is bracketed by a pair of HIP events recorded on the launch stream.
+ * split_profile_read waits for the recorded events, returns the summed
+ * elapsed milliseconds and the number of launches since the previous read,
+ * and resets both.  Disabled by default; do not enable it for calls that
+ * are being captured into a graph.
+ */
+int split_profile_enable(int32_t on);
+int split_profile_read(double *kernel_ms, int64_t *launches);
 
 /*
  * Plans: the batched form.  A plan binds one set of device buffers and

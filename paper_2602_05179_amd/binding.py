@@ -31,7 +31,9 @@ EXPORTED = (
     "split_plan_create",
     "split_plan_launch",
     "split_plan_destroy",
-    "split_set_ring",
+    "split_set_schedule",
+    "split_profile_enable",
+    "split_profile_read",
 )
 
 
@@ -68,8 +70,12 @@ def _load():
     lib.split_plan_launch.argtypes = [P, P]
     lib.split_plan_destroy.restype = ctypes.c_int
     lib.split_plan_destroy.argtypes = [P]
-    lib.split_set_ring.restype = ctypes.c_int
-    lib.split_set_ring.argtypes = [i32]
+    lib.split_set_schedule.restype = ctypes.c_int
+    lib.split_set_schedule.argtypes = [i32, i32, i32]
+    lib.split_profile_enable.restype = ctypes.c_int
+    lib.split_profile_enable.argtypes = [i32]
+    lib.split_profile_read.restype = ctypes.c_int
+    lib.split_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     return lib
 
 
@@ -85,9 +91,24 @@ def _check(rc: int):
         raise SplitError(rc, last_error())
 
 
-def set_ring(ring: int):
-    """Force the register-ring length (32 or 64); 0 = automatic."""
-    _check(lib.split_set_ring(int(ring)))
+SCHEDULES = [(r, f, e) for r in (32, 64) for f, e in ((0, 1), (8, 2), (6, 2), (8, 3), (4, 2))]
+
+
+def set_schedule(ring: int, first: int = 8, every: int = 2):
+    """Force the main-kernel schedule; ring=0 restores the automatic choice."""
+    _check(lib.split_set_schedule(int(ring), int(first), int(every)))
+
+
+def profile_enable(on: bool = True):
+    """Bracket every main-kernel launch with HIP events (measurement)."""
+    _check(lib.split_profile_enable(1 if on else 0))
+
+
+def profile_read():
+    """(summed main-kernel milliseconds, launches) since the last read."""
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(lib.split_profile_read(ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
 
 
 def _np_ptr(a):

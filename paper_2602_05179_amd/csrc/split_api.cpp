@@ -120,14 +120,43 @@ struct HostCtx {
 
 HostCtx g_ctx;
 
-int g_ring_override = 0; // 0 = automatic
+splitk::Schedule g_override = {0, 0, 0}; // ring 0 = automatic
 
 splitk::Schedule pick_schedule(int32_t N, int64_t S, int32_t Q)
 {
-    splitk::Schedule s = splitk::default_schedule(N, S, Q);
-    if (g_ring_override)
-        s.ring = g_ring_override;
-    return s;
+    return g_override.ring ? g_override : splitk::default_schedule(N, S, Q);
+}
+
+// Event pairs around main-kernel launches while profiling is enabled.
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    std::vector<splitk::LaunchEvents> pending, spare;
+};
+
+Profiler g_prof;
+
+// Returns events to bracket the next launch (or nullptr when disabled).
+hipError_t profile_events(splitk::LaunchEvents *out, bool *use)
+{
+    std::lock_guard<std::mutex> lock(g_prof.mu);
+    *use = g_prof.on;
+    if (!g_prof.on)
+        return hipSuccess;
+    splitk::LaunchEvents ev;
+    if (!g_prof.spare.empty()) {
+        ev = g_prof.spare.back();
+        g_prof.spare.pop_back();
+    } else {
+        hipError_t e = hipEventCreate(&ev.before);
+        if (e == hipSuccess)
+            e = hipEventCreate(&ev.after);
+        if (e != hipSuccess)
+            return e;
+    }
+    g_prof.pending.push_back(ev);
+    *out = ev;
+    return hipSuccess;
 }
 
 hipError_t ensure(HostCtx::Buf &b, size_t bytes)
@@ -155,12 +184,18 @@ extern "C" {
 
 const char *split_last_error(void) { return g_err; }
 
-int split_set_ring(int32_t ring)
+int split_set_schedule(int32_t ring, int32_t first, int32_t every)
 {
     g_err[0] = 0;
-    if (ring != 0 && ring != 32 && ring != 64)
-        return fail(SPLIT_EINVAL, "ring must be 0, 32 or 64 (got %d)", ring);
-    g_ring_override = ring;
+    if (ring == 0) {
+        g_override = splitk::Schedule{0, 0, 0};
+        return SPLIT_OK;
+    }
+    const splitk::Schedule s{ring, first, every};
+    if (!splitk::schedule_supported(s))
+        return fail(SPLIT_EINVAL, "unsupported schedule ring=%d first=%d every=%d", ring, first,
+                    every);
+    g_override = s;
     return SPLIT_OK;
 }
 
@@ -194,10 +229,43 @@ int split_eval_device(const int32_t *d_tours, const int32_t *d_lens, int32_t num
         return fail(SPLIT_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
     const splitk::Workspace ws = splitk::carve_workspace(d_workspace, num_tours, max_len, S);
     const splitk::Schedule sched = pick_schedule(N, S, Q);
+    splitk::LaunchEvents ev;
+    bool use_ev = false;
+    HIP_TRY(profile_events(&ev, &use_ev), "profile events");
     HIP_TRY(splitk::launch_eval(d_tours, d_lens, num_tours, max_len, d_dist, N, d_demands, S, Q,
                                 d_costs, d_sums, d_means, ws, static_cast<hipStream_t>(stream),
-                                sched),
+                                sched, use_ev ? &ev : nullptr),
             "launch");
+    return SPLIT_OK;
+}
+
+int split_profile_enable(int32_t on)
+{
+    g_err[0] = 0;
+    std::lock_guard<std::mutex> lock(g_prof.mu);
+    g_prof.on = on != 0;
+    return SPLIT_OK;
+}
+
+int split_profile_read(double *kernel_ms, int64_t *launches)
+{
+    g_err[0] = 0;
+    if (!kernel_ms || !launches)
+        return fail(SPLIT_EINVAL, "null pointer argument");
+    std::lock_guard<std::mutex> lock(g_prof.mu);
+    double total = 0.0;
+    int64_t count = 0;
+    for (const splitk::LaunchEvents &ev : g_prof.pending) {
+        HIP_TRY(hipEventSynchronize(ev.after), "event synchronize");
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ev.before, ev.after), "event elapsed");
+        total += ms;
+        ++count;
+        g_prof.spare.push_back(ev);
+    }
+    g_prof.pending.clear();
+    *kernel_ms = total;
+    *launches = count;
     return SPLIT_OK;
 }
 

@@ -18,23 +18,33 @@ struct TourRec {
 
 // Device scratch carved from one caller- or library-owned allocation.
 struct Workspace {
-    int2 *st;              // [T * max_len] {customer index, c_j}
+    int2 *tab;             // [T * (max_len + 3)] {customer index, c_j}, padded
     int2 *ab;              // [T * max_len] {a_j, b_j} (exact fallback)
     TourRec *rec;          // [T]
-    long long *tile_sum;   // [units] exact sum of finite costs of a unit
-    int *tile_inf;         // [units] number of SPLIT_INF costs of a unit
+    long long *slots;      // [T * kSlots * kSlotStride] per-tour partial {sum, #inf}
     int *list;             // [units] units handed to the exact fallback
     int *list_count;       // [1]
+    int *done;             // [1] fallback blocks finished
     int *vscratch;         // [fallback blocks * 64 * (max_len + 1)] value history
     int max_len;
 };
 
-// How the main kernel runs.
+// How the main kernel runs (one instantiation per supported triple).
 struct Schedule {
-    int ring; // register ring length R (32 or 64)
+    int ring;  // register ring length R (32 or 64)
+    int first; // cells of the first head group, validated once (0 = pairs)
+    int every; // tail cells between exits on an empty EXEC
+};
+
+// Optional events bracketing the main kernel launch (measurement only).
+struct LaunchEvents {
+    hipEvent_t before = nullptr;
+    hipEvent_t after = nullptr;
 };
 
 constexpr int kTile = 64;            // scenarios per unit (one wave)
+constexpr int kSlots = 64;           // partial-sum slots per tour
+constexpr int kSlotStride = 16;      // int64 words between slots (128 bytes)
 constexpr int kMaxLen = 65535;       // longest tour the library accepts
 constexpr int kLdsLimit = 160 * 1024; // LDS bytes one workgroup may use on gfx950
 
@@ -45,12 +55,14 @@ Workspace carve_workspace(void *base, int32_t T, int32_t max_len, int64_t S);
 hipError_t launch_eval(const int32_t *tours, const int32_t *lens, int32_t T, int32_t max_len,
                        const int32_t *dist, int32_t N, const int16_t *demands, int64_t S,
                        int32_t Q, int32_t *costs, int64_t *sums, double *means,
-                       const Workspace &ws, hipStream_t stream, const Schedule &sched);
+                       const Workspace &ws, hipStream_t stream, const Schedule &sched,
+                       const LaunchEvents *ev = nullptr);
 
 hipError_t launch_count_cells(const int32_t *tours, const int32_t *lens, int32_t T, int32_t N,
                               const int16_t *demands, int64_t S, int32_t Q, int64_t *cells,
                               hipStream_t stream);
 
 Schedule default_schedule(int32_t N, int64_t S, int32_t Q);
+bool schedule_supported(const Schedule &s);
 
 } // namespace splitk

@@ -21,14 +21,12 @@
 // tile's demand rows (int16, scenario-major, contiguous in HBM) are streamed
 // into LDS with 16-byte coalesced loads and narrowed to bytes when every
 // value of the tile fits (the common case); each lane then gathers its
-// demands through the tour from its own LDS row.  The last R potentials
-// f_p and thresholds L_p + Q of a lane live in registers; the j loop is
-// unrolled R times so every ring slot is a compile-time register.  The
-// masked window minimum runs in two regimes:
-//   head: while every lane of the wave admits predecessor d+1 (one compare,
-//         one ballot), two potentials are folded per v_min3 with no mask;
-//   tail: beyond that, each predecessor is masked per lane and the scan
-//         stops when no lane admits it any more.
+// demands through the tour from its own LDS row.  The per-position table
+// {customer, c_i} is uniform across the wave and is read with scalar loads.
+// The last R potentials f_p and thresholds L_p + Q of a lane live in
+// registers; the position loop is unrolled R times so every ring slot is a
+// compile-time register, and the masked window minimum of a position is the
+// inline-assembly block of window_min_asm.inc (see gen_window_asm.py).
 // A lane whose window reaches past the ring, and any tile whose demands do
 // not fit a byte, are recomputed by an exact fallback kernel.
 //
@@ -36,6 +34,11 @@
 // window leaves m = INF, and every later value stays >= INF because all
 // route costs are non-negative, while feasible values stay < 2^29 under the
 // documented cost guard; V(n) >= INF is reported as SPLIT_INF.
+//
+// Per-tour sums: every unit adds its exact int64 partial sum into one of
+// kSlots per-tour slots (128 bytes apart, so concurrent atomics spread over
+// L2 channels); the last block of the fallback kernel folds the slots into
+// the tour's sum and mean (sum / S, one IEEE double division).
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -53,12 +56,15 @@ constexpr int kNeg = -(1 << 30); // threshold of ring slots before the tour star
 
 enum : int { ST_OK = 0, ST_BAD_TOUR = 1, ST_BAD_DEMAND = 2 };
 
+typedef const __attribute__((address_space(4))) int CInt; // scalar-loadable table words
+
+// table entry j of a per-tour table viewed as scalar-loadable words
+__device__ __forceinline__ int2 tab_at(CInt *tab, int j) { return make_int2(tab[2 * j], tab[2 * j + 1]); }
+
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
-
-__device__ __forceinline__ int min3i(int a, int b, int c) { return min(a, min(b, c)); }
 
 __device__ __forceinline__ long long wave_sum_i64(long long v)
 {
@@ -76,9 +82,27 @@ __device__ __forceinline__ int wave_sum_i32(int v)
     return v;
 }
 
+// slot k of tour t: {sum, number of SPLIT_INF costs}
+__device__ __forceinline__ long long *slot_ptr(const Workspace &ws, int t, int k)
+{
+    return ws.slots + ((int64_t)t * kSlots + k) * kSlotStride;
+}
+
+__device__ __forceinline__ void add_unit_result(const Workspace &ws, int t, int64_t unit,
+                                                long long sum, int ninf)
+{
+    long long *sp = slot_ptr(ws, t, (int)(unit % kSlots));
+    if (sum)
+        atomicAdd(reinterpret_cast<unsigned long long *>(sp), (unsigned long long)sum);
+    if (ninf)
+        atomicAdd(reinterpret_cast<unsigned long long *>(sp + 1), (unsigned long long)ninf);
+}
+
 // ---------------------------------------------------------------------------
-// prep: per-tour constants (state table), validation, counter reset
+// prep: per-tour table, validation, accumulator reset
 // grid = num_tours blocks of 256 threads
+// tab[t * (max_len + 3) + j] = {customer index of position j, c_j} for
+// j = 1..n, zero at j = 0 and for the padding entries n+1, n+2.
 // ---------------------------------------------------------------------------
 constexpr int kPrepThreads = 256;
 
@@ -95,9 +119,14 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1), wid = tid / kWave;
     const int64_t N1 = (int64_t)N + 1;
+    (void)num_tours;
 
-    if (t == 0 && tid == 0)
+    if (t == 0 && tid == 0) {
         *ws.list_count = 0;
+        *ws.done = 0;
+    }
+    for (int i = tid; i < kSlots * kSlotStride; i += kPrepThreads)
+        ws.slots[(int64_t)t * kSlots * kSlotStride + i] = 0;
 
     // offset of this tour in the concatenated array; an invalid earlier
     // length makes the layout ambiguous, so this tour is rejected too
@@ -132,8 +161,11 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(
         s_carry = 0;
     __syncthreads();
 
-    int2 *st = ws.st + (int64_t)t * max_len;
+    int2 *tab = ws.tab + (int64_t)t * (max_len + 3);
     int2 *ab = ws.ab + (int64_t)t * max_len;
+    for (int i = tid; i < 3; i += kPrepThreads)
+        tab[i == 0 ? 0 : nn + i] = make_int2(0, 0);
+    int first_out = 0;
     for (int base = 0; base < nn; base += kPrepThreads) {
         const int k = base + tid; // tour position k+1 (0-based k)
         long long arc = 0;
@@ -160,6 +192,8 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(
                 a > SPLIT_MAX_COST)
                 bad = 1;
             maxc = max(maxc, max(out, max(in, a)));
+            if (k == 0)
+                first_out = out;
         }
         // exclusive prefix of arc over positions: D_{k+1} = sum_{m<k} arc_m
         long long incl = arc;
@@ -183,21 +217,24 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(
             const long long ak = (long long)out - Dk;
             const long long bk = Dk + in;
             const int ck = (k + 1 < nn) ? (in + outn - (int)arc) : 0;
-            st[k] = make_int2(c - 1, ck);
+            tab[k + 1] = make_int2(c - 1, ck);
             ab[k] = make_int2((int)ak, (int)bk);
         }
         __syncthreads();
     }
 
-    // reduce bad flag and largest cost
-    int b = bad, mc = maxc;
+    // reduce bad flag, largest cost and the first depot leg
+    int b = bad, mc = maxc, fo = first_out;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
         b |= __shfl_xor(b, o, kWave);
         mc = max(mc, __shfl_xor(mc, o, kWave));
+        fo = max(fo, __shfl_xor(fo, o, kWave));
     }
     if (lane == 0)
         s_redi[wid] = b ? -1 : mc;
+    if (tid == 0)
+        s_red[0] = fo; // only thread 0 (position 1) holds a non-zero first leg
     __syncthreads();
     if (tid == 0) {
         int allbad = 0, allmax = 0;
@@ -212,7 +249,7 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(
             allbad = 1;
         TourRec r;
         r.n = nn;
-        r.f0 = nn > 0 ? ab[0].x : 0;
+        r.f0 = (int)s_red[0]; // a_1 = c[0][sigma_1] since D_1 = 0
         r.bn = nn > 0 ? ab[nn - 1].y : 0;
         r.status = allbad ? ST_BAD_TOUR : ST_OK;
         ws.rec[t] = r;
@@ -268,22 +305,16 @@ __device__ __forceinline__ bool stage_tile_u8(const int16_t *__restrict__ src, u
 // ---------------------------------------------------------------------------
 // the per-lane recursion, ring of R potentials in registers
 //
-// One DpState<R, U>::run advances every lane of the wave by one tour
+// One DpState<...>::run advances every lane of the wave by one tour
 // position j (j = R*block + U); ring slot (j - d) mod R = (U - d) mod R holds
-// predecessor p = j - d, so every slot is a compile-time register.  The
-// masked window minimum is the inline-assembly block of window_min_asm.inc:
-//   head: pair (d, d+1) is folded with one v_min3 while every active lane
-//         admits d+1 (hence d, the window being contiguous);
-//   tail: from the first pair some lane rejects, v_cmpx narrows EXEC to the
-//         lanes still admitting d and the scan ends when EXEC is empty.
-// Loads are software-pipelined: the demand of j+1 and the table entry of
-// j+2 are in flight while position j is relaxed.
+// predecessor p = j - d, so every slot is a compile-time register.  Loads
+// are software-pipelined: the demand of j+1 and the table entry of j+2 are
+// in flight while position j is relaxed.
 // ---------------------------------------------------------------------------
 #include "window_min_asm.inc"
 
 struct DpRegs {
     int L;    // load of positions 1..j
-    int q;    // demand of the current position (arrived)
     int qn;   // demand of the next position (in flight)
     int2 tn;  // table entry of the next position {customer, c}
     int2 tnn; // table entry of the position after next (in flight)
@@ -291,36 +322,23 @@ struct DpRegs {
     int ovf;  // 1 when a window reached past the ring
 };
 
-template <int R, int U> struct DpState {
-    static_assert(R == 32 || R == 64, "ring of 32 or 64 potentials");
+template <int R, int FIRST, int EVERY, int U> struct DpState {
     __device__ __forceinline__ static bool run(int (&f)[R], int (&lq)[R], DpRegs &r,
-                                               const uint8_t *row, const int2 *tab, int j0,
-                                               int n, int Q)
+                                               const uint8_t *row, CInt *tab, int j0, int n,
+                                               int Q)
     {
         const int j = j0 + U;
         if (j == 0)
             return true;
         if (j > n)
             return false;
-        r.q = r.qn;
+        const int q = r.qn;
         const int cj = r.tn.y;
         r.tn = r.tnn;
         r.qn = row[r.tn.x];
-        r.tnn = tab[j + 2];
-        r.L += r.q;
-        int m;
-        uint64_t sv, c;
-        if constexpr (R == 32) {
-            asm volatile(SPLIT_WINDOW_ASM_R32
-                         : [m] "=&v"(m), [ov] "+v"(r.ovf), [sv] "=&s"(sv), [c] "=&s"(c)
-                         : [L] "v"(r.L), [j] "s"(j), SPLIT_WINDOW_OPERANDS_R32(f, lq, U)
-                         : "vcc", "scc");
-        } else {
-            asm volatile(SPLIT_WINDOW_ASM_R64
-                         : [m] "=&v"(m), [ov] "+v"(r.ovf), [sv] "=&s"(sv), [c] "=&s"(c)
-                         : [L] "v"(r.L), [j] "s"(j), SPLIT_WINDOW_OPERANDS_R64(f, lq, U)
-                         : "vcc", "scc");
-        }
+        r.tnn = tab_at(tab, j + 2);
+        r.L += q;
+        const int m = WindowMin<R, FIRST, EVERY>::template run<U>(f, lq, r.L, j, r.ovf);
         r.mres = m; // the last position relaxed is j = n
         f[U] = m + cj;
         lq[U] = r.L + Q;
@@ -328,18 +346,17 @@ template <int R, int U> struct DpState {
     }
 };
 
-template <int R, int... Us>
+template <int R, int FIRST, int EVERY, int... Us>
 __device__ __forceinline__ bool dp_block(int (&f)[R], int (&lq)[R], DpRegs &r, const uint8_t *row,
-                                         const int2 *tab, int j0, int n, int Q,
+                                         CInt *tab, int j0, int n, int Q,
                                          std::integer_sequence<int, Us...>)
 {
-    return (DpState<R, Us>::run(f, lq, r, row, tab, j0, n, Q) && ...);
+    return (DpState<R, FIRST, EVERY, Us>::run(f, lq, r, row, tab, j0, n, Q) && ...);
 }
 
-// tab[j] = {customer index of position j, c_j} for j = 1..n (tab[0] unused,
-// two padding entries after n); returns m_n.
-template <int R>
-__device__ __forceinline__ int dp_lane(const uint8_t *row, const int2 *tab, int n, int f0, int Q,
+// Returns m_n of the lane's scenario; sets ovf when a window left the ring.
+template <int R, int FIRST, int EVERY>
+__device__ __forceinline__ int dp_lane(const uint8_t *row, CInt *tab, int n, int f0, int Q,
                                        bool &ovf)
 {
     int f[R], lq[R];
@@ -354,11 +371,12 @@ __device__ __forceinline__ int dp_lane(const uint8_t *row, const int2 *tab, int 
     r.L = 0;
     r.mres = kInf;
     r.ovf = 0;
-    r.tn = tab[1];
+    r.tn = tab_at(tab, 1);
     r.qn = row[r.tn.x];
-    r.tnn = tab[2];
+    r.tnn = tab_at(tab, 2);
     for (int j0 = 0; j0 <= n; j0 += R) {
-        if (!dp_block<R>(f, lq, r, row, tab, j0, n, Q, std::make_integer_sequence<int, R>{}))
+        if (!dp_block<R, FIRST, EVERY>(f, lq, r, row, tab, j0, n, Q,
+                                       std::make_integer_sequence<int, R>{}))
             break;
     }
     ovf = r.ovf != 0;
@@ -369,10 +387,9 @@ __device__ __forceinline__ int dp_lane(const uint8_t *row, const int2 *tab, int 
 // main evaluation kernel: one wave per (tile, tour) unit
 // unit u -> tile k = u / T, tour t = u % T  (all tours of a tile run close
 // together in time, so a shared demand tile is read from HBM once per XCD)
-//
-// LDS: [64 x N demand bytes, 16-aligned][table: (max_len + 3) int2]
+// LDS: 64 x N demand bytes
 // ---------------------------------------------------------------------------
-template <int R>
+template <int R, int FIRST, int EVERY>
 __global__ __launch_bounds__(kWave) void split_tile_kernel(const int16_t *__restrict__ demands,
                                                            int32_t N, int64_t S, int32_t Q,
                                                            int32_t T, int32_t *__restrict__ costs,
@@ -388,44 +405,23 @@ __global__ __launch_bounds__(kWave) void split_tile_kernel(const int16_t *__rest
     const TourRec rec = ws.rec[t];
     int32_t *out = costs + (int64_t)t * S + s0;
 
-    if (rec.status != ST_OK) {
+    if (rec.status != ST_OK || rec.n == 0) {
         if (lane < rows)
-            out[lane] = SPLIT_INF;
-        if (lane == 0) {
-            ws.tile_sum[u] = 0;
-            ws.tile_inf[u] = 0;
-        }
-        return;
-    }
-    if (rec.n == 0) {
-        if (lane < rows)
-            out[lane] = 0;
-        if (lane == 0) {
-            ws.tile_sum[u] = 0;
-            ws.tile_inf[u] = 0;
-        }
+            out[lane] = rec.status != ST_OK ? SPLIT_INF : 0;
         return;
     }
 
     bool redo = true;
     if (use_lds) {
-        const int n = rec.n;
-        const size_t rows_bytes = ((size_t)kWave * N + 15) & ~(size_t)15;
-        int2 *tab = reinterpret_cast<int2 *>(lds + rows_bytes);
-        const int2 *st = ws.st + (int64_t)t * ws.max_len;
-        for (int i = lane; i < n + 3; i += kWave) {
-            int2 e = make_int2(0, 0);
-            if (i >= 1 && i <= n)
-                e = st[i - 1];
-            tab[i] = e;
-        }
         const bool ok = stage_tile_u8(demands + s0 * N, lds, (int64_t)rows * N, lane);
         __syncthreads();
         if (ok) {
+            CInt *tab = (CInt *)(ws.tab + (int64_t)t * (ws.max_len + 3));
             bool ovf = false;
             int v = 0;
             if (lane < rows) {
-                const int m = dp_lane<R>(lds + (int64_t)lane * N, tab, n, rec.f0, Q, ovf);
+                const int m = dp_lane<R, FIRST, EVERY>(lds + (int64_t)lane * N, tab, rec.n,
+                                                       rec.f0, Q, ovf);
                 v = m + rec.bn;
             }
             redo = ballot(ovf) != 0;
@@ -436,10 +432,8 @@ __global__ __launch_bounds__(kWave) void split_tile_kernel(const int16_t *__rest
                     out[lane] = inf ? SPLIT_INF : v;
                 const long long s = wave_sum_i64(fin ? (long long)v : 0LL);
                 const int ni = wave_sum_i32(inf ? 1 : 0);
-                if (lane == 0) {
-                    ws.tile_sum[u] = s;
-                    ws.tile_inf[u] = ni;
-                }
+                if (lane == 0)
+                    add_unit_result(ws, t, u, s, ni);
             }
         }
     }
@@ -450,15 +444,16 @@ __global__ __launch_bounds__(kWave) void split_tile_kernel(const int16_t *__rest
 }
 
 // ---------------------------------------------------------------------------
-// exact fallback: listed units, straight from the definition
-// (any window length, any demand value), V history in global scratch
+// exact fallback for listed units (any window length, any demand value),
+// straight from the definition with the value history in global scratch;
+// the last block to finish folds every tour's slots into its sum and mean
 // ---------------------------------------------------------------------------
 constexpr int kFallbackBlocks = 64;
 
-__global__ __launch_bounds__(kWave) void split_fallback_kernel(const int16_t *__restrict__ demands,
+__global__ __launch_bounds__(kWave) void fallback_final_kernel(const int16_t *__restrict__ demands,
                                                                int32_t N, int64_t S, int32_t Q,
-                                                               int32_t T,
-                                                               int32_t *__restrict__ costs,
+                                                               int32_t T, int32_t *costs,
+                                                               int64_t *sums, double *means,
                                                                Workspace ws)
 {
     const int lane = threadIdx.x;
@@ -471,7 +466,7 @@ __global__ __launch_bounds__(kWave) void split_fallback_kernel(const int16_t *__
         const int64_t s0 = k * kWave;
         const int rows = (int)min<int64_t>(kWave, S - s0);
         const TourRec rec = ws.rec[t];
-        const int2 *st = ws.st + (int64_t)t * ws.max_len;
+        const int2 *tab = ws.tab + (int64_t)t * (ws.max_len + 3);
         const int2 *ab = ws.ab + (int64_t)t * ws.max_len;
         const int n = rec.n;
         int v = 0;
@@ -484,7 +479,7 @@ __global__ __launch_bounds__(kWave) void split_fallback_kernel(const int16_t *__
                 int best = kInf;
                 int load = 0;
                 for (int p = j - 1; p >= 0; --p) {
-                    const int q = qrow[st[p].x];
+                    const int q = qrow[tab[p + 1].x];
                     negq = negq || q < 0;
                     load += q;
                     if (load > Q)
@@ -507,63 +502,47 @@ __global__ __launch_bounds__(kWave) void split_fallback_kernel(const int16_t *__
             costs[(int64_t)t * S + s0 + lane] = inf ? SPLIT_INF : v;
         const long long s = wave_sum_i64(fin ? (long long)v : 0LL);
         const int ni = wave_sum_i32(inf ? 1 : 0);
-        if (lane == 0) {
-            ws.tile_sum[u] = s;
-            ws.tile_inf[u] = ni;
-        }
+        if (lane == 0)
+            add_unit_result(ws, t, u, s, ni);
     }
-}
 
-// ---------------------------------------------------------------------------
-// finalize: per-tour exact sum over tiles, mean = sum / S
-// ---------------------------------------------------------------------------
-constexpr int kFinThreads = 256;
-
-__global__ __launch_bounds__(kFinThreads) void finalize_kernel(int64_t S, int32_t T,
-                                                               int64_t tiles, int32_t *costs,
-                                                               int64_t *sums, double *means,
-                                                               Workspace ws)
-{
-    __shared__ long long s_sum[kFinThreads / kWave];
-    __shared__ int s_inf[kFinThreads / kWave];
-    const int t = blockIdx.x;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-    long long s = 0;
-    int ni = 0;
-    for (int64_t k = tid; k < tiles; k += kFinThreads) {
-        s += ws.tile_sum[k * T + t];
-        ni += ws.tile_inf[k * T + t];
-    }
-    s = wave_sum_i64(s);
-    ni = wave_sum_i32(ni);
+    // last block: per-tour exact sum over slots, mean = sum / S
+    int last = 0;
     if (lane == 0) {
-        s_sum[wid] = s;
-        s_inf[wid] = ni;
+        __threadfence();
+        last = atomicAdd(ws.done, 1) == (int)gridDim.x - 1;
     }
-    __syncthreads();
-    const int status = ws.rec[t].status;
-    if (status != ST_OK) {
-        // invalid inputs: every cost SPLIT_INF, the sum marks the error
-        for (int64_t i = tid; i < S; i += kFinThreads)
-            costs[(int64_t)t * S + i] = SPLIT_INF;
-    }
-    if (tid == 0) {
-        long long tot = 0;
-        int totinf = 0;
-        for (int w = 0; w < kFinThreads / kWave; ++w) {
-            tot += s_sum[w];
-            totinf += s_inf[w];
+    last = __shfl(last, 0, kWave);
+    if (!last)
+        return;
+    __threadfence();
+    for (int t = lane; t < T; t += kWave) {
+        long long tot = 0, ninf = 0;
+        for (int k = 0; k < kSlots; ++k) {
+            long long *sp = slot_ptr(ws, t, k);
+            tot += __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ninf += __hip_atomic_load(sp + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+        const int status =
+            __hip_atomic_load(&ws.rec[t].status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (status != ST_OK) {
             sums[t] = SPLIT_SUM_INVALID;
             means[t] = __builtin_nan("");
-        } else if (totinf) {
+        } else if (ninf) {
             sums[t] = INT64_MAX;
             means[t] = __builtin_inf();
         } else {
             sums[t] = tot;
             means[t] = (double)tot / (double)S;
         }
+    }
+    // invalid tours (rare): every cost of the tour becomes SPLIT_INF
+    for (int t = 0; t < T; ++t) {
+        const int status =
+            __hip_atomic_load(&ws.rec[t].status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (status != ST_OK)
+            for (int64_t i = lane; i < S; i += kWave)
+                costs[(int64_t)t * S + i] = SPLIT_INF;
     }
 }
 
@@ -590,11 +569,11 @@ __global__ __launch_bounds__(kWave) void count_cells_kernel(const int32_t *__res
     long long cnt = 0;
     if (s < S) {
         const int16_t *qrow = demands + s * N;
-        int L = 0, Ll = 0, l = 0; // window [l, j-1]; Ll = load of positions 1..l
         auto q_at = [&](int pos) { // demand of tour position pos (ids clamped into range)
             const int c = min(max(tour[pos - 1], 1), N);
             return (int)qrow[c - 1];
         };
+        int L = 0, Ll = 0, l = 0; // window [l, j-1]; Ll = load of positions 1..l
         for (int j = 1; j <= n; ++j) {
             L += q_at(j);
             while (l < j && L - Ll > Q) {
@@ -627,13 +606,12 @@ size_t workspace_bytes(int32_t T, int32_t max_len, int64_t S)
 {
     const size_t units = (size_t)T * (size_t)num_tiles(S);
     size_t b = 0;
-    b += align256((size_t)T * max_len * sizeof(int2));
+    b += align256((size_t)T * ((size_t)max_len + 3) * sizeof(int2));
     b += align256((size_t)T * max_len * sizeof(int2));
     b += align256((size_t)T * sizeof(TourRec));
-    b += align256(units * sizeof(long long));
+    b += align256((size_t)T * kSlots * kSlotStride * sizeof(long long));
     b += align256(units * sizeof(int));
-    b += align256(units * sizeof(int));
-    b += align256(sizeof(int));
+    b += align256(2 * sizeof(int));
     b += align256((size_t)kFallbackBlocks * kWave * ((size_t)max_len + 1) * sizeof(int));
     return b;
 }
@@ -643,20 +621,19 @@ Workspace carve_workspace(void *base, int32_t T, int32_t max_len, int64_t S)
     const size_t units = (size_t)T * (size_t)num_tiles(S);
     char *p = static_cast<char *>(base);
     Workspace ws;
-    ws.st = reinterpret_cast<int2 *>(p);
-    p += align256((size_t)T * max_len * sizeof(int2));
+    ws.tab = reinterpret_cast<int2 *>(p);
+    p += align256((size_t)T * ((size_t)max_len + 3) * sizeof(int2));
     ws.ab = reinterpret_cast<int2 *>(p);
     p += align256((size_t)T * max_len * sizeof(int2));
     ws.rec = reinterpret_cast<TourRec *>(p);
     p += align256((size_t)T * sizeof(TourRec));
-    ws.tile_sum = reinterpret_cast<long long *>(p);
-    p += align256(units * sizeof(long long));
-    ws.tile_inf = reinterpret_cast<int *>(p);
-    p += align256(units * sizeof(int));
+    ws.slots = reinterpret_cast<long long *>(p);
+    p += align256((size_t)T * kSlots * kSlotStride * sizeof(long long));
     ws.list = reinterpret_cast<int *>(p);
     p += align256(units * sizeof(int));
     ws.list_count = reinterpret_cast<int *>(p);
-    p += align256(sizeof(int));
+    ws.done = ws.list_count + 1;
+    p += align256(2 * sizeof(int));
     ws.vscratch = reinterpret_cast<int *>(p);
     ws.max_len = max_len;
     return ws;
@@ -668,16 +645,27 @@ Schedule default_schedule(int32_t N, int64_t S, int32_t Q)
     (void)S;
     Schedule s;
     s.ring = Q > 200 ? 64 : 32;
+    s.first = 8;
+    s.every = 3;
     return s;
 }
 
-template <int R>
+bool schedule_supported(const Schedule &s)
+{
+#define SPLIT_SUPPORTED(R_, F_, E_)                                                              \
+    if (s.ring == R_ && s.first == F_ && s.every == E_)                                          \
+        return true;
+    SPLIT_WINDOW_VARIANTS(SPLIT_SUPPORTED)
+#undef SPLIT_SUPPORTED
+    return false;
+}
+
+template <int R, int FIRST, int EVERY>
 static hipError_t launch_tiles(const int16_t *demands, int32_t N, int64_t S, int32_t Q, int32_t T,
                                int32_t *costs, const Workspace &ws, hipStream_t stream)
 {
     const int64_t units = (int64_t)T * num_tiles(S);
-    const size_t lds = (((size_t)kTile * (size_t)N + 15) & ~(size_t)15) +
-                       ((size_t)ws.max_len + 3) * sizeof(int2);
+    const size_t lds = ((size_t)kTile * (size_t)N + 15) & ~(size_t)15;
     static int lds_limit = -1;
     if (lds_limit < 0) {
         int dev = 0, lim = 0;
@@ -687,42 +675,52 @@ static hipError_t launch_tiles(const int16_t *demands, int32_t N, int64_t S, int
         if (e != hipSuccess)
             return e;
         lim = lim < kLdsLimit ? lim : kLdsLimit;
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&split_tile_kernel<R>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        e = hipFuncSetAttribute(
+            reinterpret_cast<const void *>(&split_tile_kernel<R, FIRST, EVERY>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
         if (e != hipSuccess)
             return e;
         lds_limit = lim;
     }
     const int use_lds = lds <= (size_t)lds_limit ? 1 : 0;
     const size_t lds_bytes = use_lds ? lds : 0;
-    hipLaunchKernelGGL(split_tile_kernel<R>, dim3((unsigned)units), dim3(kWave), lds_bytes, stream,
-                       demands, N, S, Q, T, costs, ws, use_lds);
+    hipLaunchKernelGGL((split_tile_kernel<R, FIRST, EVERY>), dim3((unsigned)units), dim3(kWave),
+                       lds_bytes, stream, demands, N, S, Q, T, costs, ws, use_lds);
     return hipGetLastError();
 }
 
 hipError_t launch_eval(const int32_t *tours, const int32_t *lens, int32_t T, int32_t max_len,
                        const int32_t *dist, int32_t N, const int16_t *demands, int64_t S,
                        int32_t Q, int32_t *costs, int64_t *sums, double *means,
-                       const Workspace &ws, hipStream_t stream, const Schedule &sched)
+                       const Workspace &ws, hipStream_t stream, const Schedule &sched,
+                       const LaunchEvents *ev)
 {
+    if (!schedule_supported(sched))
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(prep_kernel, dim3(T), dim3(kPrepThreads), 0, stream, tours, lens, T,
                        max_len, dist, N, ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    if (sched.ring == 64)
-        e = launch_tiles<64>(demands, N, S, Q, T, costs, ws, stream);
-    else
-        e = launch_tiles<32>(demands, N, S, Q, T, costs, ws, stream);
+    if (ev && ev->before) {
+        e = hipEventRecord(ev->before, stream);
+        if (e != hipSuccess)
+            return e;
+    }
+#define SPLIT_LAUNCH(R_, F_, E_)                                                                 \
+    if (sched.ring == R_ && sched.first == F_ && sched.every == E_)                               \
+        e = launch_tiles<R_, F_, E_>(demands, N, S, Q, T, costs, ws, stream);
+    SPLIT_WINDOW_VARIANTS(SPLIT_LAUNCH)
+#undef SPLIT_LAUNCH
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(split_fallback_kernel, dim3(kFallbackBlocks), dim3(kWave), 0, stream,
-                       demands, N, S, Q, T, costs, ws);
-    e = hipGetLastError();
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(finalize_kernel, dim3(T), dim3(kFinThreads), 0, stream, S, T, num_tiles(S),
-                       costs, sums, means, ws);
+    if (ev && ev->after) {
+        e = hipEventRecord(ev->after, stream);
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(fallback_final_kernel, dim3(kFallbackBlocks), dim3(kWave), 0, stream,
+                       demands, N, S, Q, T, costs, sums, means, ws);
     return hipGetLastError();
 }
 

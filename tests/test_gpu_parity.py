@@ -141,11 +141,25 @@ def _edge_instances():
 @pytest.mark.parametrize("k", range(len(_edge_instances())))
 def test_edge_cases(binding, k, ring):
     inst = _edge_instances()[k]
-    binding.set_ring(ring)
+    binding.set_schedule(ring, 8, 2)
     try:
         _run_both(binding, inst, label="%s ring=%d" % (inst.name, ring), host_form=True)
     finally:
-        binding.set_ring(0)
+        binding.set_schedule(0)
+
+
+def test_every_schedule_on_paper_shape(binding):
+    """All compiled schedules give identical results (n=200, Q=150 shape)."""
+    inst = W.plain_paper_scale(11, S=20_000)
+    tours, lens, dist, dem = W.as_arrays(inst)
+    ref = oracle.split_eval(tours, lens, dist, dem, inst.Q, nthreads=THREADS)
+    for sched in binding.SCHEDULES:
+        _say("schedule %s" % (sched,))
+        binding.set_schedule(*sched)
+        try:
+            _assert_same(_device_eval(binding, tours, lens, dist, dem, inst.Q), ref, "schedule %s" % (sched,))
+        finally:
+            binding.set_schedule(0)
 
 
 def test_large_customer_pool_beyond_lds(binding):
