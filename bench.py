@@ -184,24 +184,27 @@ def main():
     torch.cuda.synchronize()
     log("inputs resident (%.1f MB demands); %d Bellman cells per step" % (dem.nbytes / 1e6, cells))
 
-    def step():
+    def eager_step():
         binding.split_eval_device(t, l, d, q, inst.Q, max_len=n, out=out, workspace=ws)
 
+    # main-kernel duration: HIP events around each launch, eager launches
     for _ in range(args.warmup):
-        step()
+        eager_step()
     torch.cuda.synchronize()
     binding.profile_read()
     binding.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    sec = (time.perf_counter() - t0) / args.steps
+    sec_eager = timed_steps(torch, eager_step, args.steps, 0)
     kms, launches = binding.profile_read()
     binding.profile_enable(False)
     kernel_s = kms / 1e3 / max(launches, 1)
-    log("timed %d steps: %.3f ms/step, main kernel %.3f ms" % (args.steps, sec * 1e3, kernel_s * 1e3))
+
+    # the step: one replay of the captured evaluation graph
+    plan = binding.Plan(t, l, d, q, inst.Q, max_len=n)
+    sec = timed_steps(torch, plan.launch, args.steps, args.warmup)
+    same = torch.equal(plan.out.costs, out.costs) and torch.equal(plan.out.sums, out.sums)
+    plan.close()
+    log("timed %d steps: %.3f ms/step (graph), %.3f ms/step (eager), main kernel %.3f ms" % (
+        args.steps, sec * 1e3, sec_eager * 1e3, kernel_s * 1e3))
 
     if args.calibration_copy:
         for _ in range(3):
@@ -229,6 +232,8 @@ def main():
                                "round(Normal(mu,0.3mu))>=1 int16 scenario-major, int32 rounded Euclidean costs" % S,
                    "n": n, "S": S, "Q": inst.Q, "seed": args.seed, "cells_per_step": cells},
         "scenarios_per_s": S / sec,
+        "eager_ms_per_step": sec_eager * 1e3,
+        "graph_equals_eager": bool(same),
         "roofline": {
             "bound": "alu",
             "kernel": "split_tile_kernel",

@@ -133,11 +133,12 @@ int split_count_cells_device(const int32_t *d_tours, const int32_t *d_lens, int3
  * of the main kernel (longer windows are recomputed by the exact fallback,
  * so results never depend on it); first = cells of the first head group
  * validated with a single check (0 = pairs only); every = tail cells
- * between exits on an empty lane mask.  ring = 0 restores the automatic
- * choice.  Unsupported triples return SPLIT_EINVAL.  Not thread-safe
+ * between exits on an empty lane mask; waves = tours per workgroup that
+ * share one staged scenario tile (1, 2, 4 or 8; 0 = automatic).  ring = 0
+ * restores the automatic choice.  Unsupported triples return SPLIT_EINVAL.  Not thread-safe
  * against concurrent evaluations.
  */
-int split_set_schedule(int32_t ring, int32_t first, int32_t every);
+int split_set_schedule(int32_t ring, int32_t first, int32_t every, int32_t waves);
 
 /*
  * Measurement.  While enabled, every launch of the main evaluation kernel

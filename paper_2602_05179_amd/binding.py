@@ -71,7 +71,7 @@ def _load():
     lib.split_plan_destroy.restype = ctypes.c_int
     lib.split_plan_destroy.argtypes = [P]
     lib.split_set_schedule.restype = ctypes.c_int
-    lib.split_set_schedule.argtypes = [i32, i32, i32]
+    lib.split_set_schedule.argtypes = [i32, i32, i32, i32]
     lib.split_profile_enable.restype = ctypes.c_int
     lib.split_profile_enable.argtypes = [i32]
     lib.split_profile_read.restype = ctypes.c_int
@@ -91,12 +91,13 @@ def _check(rc: int):
         raise SplitError(rc, last_error())
 
 
-SCHEDULES = [(r, f, e) for r in (32, 64) for f, e in ((0, 1), (8, 2), (6, 2), (8, 3), (4, 2))]
+SCHEDULES = [(32, 0, 1), (32, 8, 2), (32, 8, 3), (32, 6, 3), (32, 4, 3), (32, 8, 4),
+             (64, 0, 1), (64, 8, 3), (64, 16, 3), (64, 24, 3)]
 
 
-def set_schedule(ring: int, first: int = 8, every: int = 2):
+def set_schedule(ring: int, first: int = 8, every: int = 3, waves: int = 0):
     """Force the main-kernel schedule; ring=0 restores the automatic choice."""
-    _check(lib.split_set_schedule(int(ring), int(first), int(every)))
+    _check(lib.split_set_schedule(int(ring), int(first), int(every), int(waves)))
 
 
 def profile_enable(on: bool = True):

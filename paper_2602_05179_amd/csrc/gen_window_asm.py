@@ -29,8 +29,12 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 INF_IMM = "2.0"  # inline constant with bit pattern 0x40000000 = 2^30
-RINGS = (32, 64)
-VARIANTS = ((0, 1), (8, 2), (6, 2), (8, 3), (4, 2))
+# (first, every) schedules compiled for each ring length
+VARIANTS = {
+    32: ((0, 1), (8, 2), (8, 3), (6, 3), (4, 3), (8, 4)),
+    64: ((0, 1), (8, 3), (16, 3), (24, 3)),
+}
+RINGS = tuple(VARIANTS)
 
 
 def head_groups(R, first):
@@ -150,12 +154,11 @@ def main():
             ""]
     for R in RINGS:
         text.append(emit_operands(R))
-        for first, every in VARIANTS:
-            if first < R:
-                text.append(emit(R, first, every))
-                text.append(emit_wrapper(R, first, every))
+        for first, every in VARIANTS[R]:
+            text.append(emit(R, first, every))
+            text.append(emit_wrapper(R, first, every))
     text.append("#define SPLIT_WINDOW_VARIANTS(X) \\")
-    combos = [(R, f, e) for R in RINGS for f, e in VARIANTS if f < R]
+    combos = [(R, f, e) for R in RINGS for f, e in VARIANTS[R]]
     for k, (R, f, e) in enumerate(combos):
         text.append("    X(%d, %d, %d)%s" % (R, f, e, " \\" if k + 1 < len(combos) else ""))
     text.append("")

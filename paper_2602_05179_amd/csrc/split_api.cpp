@@ -120,7 +120,7 @@ struct HostCtx {
 
 HostCtx g_ctx;
 
-splitk::Schedule g_override = {0, 0, 0}; // ring 0 = automatic
+splitk::Schedule g_override = {0, 0, 0, 0}; // ring 0 = automatic
 
 splitk::Schedule pick_schedule(int32_t N, int64_t S, int32_t Q)
 {
@@ -184,14 +184,16 @@ extern "C" {
 
 const char *split_last_error(void) { return g_err; }
 
-int split_set_schedule(int32_t ring, int32_t first, int32_t every)
+int split_set_schedule(int32_t ring, int32_t first, int32_t every, int32_t waves)
 {
     g_err[0] = 0;
     if (ring == 0) {
-        g_override = splitk::Schedule{0, 0, 0};
+        g_override = splitk::Schedule{0, 0, 0, 0};
         return SPLIT_OK;
     }
-    const splitk::Schedule s{ring, first, every};
+    const splitk::Schedule s{ring, first, every, waves};
+    if (waves != 0 && waves != 1 && waves != 2 && waves != 4 && waves != 8)
+        return fail(SPLIT_EINVAL, "waves must be 0, 1, 2, 4 or 8 (got %d)", waves);
     if (!splitk::schedule_supported(s))
         return fail(SPLIT_EINVAL, "unsupported schedule ring=%d first=%d every=%d", ring, first,
                     every);

@@ -21,7 +21,7 @@ struct Workspace {
     int2 *tab;             // [T * (max_len + 3)] {customer index, c_j}, padded
     int2 *ab;              // [T * max_len] {a_j, b_j} (exact fallback)
     TourRec *rec;          // [T]
-    long long *slots;      // [T * kSlots * kSlotStride] per-tour partial {sum, #inf}
+    long long *slots;      // [T * slots_per_tour(T) * kSlotStride] per-tour {sum, #inf}
     int *list;             // [units] units handed to the exact fallback
     int *list_count;       // [1]
     int *done;             // [1] fallback blocks finished
@@ -34,6 +34,7 @@ struct Schedule {
     int ring;  // register ring length R (32 or 64)
     int first; // cells of the first head group, validated once (0 = pairs)
     int every; // tail cells between exits on an empty EXEC
+    int waves; // tours (waves) per workgroup sharing one staged tile; 0 = automatic
 };
 
 // Optional events bracketing the main kernel launch (measurement only).
@@ -43,7 +44,7 @@ struct LaunchEvents {
 };
 
 constexpr int kTile = 64;            // scenarios per unit (one wave)
-constexpr int kSlots = 64;           // partial-sum slots per tour
+constexpr int kSlots = 64;           // partial-sum slots of a single tour (fewer when T > 1)
 constexpr int kSlotStride = 16;      // int64 words between slots (128 bytes)
 constexpr int kMaxLen = 65535;       // longest tour the library accepts
 constexpr int kLdsLimit = 160 * 1024; // LDS bytes one workgroup may use on gfx950

@@ -82,16 +82,23 @@ __device__ __forceinline__ int wave_sum_i32(int v)
     return v;
 }
 
-// slot k of tour t: {sum, number of SPLIT_INF costs}
-__device__ __forceinline__ long long *slot_ptr(const Workspace &ws, int t, int k)
+// Partial-sum slots per tour: enough that no slot sees many atomics (a
+// tour has ceil(S/64) units), few enough that the final fold stays short.
+__host__ __device__ __forceinline__ int slots_per_tour(int32_t T)
 {
-    return ws.slots + ((int64_t)t * kSlots + k) * kSlotStride;
+    return T >= kSlots ? 1 : kSlots / (1 << (31 - __builtin_clz((unsigned)T)));
 }
 
-__device__ __forceinline__ void add_unit_result(const Workspace &ws, int t, int64_t unit,
+// slot k of tour t: {sum, number of SPLIT_INF costs}
+__device__ __forceinline__ long long *slot_ptr(const Workspace &ws, int T, int t, int k)
+{
+    return ws.slots + ((int64_t)t * slots_per_tour(T) + k) * kSlotStride;
+}
+
+__device__ __forceinline__ void add_unit_result(const Workspace &ws, int T, int t, int64_t unit,
                                                 long long sum, int ninf)
 {
-    long long *sp = slot_ptr(ws, t, (int)(unit % kSlots));
+    long long *sp = slot_ptr(ws, T, t, (int)(unit % slots_per_tour(T)));
     if (sum)
         atomicAdd(reinterpret_cast<unsigned long long *>(sp), (unsigned long long)sum);
     if (ninf)
@@ -119,14 +126,14 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1), wid = tid / kWave;
     const int64_t N1 = (int64_t)N + 1;
-    (void)num_tours;
 
     if (t == 0 && tid == 0) {
         *ws.list_count = 0;
         *ws.done = 0;
     }
-    for (int i = tid; i < kSlots * kSlotStride; i += kPrepThreads)
-        ws.slots[(int64_t)t * kSlots * kSlotStride + i] = 0;
+    const int spt = slots_per_tour(num_tours);
+    for (int i = tid; i < spt * kSlotStride; i += kPrepThreads)
+        ws.slots[(int64_t)t * spt * kSlotStride + i] = 0;
 
     // offset of this tour in the concatenated array; an invalid earlier
     // length makes the layout ambiguous, so this tour is rejected too
@@ -262,19 +269,23 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(
 // ---------------------------------------------------------------------------
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+// s_bad: an LDS word outside the staged bytes (the block-wide "bad" flag)
 __device__ __forceinline__ bool stage_tile_u8(const int16_t *__restrict__ src, uint8_t *lds,
-                                              int64_t elems, int lane)
+                                              int64_t elems, int tid, int nthreads, int &s_bad)
 {
+    if (tid == 0)
+        s_bad = 0;
+    __syncthreads();
     const int64_t chunks = elems >> 3; // full 8-element (16-byte) chunks
     uint32_t bad = 0;
     const u32x4 *src4 = reinterpret_cast<const u32x4 *>(src);
     uint2 *dst8 = reinterpret_cast<uint2 *>(lds);
-    int64_t i = lane;
-    for (; i + 3 * kWave < chunks; i += 4 * kWave) {
+    int64_t i = tid;
+    for (; i + 3 * nthreads < chunks; i += 4 * nthreads) {
         u32x4 v[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            v[r] = __builtin_nontemporal_load(&src4[i + r * kWave]);
+            v[r] = __builtin_nontemporal_load(&src4[i + r * nthreads]);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const uint32_t x0 = v[r].x, x1 = v[r].y, x2 = v[r].z, x3 = v[r].w;
@@ -282,10 +293,10 @@ __device__ __forceinline__ bool stage_tile_u8(const int16_t *__restrict__ src, u
             uint2 o;
             o.x = __builtin_amdgcn_perm(x1, x0, 0x06040200u);
             o.y = __builtin_amdgcn_perm(x3, x2, 0x06040200u);
-            dst8[i + r * kWave] = o;
+            dst8[i + r * nthreads] = o;
         }
     }
-    for (; i < chunks; i += kWave) {
+    for (; i < chunks; i += nthreads) {
         const u32x4 v = __builtin_nontemporal_load(&src4[i]);
         const uint32_t x0 = v.x, x1 = v.y, x2 = v.z, x3 = v.w;
         bad |= (x0 | x1 | x2 | x3) & 0xFF00FF00u;
@@ -294,12 +305,15 @@ __device__ __forceinline__ bool stage_tile_u8(const int16_t *__restrict__ src, u
         o.y = __builtin_amdgcn_perm(x3, x2, 0x06040200u);
         dst8[i] = o;
     }
-    for (int64_t e = (chunks << 3) + lane; e < elems; e += kWave) {
+    for (int64_t e = (chunks << 3) + tid; e < elems; e += nthreads) {
         const int v = src[e];
         bad |= (v < 0 || v > 255) ? 1u : 0u;
         lds[e] = (uint8_t)v;
     }
-    return ballot(bad != 0) == 0;
+    if (ballot(bad != 0) != 0 && (tid & (kWave - 1)) == 0)
+        atomicOr(&s_bad, 1);
+    __syncthreads();
+    return s_bad == 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -384,57 +398,73 @@ __device__ __forceinline__ int dp_lane(const uint8_t *row, CInt *tab, int n, int
 }
 
 // ---------------------------------------------------------------------------
-// main evaluation kernel: one wave per (tile, tour) unit
-// unit u -> tile k = u / T, tour t = u % T  (all tours of a tile run close
-// together in time, so a shared demand tile is read from HBM once per XCD)
+// main evaluation kernel: a workgroup of W waves stages one tile of 64
+// scenario rows and runs W different tours over it (wave w takes tour
+// g*W + w), so tours sharing a scenario set share one LDS copy of it.
+// Workgroup b -> tile k = b / G, tour group g = b % G with G = ceil(T/W):
+// all tours of a tile run close together in time, so a shared demand tile
+// is read from HBM about once per XCD.  The (tile, tour) unit id used by
+// the fallback list is u = k*T + t.
 // LDS: 64 x N demand bytes
 // ---------------------------------------------------------------------------
+constexpr int kMaxWavesPerGroup = 8;
+
 template <int R, int FIRST, int EVERY>
-__global__ __launch_bounds__(kWave) void split_tile_kernel(const int16_t *__restrict__ demands,
-                                                           int32_t N, int64_t S, int32_t Q,
-                                                           int32_t T, int32_t *__restrict__ costs,
-                                                           Workspace ws, int32_t use_lds)
+__global__ __launch_bounds__(kWave *kMaxWavesPerGroup) void split_tile_kernel(
+    const int16_t *__restrict__ demands, int32_t N, int64_t S, int32_t Q, int32_t T,
+    int32_t *__restrict__ costs, Workspace ws, int32_t use_lds)
 {
     extern __shared__ __align__(16) uint8_t lds[];
-    const int64_t u = blockIdx.x;
-    const int lane = threadIdx.x;
-    const int64_t k = u / T;
-    const int t = (int)(u - k * T);
+    const int W = blockDim.x / kWave;
+    const int G = (T + W - 1) / W;
+    const int64_t b = blockIdx.x;
+    const int64_t k = b / G;
+    const int g = (int)(b - k * G);
+    const int lane = threadIdx.x & (kWave - 1);
+    // uniform within the wave; readfirstlane lets the compiler keep the
+    // tour's scalars (length, table pointer) in SGPRs
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int t = g * W + wave;
     const int64_t s0 = k * kWave;
     const int rows = (int)min<int64_t>(kWave, S - s0);
+
+    bool ok = false;
+    if (use_lds) {
+        int &s_bad = *reinterpret_cast<int *>(lds + (((size_t)kWave * N + 15) & ~(size_t)15));
+        ok = stage_tile_u8(demands + s0 * N, lds, (int64_t)rows * N, threadIdx.x, blockDim.x,
+                           s_bad);
+        __syncthreads();
+    }
+    if (t >= T)
+        return;
+    const int64_t u = k * T + t;
     const TourRec rec = ws.rec[t];
     int32_t *out = costs + (int64_t)t * S + s0;
-
     if (rec.status != ST_OK || rec.n == 0) {
         if (lane < rows)
             out[lane] = rec.status != ST_OK ? SPLIT_INF : 0;
         return;
     }
-
     bool redo = true;
-    if (use_lds) {
-        const bool ok = stage_tile_u8(demands + s0 * N, lds, (int64_t)rows * N, lane);
-        __syncthreads();
-        if (ok) {
-            CInt *tab = (CInt *)(ws.tab + (int64_t)t * (ws.max_len + 3));
-            bool ovf = false;
-            int v = 0;
-            if (lane < rows) {
-                const int m = dp_lane<R, FIRST, EVERY>(lds + (int64_t)lane * N, tab, rec.n,
-                                                       rec.f0, Q, ovf);
-                v = m + rec.bn;
-            }
-            redo = ballot(ovf) != 0;
-            if (!redo) {
-                const bool fin = lane < rows && v < kInf;
-                const bool inf = lane < rows && v >= kInf;
-                if (lane < rows)
-                    out[lane] = inf ? SPLIT_INF : v;
-                const long long s = wave_sum_i64(fin ? (long long)v : 0LL);
-                const int ni = wave_sum_i32(inf ? 1 : 0);
-                if (lane == 0)
-                    add_unit_result(ws, t, u, s, ni);
-            }
+    if (ok) {
+        CInt *tab = (CInt *)(ws.tab + (int64_t)t * (ws.max_len + 3));
+        bool ovf = false;
+        int v = 0;
+        if (lane < rows) {
+            const int m = dp_lane<R, FIRST, EVERY>(lds + (int64_t)lane * N, tab, rec.n, rec.f0,
+                                                   Q, ovf);
+            v = m + rec.bn;
+        }
+        redo = ballot(ovf) != 0;
+        if (!redo) {
+            const bool fin = lane < rows && v < kInf;
+            const bool inf = lane < rows && v >= kInf;
+            if (lane < rows)
+                out[lane] = inf ? SPLIT_INF : v;
+            const long long sm = wave_sum_i64(fin ? (long long)v : 0LL);
+            const int ni = wave_sum_i32(inf ? 1 : 0);
+            if (lane == 0)
+                add_unit_result(ws, T, t, u, sm, ni);
         }
     }
     if (redo && lane == 0) {
@@ -503,7 +533,7 @@ __global__ __launch_bounds__(kWave) void fallback_final_kernel(const int16_t *__
         const long long s = wave_sum_i64(fin ? (long long)v : 0LL);
         const int ni = wave_sum_i32(inf ? 1 : 0);
         if (lane == 0)
-            add_unit_result(ws, t, u, s, ni);
+            add_unit_result(ws, T, t, u, s, ni);
     }
 
     // last block: per-tour exact sum over slots, mean = sum / S
@@ -516,33 +546,47 @@ __global__ __launch_bounds__(kWave) void fallback_final_kernel(const int16_t *__
     if (!last)
         return;
     __threadfence();
-    for (int t = lane; t < T; t += kWave) {
+    // lanes cover (tour, slot) pairs; slots of one tour sit in a group of
+    // spt adjacent lanes (spt is a power of two dividing 64)
+    const int spt = slots_per_tour(T);
+    for (int base = 0; base < T * spt; base += kWave) { // uniform loop: every lane active
+        const int idx = base + lane;
+        const int t = idx / spt;
+        const int kk = idx - t * spt;
         long long tot = 0, ninf = 0;
-        for (int k = 0; k < kSlots; ++k) {
-            long long *sp = slot_ptr(ws, t, k);
-            tot += __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ninf += __hip_atomic_load(sp + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int status = ST_OK;
+        if (t < T) {
+            long long *sp = slot_ptr(ws, T, t, kk);
+            tot = __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ninf = __hip_atomic_load(sp + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            status = __hip_atomic_load(&ws.rec[t].status, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
         }
-        const int status =
-            __hip_atomic_load(&ws.rec[t].status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (status != ST_OK) {
-            sums[t] = SPLIT_SUM_INVALID;
-            means[t] = __builtin_nan("");
-        } else if (ninf) {
-            sums[t] = INT64_MAX;
-            means[t] = __builtin_inf();
-        } else {
-            sums[t] = tot;
-            means[t] = (double)tot / (double)S;
+        for (int o = 1; o < spt; o <<= 1) {
+            tot += __shfl_xor(tot, o, kWave);
+            ninf += __shfl_xor(ninf, o, kWave);
         }
-    }
-    // invalid tours (rare): every cost of the tour becomes SPLIT_INF
-    for (int t = 0; t < T; ++t) {
-        const int status =
-            __hip_atomic_load(&ws.rec[t].status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (status != ST_OK)
+        if (t < T && kk == 0) {
+            if (status != ST_OK) {
+                sums[t] = SPLIT_SUM_INVALID;
+                means[t] = __builtin_nan("");
+            } else if (ninf) {
+                sums[t] = INT64_MAX;
+                means[t] = __builtin_inf();
+            } else {
+                sums[t] = tot;
+                means[t] = (double)tot / (double)S;
+            }
+        }
+        // invalid tours (rare): every cost of the tour becomes SPLIT_INF
+        uint64_t bad = ballot(t < T && kk == 0 && status != ST_OK);
+        while (bad) {
+            const int l = __builtin_ctzll(bad);
+            bad &= bad - 1;
+            const int64_t tb = (base + l) / spt;
             for (int64_t i = lane; i < S; i += kWave)
-                costs[(int64_t)t * S + i] = SPLIT_INF;
+                costs[tb * S + i] = SPLIT_INF;
+        }
     }
 }
 
@@ -609,7 +653,7 @@ size_t workspace_bytes(int32_t T, int32_t max_len, int64_t S)
     b += align256((size_t)T * ((size_t)max_len + 3) * sizeof(int2));
     b += align256((size_t)T * max_len * sizeof(int2));
     b += align256((size_t)T * sizeof(TourRec));
-    b += align256((size_t)T * kSlots * kSlotStride * sizeof(long long));
+    b += align256((size_t)T * slots_per_tour(T) * kSlotStride * sizeof(long long));
     b += align256(units * sizeof(int));
     b += align256(2 * sizeof(int));
     b += align256((size_t)kFallbackBlocks * kWave * ((size_t)max_len + 1) * sizeof(int));
@@ -628,7 +672,7 @@ Workspace carve_workspace(void *base, int32_t T, int32_t max_len, int64_t S)
     ws.rec = reinterpret_cast<TourRec *>(p);
     p += align256((size_t)T * sizeof(TourRec));
     ws.slots = reinterpret_cast<long long *>(p);
-    p += align256((size_t)T * kSlots * kSlotStride * sizeof(long long));
+    p += align256((size_t)T * slots_per_tour(T) * kSlotStride * sizeof(long long));
     ws.list = reinterpret_cast<int *>(p);
     p += align256(units * sizeof(int));
     ws.list_count = reinterpret_cast<int *>(p);
@@ -645,8 +689,9 @@ Schedule default_schedule(int32_t N, int64_t S, int32_t Q)
     (void)S;
     Schedule s;
     s.ring = Q > 200 ? 64 : 32;
-    s.first = 8;
+    s.first = Q > 200 ? 16 : 8;
     s.every = 3;
+    s.waves = 0;
     return s;
 }
 
@@ -662,10 +707,11 @@ bool schedule_supported(const Schedule &s)
 
 template <int R, int FIRST, int EVERY>
 static hipError_t launch_tiles(const int16_t *demands, int32_t N, int64_t S, int32_t Q, int32_t T,
-                               int32_t *costs, const Workspace &ws, hipStream_t stream)
+                               int32_t *costs, const Workspace &ws, hipStream_t stream, int W)
 {
-    const int64_t units = (int64_t)T * num_tiles(S);
-    const size_t lds = ((size_t)kTile * (size_t)N + 15) & ~(size_t)15;
+    const int G = (T + W - 1) / W;
+    const int64_t groups = (int64_t)G * num_tiles(S);
+    const size_t lds = (((size_t)kTile * (size_t)N + 15) & ~(size_t)15) + 16; // rows + flag
     static int lds_limit = -1;
     if (lds_limit < 0) {
         int dev = 0, lim = 0;
@@ -684,9 +730,20 @@ static hipError_t launch_tiles(const int16_t *demands, int32_t N, int64_t S, int
     }
     const int use_lds = lds <= (size_t)lds_limit ? 1 : 0;
     const size_t lds_bytes = use_lds ? lds : 0;
-    hipLaunchKernelGGL((split_tile_kernel<R, FIRST, EVERY>), dim3((unsigned)units), dim3(kWave),
-                       lds_bytes, stream, demands, N, S, Q, T, costs, ws, use_lds);
+    hipLaunchKernelGGL((split_tile_kernel<R, FIRST, EVERY>), dim3((unsigned)groups),
+                       dim3(kWave * W), lds_bytes, stream, demands, N, S, Q, T, costs, ws,
+                       use_lds);
     return hipGetLastError();
+}
+
+// Tours per workgroup: enough to keep the shared tile's LDS per wave small.
+int waves_per_group(int32_t T, int32_t N)
+{
+    const int64_t bytes = (int64_t)kTile * N;
+    int W = 1;
+    while (W < kMaxWavesPerGroup && W < T && bytes / W > 8 * 1024)
+        W *= 2;
+    return W < T ? W : T;
 }
 
 hipError_t launch_eval(const int32_t *tours, const int32_t *lens, int32_t T, int32_t max_len,
@@ -709,7 +766,8 @@ hipError_t launch_eval(const int32_t *tours, const int32_t *lens, int32_t T, int
     }
 #define SPLIT_LAUNCH(R_, F_, E_)                                                                 \
     if (sched.ring == R_ && sched.first == F_ && sched.every == E_)                               \
-        e = launch_tiles<R_, F_, E_>(demands, N, S, Q, T, costs, ws, stream);
+        e = launch_tiles<R_, F_, E_>(demands, N, S, Q, T, costs, ws, stream,                \
+                                     sched.waves ? sched.waves : waves_per_group(T, N));
     SPLIT_WINDOW_VARIANTS(SPLIT_LAUNCH)
 #undef SPLIT_LAUNCH
     if (e != hipSuccess)

@@ -81,6 +81,17 @@ def test_paper_scale_full(binding):
     _run_both(binding, W.plain_paper_scale(3, S=1_000_000))
 
 
+@pytest.mark.parametrize("waves", [0, 1, 2, 8])
+def test_batched_tours_per_workgroup(binding, waves):
+    """Tours sharing a staged tile: any grouping gives the oracle's results."""
+    inst = W.batched_ragged(12, num_tours=37, S=1500)
+    binding.set_schedule(32, 8, 3, waves)
+    try:
+        _run_both(binding, inst, label="%s waves=%d" % (inst.name, waves))
+    finally:
+        binding.set_schedule(0)
+
+
 def test_batched_ragged_and_equal_to_plain(binding):
     inst = W.batched_ragged(4)
     got, ref = _run_both(binding, inst)
@@ -141,7 +152,7 @@ def _edge_instances():
 @pytest.mark.parametrize("k", range(len(_edge_instances())))
 def test_edge_cases(binding, k, ring):
     inst = _edge_instances()[k]
-    binding.set_schedule(ring, 8, 2)
+    binding.set_schedule(ring, 8, 3)
     try:
         _run_both(binding, inst, label="%s ring=%d" % (inst.name, ring), host_form=True)
     finally:
