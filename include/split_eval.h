@@ -134,11 +134,14 @@ int split_count_cells_device(const int32_t *d_tours, const int32_t *d_lens, int3
  * so results never depend on it); first = cells of the first head group
  * validated with a single check (0 = pairs only); every = tail cells
  * between exits on an empty lane mask; waves = tours per workgroup that
- * share one staged scenario tile (1, 2, 4 or 8; 0 = automatic).  ring = 0
- * restores the automatic choice.  Unsupported triples return SPLIT_EINVAL.  Not thread-safe
+ * share one staged scenario tile (1, 2, 4 or 8; 0 = automatic); path =
+ * 1 stages whole scenario rows in LDS and gathers through the tour, 2 first
+ * rewrites the demands in tour order and streams them (0 = automatic, by
+ * the LDS each wave would need).  ring = 0 restores the automatic choice.
+ * split_workspace_bytes accounts for the override in force when called.  Unsupported triples return SPLIT_EINVAL.  Not thread-safe
  * against concurrent evaluations.
  */
-int split_set_schedule(int32_t ring, int32_t first, int32_t every, int32_t waves);
+int split_set_schedule(int32_t ring, int32_t first, int32_t every, int32_t waves, int32_t path);
 
 /*
  * Measurement.  While enabled, every launch of the main evaluation kernel
@@ -164,6 +167,41 @@ int split_plan_create(split_plan **plan, const int32_t *d_tours, const int32_t *
                       int64_t *d_sums, double *d_means, split_stream_t stream);
 int split_plan_launch(split_plan *plan, split_stream_t stream);
 int split_plan_destroy(split_plan *plan);
+
+/*
+ * Served form: continuous batching of evaluation requests under an HBM
+ * budget.  Each request is one giant tour over its own customers (the same
+ * operation as split_eval with num_tours = 1).  The server reserves
+ * `budget_bytes` of device memory at creation; a request is admitted, in
+ * arrival order, once its own footprint (outputs and workspace, reported in
+ * split_server_stats) fits, and runs on one of `num_streams` HIP streams
+ * (1..8), so requests admitted while others run overlap on the device.
+ * Memory returns to the budget as soon as a request completes.
+ *
+ * split_server_submit copies the tour (host pointer, ids in [1, N]) and
+ *   returns a request id at once.  d_dist (int32 [(N+1)*(N+1)]) and
+ *   d_demands (int16 [S*N], 16-byte aligned) are DEVICE pointers that the
+ *   caller keeps valid and unmodified until the request completes (the
+ *   demands stay resident; the server does not copy them).  costs_out is an
+ *   optional HOST buffer of S int32 filled before completion is reported.
+ *   SPLIT_ENOMEM if the request alone exceeds the budget.
+ * split_server_poll returns SPLIT_EAGAIN while the request runs; once done it
+ *   returns its sum and mean (as split_eval) and its latency from submission
+ *   to completion in seconds, and forgets the request.  A request whose
+ *   inputs fail device-side validation returns SPLIT_EINVAL.
+ * split_server_wait blocks until the request is done (poll still needed).
+ * split_server_destroy waits for all admitted and pending requests.
+ */
+int split_server_create(split_server **server, size_t budget_bytes, int32_t num_streams);
+int split_server_submit(split_server *server, const int32_t *tour, int32_t n,
+                        const int32_t *d_dist, int32_t N, const int16_t *d_demands, int64_t S,
+                        int32_t Q, int32_t *costs_out, int64_t *request_id);
+int split_server_poll(split_server *server, int64_t request_id, int64_t *sum, double *mean,
+                      double *latency_s);
+int split_server_wait(split_server *server, int64_t request_id);
+int split_server_stats(split_server *server, int64_t *submitted, int64_t *completed,
+                       int64_t *pending, size_t *bytes_in_use, size_t *peak_bytes);
+int split_server_destroy(split_server *server);
 
 #ifdef __cplusplus
 }

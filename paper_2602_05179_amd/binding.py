@@ -34,6 +34,12 @@ EXPORTED = (
     "split_set_schedule",
     "split_profile_enable",
     "split_profile_read",
+    "split_server_create",
+    "split_server_submit",
+    "split_server_poll",
+    "split_server_wait",
+    "split_server_stats",
+    "split_server_destroy",
 )
 
 
@@ -71,11 +77,25 @@ def _load():
     lib.split_plan_destroy.restype = ctypes.c_int
     lib.split_plan_destroy.argtypes = [P]
     lib.split_set_schedule.restype = ctypes.c_int
-    lib.split_set_schedule.argtypes = [i32, i32, i32, i32]
+    lib.split_set_schedule.argtypes = [i32, i32, i32, i32, i32]
     lib.split_profile_enable.restype = ctypes.c_int
     lib.split_profile_enable.argtypes = [i32]
     lib.split_profile_read.restype = ctypes.c_int
     lib.split_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.split_server_create.restype = ctypes.c_int
+    lib.split_server_create.argtypes = [ctypes.POINTER(P), sz, i32]
+    lib.split_server_submit.restype = ctypes.c_int
+    lib.split_server_submit.argtypes = [P, P, i32, P, i32, P, i64, i32, P, ctypes.POINTER(i64)]
+    lib.split_server_poll.restype = ctypes.c_int
+    lib.split_server_poll.argtypes = [P, i64, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double)]
+    lib.split_server_wait.restype = ctypes.c_int
+    lib.split_server_wait.argtypes = [P, i64]
+    lib.split_server_stats.restype = ctypes.c_int
+    lib.split_server_stats.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                       ctypes.POINTER(sz), ctypes.POINTER(sz)]
+    lib.split_server_destroy.restype = ctypes.c_int
+    lib.split_server_destroy.argtypes = [P]
     return lib
 
 
@@ -95,9 +115,12 @@ SCHEDULES = [(32, 0, 1), (32, 8, 2), (32, 8, 3), (32, 6, 3), (32, 4, 3), (32, 8,
              (64, 0, 1), (64, 8, 3), (64, 16, 3), (64, 24, 3)]
 
 
-def set_schedule(ring: int, first: int = 8, every: int = 3, waves: int = 0):
+PATH_AUTO, PATH_FUSED, PATH_ORDERED = 0, 1, 2
+
+
+def set_schedule(ring: int, first: int = 8, every: int = 3, waves: int = 0, path: int = 0):
     """Force the main-kernel schedule; ring=0 restores the automatic choice."""
-    _check(lib.split_set_schedule(int(ring), int(first), int(every), int(waves)))
+    _check(lib.split_set_schedule(int(ring), int(first), int(every), int(waves), int(path)))
 
 
 def profile_enable(on: bool = True):
@@ -233,6 +256,64 @@ class Plan:
         if self._h:
             lib.split_plan_destroy(self._h)
             self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Served form: continuous batching of single-tour requests under an HBM
+    budget (C ABI split_server_*).  Demands and cost matrices are device
+    tensors the caller keeps alive until the request completes; this wrapper
+    holds a reference to them until the request is polled."""
+
+    def __init__(self, budget_bytes: int, streams: int = 4):
+        self._h = ctypes.c_void_p()
+        _check(lib.split_server_create(ctypes.byref(self._h), int(budget_bytes), int(streams)))
+        self._keep = {}
+
+    def submit(self, tour, dist, demands, Q, *, want_costs=False) -> int:
+        tour = np.ascontiguousarray(tour, np.int32)
+        N = int(dist.shape[0] - 1)
+        S = int(demands.shape[0])
+        costs = np.empty(S, np.int32) if want_costs else None
+        rid = ctypes.c_int64()
+        _check(lib.split_server_submit(self._h, _np_ptr(tour) if tour.size else None, int(tour.size), _dptr(dist),
+                                       N, _dptr(demands), S, int(Q),
+                                       _np_ptr(costs) if costs is not None else None, ctypes.byref(rid)))
+        self._keep[rid.value] = (dist, demands, costs)
+        return rid.value
+
+    def poll(self, rid: int):
+        """None while running, else dict(sum, mean, latency_s, costs)."""
+        sm, mn, lat = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        rc = lib.split_server_poll(self._h, int(rid), ctypes.byref(sm), ctypes.byref(mn), ctypes.byref(lat))
+        if rc == SPLIT_EAGAIN:
+            return None
+        keep = self._keep.pop(int(rid), (None, None, None))
+        _check(rc)
+        return dict(sum=sm.value, mean=mn.value, latency_s=lat.value, costs=keep[2])
+
+    def wait(self, rid: int):
+        _check(lib.split_server_wait(self._h, int(rid)))
+        return self.poll(rid)
+
+    def stats(self):
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        d, e = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib.split_server_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d),
+                                      ctypes.byref(e)))
+        return dict(submitted=a.value, completed=b.value, pending=c.value, bytes_in_use=d.value,
+                    peak_bytes=e.value)
+
+    def close(self):
+        if self._h:
+            lib.split_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._keep.clear()
 
     def __del__(self):
         try:

@@ -9,8 +9,10 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsplit_eval.so")
-SOURCES = [os.path.join(CSRC, "split_kernels.hip"), os.path.join(CSRC, "split_api.cpp")]
-HEADERS = [os.path.join(INCLUDE, "split_eval.h"), os.path.join(CSRC, "split_internal.h")]
+SOURCES = [os.path.join(CSRC, "split_kernels.hip"), os.path.join(CSRC, "split_api.cpp"),
+           os.path.join(CSRC, "split_server.cpp")]
+HEADERS = [os.path.join(INCLUDE, "split_eval.h"), os.path.join(CSRC, "split_internal.h"),
+           os.path.join(CSRC, "window_min_asm.inc")]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are disabled for every GPU object this library
@@ -18,7 +20,7 @@ ARCH = "gfx950"
 HIPCC_FLAGS = [
     "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wall", "-Wno-unused-function",
+    "-Wall", "-Wno-unused-function", "-pthread",
 ]
 
 

@@ -28,6 +28,25 @@ int fail(int code, const char *fmt, ...)
     return code;
 }
 
+} // namespace
+
+namespace splitk {
+
+int set_error(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+void clear_error() { g_err[0] = 0; }
+
+} // namespace splitk
+
+namespace {
+
 int hip_fail(hipError_t e, const char *what)
 {
     if (e == hipErrorOutOfMemory)
@@ -120,11 +139,21 @@ struct HostCtx {
 
 HostCtx g_ctx;
 
-splitk::Schedule g_override = {0, 0, 0, 0}; // ring 0 = automatic
+splitk::Schedule g_override = {0, 0, 0, 0, 0}; // ring 0 = automatic
 
 splitk::Schedule pick_schedule(int32_t N, int64_t S, int32_t Q)
 {
     return g_override.ring ? g_override : splitk::default_schedule(N, S, Q);
+}
+
+// Whether the ordered path (permute + stream) runs for this call.
+bool ordered_for(int32_t T, int32_t N, int32_t max_len)
+{
+    if (!splitk::ordered_path_possible(N, max_len))
+        return false;
+    if (g_override.ring && g_override.path)
+        return g_override.path == 2;
+    return splitk::use_ordered_path(T, N, max_len);
 }
 
 // Event pairs around main-kernel launches while profiling is enabled.
@@ -184,14 +213,16 @@ extern "C" {
 
 const char *split_last_error(void) { return g_err; }
 
-int split_set_schedule(int32_t ring, int32_t first, int32_t every, int32_t waves)
+int split_set_schedule(int32_t ring, int32_t first, int32_t every, int32_t waves, int32_t path)
 {
     g_err[0] = 0;
     if (ring == 0) {
-        g_override = splitk::Schedule{0, 0, 0, 0};
+        g_override = splitk::Schedule{0, 0, 0, 0, 0};
         return SPLIT_OK;
     }
-    const splitk::Schedule s{ring, first, every, waves};
+    const splitk::Schedule s{ring, first, every, waves, path};
+    if (path < 0 || path > 2)
+        return fail(SPLIT_EINVAL, "path must be 0, 1 or 2 (got %d)", path);
     if (waves != 0 && waves != 1 && waves != 2 && waves != 4 && waves != 8)
         return fail(SPLIT_EINVAL, "waves must be 0, 1, 2, 4 or 8 (got %d)", waves);
     if (!splitk::schedule_supported(s))
@@ -203,10 +234,9 @@ int split_set_schedule(int32_t ring, int32_t first, int32_t every, int32_t waves
 
 size_t split_workspace_bytes(int32_t num_tours, int32_t max_len, int32_t N, int64_t S)
 {
-    (void)N;
-    if (num_tours < 1 || max_len < 0 || S < 1)
+    if (num_tours < 1 || max_len < 0 || S < 1 || N < 1)
         return 0;
-    return splitk::workspace_bytes(num_tours, max_len, S);
+    return splitk::workspace_bytes(num_tours, max_len, N, S, ordered_for(num_tours, N, max_len));
 }
 
 int split_eval_device(const int32_t *d_tours, const int32_t *d_lens, int32_t num_tours,
@@ -226,10 +256,11 @@ int split_eval_device(const int32_t *d_tours, const int32_t *d_lens, int32_t num
         return fail(SPLIT_EINVAL, "demands must be 16-byte aligned");
     if (reinterpret_cast<uintptr_t>(d_workspace) % 256)
         return fail(SPLIT_EINVAL, "workspace must be 256-byte aligned");
-    const size_t need = splitk::workspace_bytes(num_tours, max_len, S);
+    const size_t need = splitk::workspace_bytes(num_tours, max_len, N, S, ordered_for(num_tours, N, max_len));
     if (ws_bytes < need)
         return fail(SPLIT_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
-    const splitk::Workspace ws = splitk::carve_workspace(d_workspace, num_tours, max_len, S);
+    const splitk::Workspace ws = splitk::carve_workspace(d_workspace, num_tours, max_len, N, S,
+                                                         ordered_for(num_tours, N, max_len));
     const splitk::Schedule sched = pick_schedule(N, S, Q);
     splitk::LaunchEvents ev;
     bool use_ev = false;
@@ -296,7 +327,7 @@ int split_eval(const int32_t *tours, const int32_t *lens, int32_t num_tours, con
     }
     hipStream_t st = g_ctx.stream;
     const size_t n1sq = ((size_t)N + 1) * ((size_t)N + 1);
-    const size_t ws_bytes = splitk::workspace_bytes(num_tours, max_len, S);
+    const size_t ws_bytes = splitk::workspace_bytes(num_tours, max_len, N, S, ordered_for(num_tours, N, max_len));
     HIP_TRY(ensure(g_ctx.tours, (size_t)total * 4), "alloc tours");
     HIP_TRY(ensure(g_ctx.lens, (size_t)num_tours * 4), "alloc lens");
     HIP_TRY(ensure(g_ctx.dist, n1sq * 4), "alloc dist");
@@ -315,7 +346,8 @@ int split_eval(const int32_t *tours, const int32_t *lens, int32_t num_tours, con
     HIP_TRY(hipMemcpyAsync(g_ctx.demands.p, demands, (size_t)S * N * 2, hipMemcpyHostToDevice, st),
             "copy demands");
     const splitk::Workspace ws =
-        splitk::carve_workspace(g_ctx.ws.p, num_tours, max_len, S);
+        splitk::carve_workspace(g_ctx.ws.p, num_tours, max_len, N, S,
+                                ordered_for(num_tours, N, max_len));
     const splitk::Schedule sched = pick_schedule(N, S, Q);
     HIP_TRY(splitk::launch_eval(static_cast<int32_t *>(g_ctx.tours.p),
                                 static_cast<int32_t *>(g_ctx.lens.p), num_tours, max_len,
@@ -384,7 +416,7 @@ int split_plan_create(split_plan **plan, const int32_t *d_tours, const int32_t *
     if (rc)
         return rc;
     split_plan *p = new split_plan();
-    const size_t bytes = splitk::workspace_bytes(num_tours, max_len, S);
+    const size_t bytes = splitk::workspace_bytes(num_tours, max_len, N, S, ordered_for(num_tours, N, max_len));
     hipError_t e = hipMalloc(&p->ws, bytes);
     if (e != hipSuccess) {
         delete p;

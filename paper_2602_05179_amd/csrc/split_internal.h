@@ -26,6 +26,8 @@ struct Workspace {
     int *list_count;       // [1]
     int *done;             // [1] fallback blocks finished
     int *vscratch;         // [fallback blocks * 64 * (max_len + 1)] value history
+    uint8_t *tile_bad;     // [tiles] ordered path: tile needs the exact fallback (or null)
+    uint8_t *perm;         // [T * S * pitch] ordered path: demands in tour order (or null)
     int max_len;
 };
 
@@ -35,6 +37,7 @@ struct Schedule {
     int first; // cells of the first head group, validated once (0 = pairs)
     int every; // tail cells between exits on an empty EXEC
     int waves; // tours (waves) per workgroup sharing one staged tile; 0 = automatic
+    int path;  // 0 = automatic, 1 = fused (tile staged in LDS), 2 = ordered (permute + stream)
 };
 
 // Optional events bracketing the main kernel launch (measurement only).
@@ -50,8 +53,12 @@ constexpr int kMaxLen = 65535;       // longest tour the library accepts
 constexpr int kLdsLimit = 160 * 1024; // LDS bytes one workgroup may use on gfx950
 
 int64_t num_tiles(int64_t S);
-size_t workspace_bytes(int32_t T, int32_t max_len, int64_t S);
-Workspace carve_workspace(void *base, int32_t T, int32_t max_len, int64_t S);
+size_t workspace_bytes(int32_t T, int32_t max_len, int32_t N, int64_t S, bool ordered);
+Workspace carve_workspace(void *base, int32_t T, int32_t max_len, int32_t N, int64_t S,
+                          bool ordered);
+int waves_per_group(int32_t T, int32_t N);
+bool ordered_path_possible(int32_t N, int32_t max_len);
+bool use_ordered_path(int32_t T, int32_t N, int32_t max_len);
 
 hipError_t launch_eval(const int32_t *tours, const int32_t *lens, int32_t T, int32_t max_len,
                        const int32_t *dist, int32_t N, const int16_t *demands, int64_t S,
@@ -64,6 +71,10 @@ hipError_t launch_count_cells(const int32_t *tours, const int32_t *lens, int32_t
                               hipStream_t stream);
 
 Schedule default_schedule(int32_t N, int64_t S, int32_t Q);
+
+// Thread-local error text returned by split_last_error().
+int set_error(int code, const char *fmt, ...);
+void clear_error();
 bool schedule_supported(const Schedule &s);
 
 } // namespace splitk

@@ -474,6 +474,211 @@ __global__ __launch_bounds__(kWave *kMaxWavesPerGroup) void split_tile_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// ordered path (large customer pools): the demands of each tile are first
+// written in tour order as bytes, perm[t][s][j-1] = q_s(sigma_j), rows
+// padded to `pitch` bytes (a multiple of 32, padding zero); the recursion
+// kernel then streams each lane's own row 32 positions at a time straight
+// into registers, so it needs no LDS and its occupancy is register-bound.
+// ---------------------------------------------------------------------------
+constexpr int kPermThreads = 256;
+
+// grid = tiles; LDS: 64 x N demand bytes + flag word + tour (u16 per position)
+__global__ __launch_bounds__(kPermThreads) void permute_tile_kernel(
+    const int16_t *__restrict__ demands, int32_t N, int64_t S, int32_t T, int32_t pitch,
+    Workspace ws)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    const int64_t k = blockIdx.x;
+    const int64_t s0 = k * kWave;
+    const int rows = (int)min<int64_t>(kWave, S - s0);
+    const size_t rows_bytes = ((size_t)kWave * N + 15) & ~(size_t)15;
+    int &s_bad = *reinterpret_cast<int *>(lds + rows_bytes);
+    uint16_t *cust = reinterpret_cast<uint16_t *>(lds + rows_bytes + 16);
+    const bool ok = stage_tile_u8(demands + s0 * N, lds, (int64_t)rows * N, threadIdx.x,
+                                  blockDim.x, s_bad);
+    if (!ok) {
+        if (threadIdx.x == 0)
+            ws.tile_bad[k] = 1;
+        return; // uniform: every tour's unit of this tile takes the exact fallback
+    }
+    if (threadIdx.x == 0)
+        ws.tile_bad[k] = 0;
+    const int chunks = pitch / 16;
+    for (int t = 0; t < T; ++t) {
+        const TourRec rec = ws.rec[t];
+        const int n = rec.status == ST_OK ? rec.n : 0;
+        const int2 *tab = ws.tab + (int64_t)t * (ws.max_len + 3);
+        __syncthreads();
+        for (int j = threadIdx.x; j < n; j += blockDim.x)
+            cust[j] = (uint16_t)tab[j + 1].x;
+        __syncthreads();
+        uint8_t *dst = ws.perm + ((int64_t)t * S + s0) * pitch;
+        for (int idx = threadIdx.x; idx < rows * chunks; idx += blockDim.x) {
+            const int r = idx / chunks;
+            const int c = idx - r * chunks;
+            const uint8_t *row = lds + (int64_t)r * N;
+            uint32_t w[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint32_t x = 0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int j = c * 16 + q * 4 + b;
+                    const uint32_t v = j < n ? row[cust[j]] : 0u;
+                    x |= v << (8 * b);
+                }
+                w[q] = x;
+            }
+            u32x4 o = {w[0], w[1], w[2], w[3]};
+            __builtin_nontemporal_store(o, reinterpret_cast<u32x4 *>(dst + (int64_t)r * pitch) + c);
+        }
+    }
+}
+
+struct DpRegsO {
+    int L;    // load of positions 1..j
+    int2 tn;  // table entry of the next position {customer, c}
+    int2 tnn; // table entry of the position after next (in flight)
+    int mres; // m of the last position relaxed (m_n after the loop)
+    int ovf;  // 1 when a window reached past the ring
+    u32x4 cur[2], nxt[2]; // demand bytes of the current / next 32 positions
+};
+
+__device__ __forceinline__ int byte_at(const u32x4 (&seg)[2], int b)
+{
+    const u32x4 &v = seg[b >> 4];
+    const int w = (b >> 2) & 3;
+    const uint32_t x = w == 0 ? v.x : w == 1 ? v.y : w == 2 ? v.z : v.w;
+    return (int)((x >> (8 * (b & 3))) & 0xFFu);
+}
+
+// position j = j0 + 1 + U of a block of R positions (j0 a multiple of R)
+template <int R, int FIRST, int EVERY, int U> struct DpStateO {
+    __device__ __forceinline__ static bool run(int (&f)[R], int (&lq)[R], DpRegsO &r,
+                                               const u32x4 *row, int64_t segs, CInt *tab,
+                                               int j0, int n, int Q)
+    {
+        constexpr int SL = (U + 1) & (R - 1);
+        const int j = j0 + 1 + U;
+        if (j > n)
+            return false;
+        const int q = byte_at(r.cur, U & 31);
+        const int cj = r.tn.y;
+        r.tn = r.tnn;
+        r.tnn = tab_at(tab, j + 2);
+        r.L += q;
+        const int m = WindowMin<R, FIRST, EVERY>::template run<SL>(f, lq, r.L, j, r.ovf);
+        r.mres = m;
+        f[SL] = m + cj;
+        lq[SL] = r.L + Q;
+        if ((U & 31) == 31) { // next 32 positions: rotate and prefetch the one after
+            r.cur[0] = r.nxt[0];
+            r.cur[1] = r.nxt[1];
+            const int64_t seg = (j + 32) >> 5; // segment holding positions j+33..j+64
+            if (seg < segs) {
+                r.nxt[0] = __builtin_nontemporal_load(row + 2 * seg);
+                r.nxt[1] = __builtin_nontemporal_load(row + 2 * seg + 1);
+            }
+        }
+        return true;
+    }
+};
+
+template <int R, int FIRST, int EVERY, int... Us>
+__device__ __forceinline__ bool dp_block_o(int (&f)[R], int (&lq)[R], DpRegsO &r, const u32x4 *row,
+                                           int64_t segs, CInt *tab, int j0, int n, int Q,
+                                           std::integer_sequence<int, Us...>)
+{
+    return (DpStateO<R, FIRST, EVERY, Us>::run(f, lq, r, row, segs, tab, j0, n, Q) && ...);
+}
+
+template <int R, int FIRST, int EVERY>
+__device__ __forceinline__ int dp_lane_ordered(const uint8_t *rowb, int pitch, CInt *tab, int n,
+                                               int f0, int Q, bool &ovf)
+{
+    int f[R], lq[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        f[i] = kInf;
+        lq[i] = kNeg;
+    }
+    f[0] = f0;
+    lq[0] = Q;
+    DpRegsO r;
+    r.L = 0;
+    r.mres = kInf;
+    r.ovf = 0;
+    r.tn = tab_at(tab, 1);
+    r.tnn = tab_at(tab, 2);
+    const u32x4 *row = reinterpret_cast<const u32x4 *>(rowb);
+    const int64_t segs = pitch / 32;
+    r.cur[0] = __builtin_nontemporal_load(row);
+    r.cur[1] = __builtin_nontemporal_load(row + 1);
+    if (segs > 1) {
+        r.nxt[0] = __builtin_nontemporal_load(row + 2);
+        r.nxt[1] = __builtin_nontemporal_load(row + 3);
+    } else {
+        r.nxt[0] = r.cur[0];
+        r.nxt[1] = r.cur[1];
+    }
+    for (int j0 = 0; j0 < n; j0 += R) {
+        if (!dp_block_o<R, FIRST, EVERY>(f, lq, r, row, segs, tab, j0, n, Q,
+                                         std::make_integer_sequence<int, R>{}))
+            break;
+    }
+    ovf = r.ovf != 0;
+    return r.mres;
+}
+
+// grid = units (u -> tile u / T, tour u % T), one wave each
+template <int R, int FIRST, int EVERY>
+__global__ __launch_bounds__(kWave) void split_ordered_kernel(int64_t S, int32_t Q, int32_t T,
+                                                              int32_t pitch,
+                                                              int32_t *__restrict__ costs,
+                                                              Workspace ws)
+{
+    const int64_t u = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t k = u / T;
+    const int t = (int)(u - k * T);
+    const int64_t s0 = k * kWave;
+    const int rows = (int)min<int64_t>(kWave, S - s0);
+    const TourRec rec = ws.rec[t];
+    int32_t *out = costs + (int64_t)t * S + s0;
+    if (rec.status != ST_OK || rec.n == 0) {
+        if (lane < rows)
+            out[lane] = rec.status != ST_OK ? SPLIT_INF : 0;
+        return;
+    }
+    bool redo = ws.tile_bad[k] != 0;
+    if (!redo) {
+        CInt *tab = (CInt *)(ws.tab + (int64_t)t * (ws.max_len + 3));
+        bool ovf = false;
+        int v = 0;
+        if (lane < rows) {
+            const uint8_t *rowb = ws.perm + ((int64_t)t * S + s0 + lane) * pitch;
+            const int m = dp_lane_ordered<R, FIRST, EVERY>(rowb, pitch, tab, rec.n, rec.f0, Q, ovf);
+            v = m + rec.bn;
+        }
+        redo = ballot(ovf) != 0;
+        if (!redo) {
+            const bool fin = lane < rows && v < kInf;
+            const bool inf = lane < rows && v >= kInf;
+            if (lane < rows)
+                out[lane] = inf ? SPLIT_INF : v;
+            const long long sm = wave_sum_i64(fin ? (long long)v : 0LL);
+            const int ni = wave_sum_i32(inf ? 1 : 0);
+            if (lane == 0)
+                add_unit_result(ws, T, t, u, sm, ni);
+        }
+    }
+    if (redo && lane == 0) {
+        const int slot = atomicAdd(ws.list_count, 1);
+        ws.list[slot] = (int)u;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // exact fallback for listed units (any window length, any demand value),
 // straight from the definition with the value history in global scratch;
 // the last block to finish folds every tour's slots into its sum and mean
@@ -646,8 +851,40 @@ int64_t num_tiles(int64_t S) { return (S + kTile - 1) / kTile; }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t workspace_bytes(int32_t T, int32_t max_len, int64_t S)
+int32_t ordered_pitch(int32_t max_len) { return ((max_len + 31) / 32) * 32 + 32; }
+
+// Tours per workgroup: enough to keep the shared tile's LDS per wave small.
+int waves_per_group(int32_t T, int32_t N)
 {
+    const int64_t bytes = (int64_t)kTile * N;
+    int W = 1;
+    while (W < kMaxWavesPerGroup && W < T && bytes / W > 8 * 1024)
+        W *= 2;
+    return W < T ? W : T;
+}
+
+// LDS bytes the permute kernel needs: rows + flag + tour (u16 per position)
+static size_t permute_lds_bytes(int32_t N, int32_t max_len)
+{
+    return (((size_t)kTile * (size_t)N + 15) & ~(size_t)15) + 16 + 2 * ((size_t)max_len + 1);
+}
+
+// Ordered path when a fused workgroup would need more than 16 KB of LDS per
+// wave (large pools, few tours), as long as the permute tile fits in LDS.
+bool ordered_path_possible(int32_t N, int32_t max_len)
+{
+    return permute_lds_bytes(N, max_len) <= (size_t)kLdsLimit && N < 65535;
+}
+
+bool use_ordered_path(int32_t T, int32_t N, int32_t max_len)
+{
+    const int W = waves_per_group(T, N);
+    return (int64_t)kTile * N / W > 16 * 1024 && ordered_path_possible(N, max_len);
+}
+
+size_t workspace_bytes(int32_t T, int32_t max_len, int32_t N, int64_t S, bool ordered)
+{
+    (void)N;
     const size_t units = (size_t)T * (size_t)num_tiles(S);
     size_t b = 0;
     b += align256((size_t)T * ((size_t)max_len + 3) * sizeof(int2));
@@ -657,11 +894,17 @@ size_t workspace_bytes(int32_t T, int32_t max_len, int64_t S)
     b += align256(units * sizeof(int));
     b += align256(2 * sizeof(int));
     b += align256((size_t)kFallbackBlocks * kWave * ((size_t)max_len + 1) * sizeof(int));
+    if (ordered) {
+        b += align256((size_t)num_tiles(S));
+        b += align256((size_t)T * (size_t)S * (size_t)ordered_pitch(max_len));
+    }
     return b;
 }
 
-Workspace carve_workspace(void *base, int32_t T, int32_t max_len, int64_t S)
+Workspace carve_workspace(void *base, int32_t T, int32_t max_len, int32_t N, int64_t S,
+                          bool ordered)
 {
+    (void)N;
     const size_t units = (size_t)T * (size_t)num_tiles(S);
     char *p = static_cast<char *>(base);
     Workspace ws;
@@ -679,6 +922,14 @@ Workspace carve_workspace(void *base, int32_t T, int32_t max_len, int64_t S)
     ws.done = ws.list_count + 1;
     p += align256(2 * sizeof(int));
     ws.vscratch = reinterpret_cast<int *>(p);
+    p += align256((size_t)kFallbackBlocks * kWave * ((size_t)max_len + 1) * sizeof(int));
+    ws.tile_bad = nullptr;
+    ws.perm = nullptr;
+    if (ordered) {
+        ws.tile_bad = reinterpret_cast<uint8_t *>(p);
+        p += align256((size_t)num_tiles(S));
+        ws.perm = reinterpret_cast<uint8_t *>(p);
+    }
     ws.max_len = max_len;
     return ws;
 }
@@ -736,16 +987,6 @@ static hipError_t launch_tiles(const int16_t *demands, int32_t N, int64_t S, int
     return hipGetLastError();
 }
 
-// Tours per workgroup: enough to keep the shared tile's LDS per wave small.
-int waves_per_group(int32_t T, int32_t N)
-{
-    const int64_t bytes = (int64_t)kTile * N;
-    int W = 1;
-    while (W < kMaxWavesPerGroup && W < T && bytes / W > 8 * 1024)
-        W *= 2;
-    return W < T ? W : T;
-}
-
 hipError_t launch_eval(const int32_t *tours, const int32_t *lens, int32_t T, int32_t max_len,
                        const int32_t *dist, int32_t N, const int16_t *demands, int64_t S,
                        int32_t Q, int32_t *costs, int64_t *sums, double *means,
@@ -764,12 +1005,38 @@ hipError_t launch_eval(const int32_t *tours, const int32_t *lens, int32_t T, int
         if (e != hipSuccess)
             return e;
     }
+    if (ws.perm) {
+        const size_t plds = permute_lds_bytes(N, max_len);
+        static bool perm_attr = false;
+        if (!perm_attr) {
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&permute_tile_kernel),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, kLdsLimit);
+            if (e != hipSuccess)
+                return e;
+            perm_attr = true;
+        }
+        const int32_t pitch = ordered_pitch(max_len);
+        hipLaunchKernelGGL(permute_tile_kernel, dim3((unsigned)num_tiles(S)), dim3(kPermThreads),
+                           plds, stream, demands, N, S, T, pitch, ws);
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+        const int64_t units = (int64_t)T * num_tiles(S);
+#define SPLIT_LAUNCH_O(R_, F_, E_)                                                               \
+    if (sched.ring == R_ && sched.first == F_ && sched.every == E_)                               \
+        hipLaunchKernelGGL((split_ordered_kernel<R_, F_, E_>), dim3((unsigned)units), dim3(kWave), \
+                           0, stream, S, Q, T, pitch, costs, ws);
+        SPLIT_WINDOW_VARIANTS(SPLIT_LAUNCH_O)
+#undef SPLIT_LAUNCH_O
+        e = hipGetLastError();
+    } else {
 #define SPLIT_LAUNCH(R_, F_, E_)                                                                 \
     if (sched.ring == R_ && sched.first == F_ && sched.every == E_)                               \
         e = launch_tiles<R_, F_, E_>(demands, N, S, Q, T, costs, ws, stream,                \
                                      sched.waves ? sched.waves : waves_per_group(T, N));
-    SPLIT_WINDOW_VARIANTS(SPLIT_LAUNCH)
+        SPLIT_WINDOW_VARIANTS(SPLIT_LAUNCH)
 #undef SPLIT_LAUNCH
+    }
     if (e != hipSuccess)
         return e;
     if (ev && ev->after) {

@@ -85,7 +85,7 @@ def test_paper_scale_full(binding):
 def test_batched_tours_per_workgroup(binding, waves):
     """Tours sharing a staged tile: any grouping gives the oracle's results."""
     inst = W.batched_ragged(12, num_tours=37, S=1500)
-    binding.set_schedule(32, 8, 3, waves)
+    binding.set_schedule(32, 8, 3, waves, 1)
     try:
         _run_both(binding, inst, label="%s waves=%d" % (inst.name, waves))
     finally:
@@ -148,13 +148,36 @@ def _edge_instances():
     return out
 
 
+@pytest.mark.parametrize("path", [1, 2])
 @pytest.mark.parametrize("ring", [32, 64])
 @pytest.mark.parametrize("k", range(len(_edge_instances())))
-def test_edge_cases(binding, k, ring):
+def test_edge_cases(binding, k, ring, path):
     inst = _edge_instances()[k]
-    binding.set_schedule(ring, 8, 3)
+    binding.set_schedule(ring, 8, 3, 0, path)
     try:
-        _run_both(binding, inst, label="%s ring=%d" % (inst.name, ring), host_form=True)
+        _run_both(binding, inst, label="%s ring=%d path=%d" % (inst.name, ring, path), host_form=True)
+    finally:
+        binding.set_schedule(0)
+
+
+@pytest.mark.parametrize("Q", [80, 150, 300])
+@pytest.mark.parametrize("path", [0, 1, 2])
+def test_served_shapes_both_paths(binding, Q, path):
+    """n=1000 requests (the served mix): LDS-staged and tour-ordered paths."""
+    inst = W.plain_normal(20 + Q, 1000, 3000, Q)
+    if path:
+        binding.set_schedule(64 if Q > 200 else 32, 16 if Q > 200 else 8, 3, 0, path)
+    try:
+        _run_both(binding, inst, label="%s path=%d" % (inst.name, path))
+    finally:
+        binding.set_schedule(0)
+
+
+def test_batched_ordered_path(binding):
+    inst = W.batched_ragged(13, num_tours=9, S=700)
+    binding.set_schedule(32, 8, 3, 0, 2)
+    try:
+        _run_both(binding, inst, label=inst.name + " ordered")
     finally:
         binding.set_schedule(0)
 
