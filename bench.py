@@ -114,7 +114,7 @@ def batched_vs_plain(torch, binding, W, reps):
     cells = int(binding.split_count_cells_device(t, l, q, inst.N, inst.Q).sum().item())
     plan = binding.Plan(t, l, d, q, inst.Q, max_len=max_len)
     t_graph = timed_steps(torch, plan.launch, reps, 2)
-    ws = torch.empty(binding.workspace_bytes(T, max_len, inst.N, inst.S), dtype=torch.uint8, device=dev)
+    ws = torch.empty(binding.workspace_bytes(T, max_len, inst.N, inst.S, inst.Q), dtype=torch.uint8, device=dev)
     out = binding.DeviceOutputs(T, inst.S, dev)
     t_eager = timed_steps(torch, lambda: binding.split_eval_device(t, l, d, q, inst.Q, max_len=max_len, out=out,
                                                                    workspace=ws), reps, 2)
@@ -125,7 +125,7 @@ def batched_vs_plain(torch, binding, W, reps):
     for k in range(T):
         n = int(lens[k])
         singles.append((t[offs[k]:offs[k] + n], l[k:k + 1], binding.DeviceOutputs(1, inst.S, dev),
-                        torch.empty(binding.workspace_bytes(1, max(n, 1), inst.N, inst.S), dtype=torch.uint8,
+                        torch.empty(binding.workspace_bytes(1, max(n, 1), inst.N, inst.S, inst.Q), dtype=torch.uint8,
                                     device=dev), max(n, 1)))
 
     def plain():
@@ -148,6 +148,68 @@ def batched_vs_plain(torch, binding, W, reps):
     }
 
 
+def served(torch, binding, W, num_requests, pool_size, budget_gb, seed=5):
+    """Served stream: Poisson arrivals of single-tour requests (n ~ U{50..1000},
+    S ~ 10^U(3,5), Q in {80,150,300}) drawn from a pool of distinct instances
+    resident on the device; continuous batching under an HBM budget."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    gen = W.served_stream(seed=seed, num_requests=pool_size)
+    pool = []
+    for req in gen:
+        inst = req.inst
+        d = torch.from_numpy(np.ascontiguousarray(inst.dist)).to(dev)
+        q = torch.from_numpy(np.ascontiguousarray(inst.demands)).to(dev)
+        t = torch.from_numpy(inst.tours).to(dev)
+        l = torch.from_numpy(inst.lens).to(dev)
+        cells = int(binding.split_count_cells_device(t, l, q, inst.N, inst.Q).sum().item())
+        pool.append((inst, d, q, cells))
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(seed + 1)
+    picks = rng.integers(0, len(pool), size=num_requests)
+    srv = binding.Server(int(budget_gb * (1 << 30)), streams=4)
+
+    def run(rate):
+        """rate None: submit everything at once (saturation)."""
+        gaps = rng.exponential(1.0 / rate, size=num_requests) if rate else np.zeros(num_requests)
+        arrivals = np.cumsum(gaps)
+        live, lat, cells = {}, [], 0
+        t0 = time.perf_counter()
+        k = 0
+        while k < num_requests or live:
+            now = time.perf_counter() - t0
+            while k < num_requests and arrivals[k] <= now:
+                inst, d, q, c = pool[picks[k]]
+                live[srv.submit(inst.tours, d, q, inst.Q)] = c
+                k += 1
+            done = []
+            for rid in list(live):
+                r = srv.poll(rid)
+                if r is not None:
+                    lat.append(r["latency_s"])
+                    cells += live[rid]
+                    done.append(rid)
+            for rid in done:
+                del live[rid]
+            if not done and k < num_requests and arrivals[k] > now:
+                time.sleep(min(2e-4, arrivals[k] - now))
+        wall = time.perf_counter() - t0
+        lat = np.array(lat) * 1e3
+        return dict(requests=num_requests, wall_s=wall, req_per_s=num_requests / wall,
+                    cells_per_s=cells / wall, p50_ms=float(np.percentile(lat, 50)),
+                    p99_ms=float(np.percentile(lat, 99)), mean_ms=float(lat.mean()))
+
+    sat = run(None)
+    out = {"workload": "%d requests from %d resident instances: n~U{50..1000}, S~10^U(3,5), "
+                       "Q in {80,150,300}, Normal(mu,0.3mu) demands" % (num_requests, len(pool)),
+           "budget_gb": budget_gb, "streams": 4, "saturated": sat}
+    for frac in (0.5, 0.8):
+        out["load_%.1f" % frac] = run(frac * sat["req_per_s"])
+    out["peak_bytes"] = srv.stats()["peak_bytes"]
+    srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +219,10 @@ def main():
     ap.add_argument("--scenarios", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=10_000)
+    ap.add_argument("--served-pool", type=int, default=32)
+    ap.add_argument("--budget-gb", type=float, default=32.0)
     ap.add_argument("--calibration-copy", action="store_true",
                     help="also run a plain device copy of the demand tensor (HBM counter scale)")
     args = ap.parse_args()
@@ -178,7 +244,7 @@ def main():
     d = torch.from_numpy(dist).to(dev)
     q = torch.from_numpy(dem).to(dev)
     T, N, S, n = inst.num_tours, inst.N, inst.S, int(lens.max())
-    ws = torch.empty(binding.workspace_bytes(T, n, N, S), dtype=torch.uint8, device=dev)
+    ws = torch.empty(binding.workspace_bytes(T, n, N, S, inst.Q), dtype=torch.uint8, device=dev)
     out = binding.DeviceOutputs(T, S, dev)
     cells = int(binding.split_count_cells_device(t, l, q, N, inst.Q).sum().item())
     torch.cuda.synchronize()
@@ -252,6 +318,9 @@ def main():
     if not args.no_batched:
         log("batched vs plain (256 ragged tours, S=10^4)")
         result["batched"] = batched_vs_plain(torch, binding, W, reps=20)
+    if not args.no_served:
+        log("served stream (%d requests)" % args.served_requests)
+        result["served"] = served(torch, binding, W, args.served_requests, args.served_pool, args.budget_gb)
     if not args.no_cpu_baseline:
         log("CPU oracle baseline on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(inst)

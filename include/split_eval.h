@@ -85,9 +85,11 @@ int split_eval(const int32_t *tours, const int32_t *lens, int32_t num_tours, con
                int64_t *sums, double *means);
 
 /*
- * Device-memory workspace needed by split_eval_device for these sizes.
+ * Device-memory workspace needed by split_eval_device for these sizes under
+ * the schedule the library would pick now (override, tuned entry or
+ * default).  Ask again after tuning or changing the schedule.
  */
-size_t split_workspace_bytes(int32_t num_tours, int32_t max_len, int32_t N, int64_t S);
+size_t split_workspace_bytes(int32_t num_tours, int32_t max_len, int32_t N, int64_t S, int32_t Q);
 
 /*
  * split_eval_device -- same operation on DEVICE pointers, enqueued on
@@ -142,6 +144,32 @@ int split_count_cells_device(const int32_t *d_tours, const int32_t *d_lens, int3
  * against concurrent evaluations.
  */
 int split_set_schedule(int32_t ring, int32_t first, int32_t every, int32_t waves, int32_t path);
+
+/*
+ * Autotuning.  split_tune_device times every compiled schedule (ring length,
+ * head/tail structure, tours per workgroup, fused or ordered path) on the
+ * given device inputs, `reps` timed launches each after two warm-ups, on
+ * `stream` (synchronising it), and records the fastest for the call's shape
+ * bucket (tour count, length, pool size, scenario count and capacity, each
+ * bucketed logarithmically); later calls in the bucket use it unless
+ * split_set_schedule overrides.  Every candidate is parity-gated: its costs
+ * and sums must equal the automatic schedule's bit for bit, else
+ * SPLIT_EDEVICE is returned and nothing is recorded.  It allocates its own
+ * device buffers.  best_ms (may be NULL) receives the winner's time per
+ * evaluation.  split_tune_lookup reports the recorded schedule as
+ * {ring, first, every, waves, path} (SPLIT_EAGAIN if none);
+ * split_tune_save / split_tune_load write / read the table as text;
+ * split_tune_clear forgets it.
+ */
+int split_tune_device(const int32_t *d_tours, const int32_t *d_lens, int32_t num_tours,
+                      int32_t max_len, const int32_t *d_dist, int32_t N,
+                      const int16_t *d_demands, int64_t S, int32_t Q, int32_t reps,
+                      split_stream_t stream, double *best_ms);
+int split_tune_lookup(int32_t num_tours, int32_t max_len, int32_t N, int64_t S, int32_t Q,
+                      int32_t sched[5]);
+int split_tune_save(const char *path);
+int split_tune_load(const char *path);
+int split_tune_clear(void);
 
 /*
  * Measurement.  While enabled, every launch of the main evaluation kernel

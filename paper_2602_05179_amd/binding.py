@@ -40,6 +40,11 @@ EXPORTED = (
     "split_server_wait",
     "split_server_stats",
     "split_server_destroy",
+    "split_tune_device",
+    "split_tune_lookup",
+    "split_tune_save",
+    "split_tune_load",
+    "split_tune_clear",
 )
 
 
@@ -65,7 +70,7 @@ def _load():
     lib.split_eval.restype = ctypes.c_int
     lib.split_eval.argtypes = [P, P, i32, P, i32, P, i64, i32, P, P, P]
     lib.split_workspace_bytes.restype = sz
-    lib.split_workspace_bytes.argtypes = [i32, i32, i32, i64]
+    lib.split_workspace_bytes.argtypes = [i32, i32, i32, i64, i32]
     lib.split_eval_device.restype = ctypes.c_int
     lib.split_eval_device.argtypes = [P, P, i32, i32, P, i32, P, i64, i32, P, P, P, P, sz, P]
     lib.split_count_cells_device.restype = ctypes.c_int
@@ -96,6 +101,16 @@ def _load():
                                        ctypes.POINTER(sz), ctypes.POINTER(sz)]
     lib.split_server_destroy.restype = ctypes.c_int
     lib.split_server_destroy.argtypes = [P]
+    lib.split_tune_device.restype = ctypes.c_int
+    lib.split_tune_device.argtypes = [P, P, i32, i32, P, i32, P, i64, i32, i32, P, ctypes.POINTER(ctypes.c_double)]
+    lib.split_tune_lookup.restype = ctypes.c_int
+    lib.split_tune_lookup.argtypes = [i32, i32, i32, i64, i32, ctypes.POINTER(i32)]
+    lib.split_tune_save.restype = ctypes.c_int
+    lib.split_tune_save.argtypes = [ctypes.c_char_p]
+    lib.split_tune_load.restype = ctypes.c_int
+    lib.split_tune_load.argtypes = [ctypes.c_char_p]
+    lib.split_tune_clear.restype = ctypes.c_int
+    lib.split_tune_clear.argtypes = []
     return lib
 
 
@@ -183,8 +198,8 @@ def _stream_handle(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def workspace_bytes(num_tours: int, max_len: int, N: int, S: int) -> int:
-    return int(lib.split_workspace_bytes(int(num_tours), int(max_len), int(N), int(S)))
+def workspace_bytes(num_tours: int, max_len: int, N: int, S: int, Q: int) -> int:
+    return int(lib.split_workspace_bytes(int(num_tours), int(max_len), int(N), int(S), int(Q)))
 
 
 class DeviceOutputs:
@@ -213,7 +228,7 @@ def split_eval_device(tours, lens, dist, demands, Q, *, max_len=None, out=None, 
         max_len = int(lens.max().item()) if T else 0
     if out is None:
         out = DeviceOutputs(T, S, demands.device)
-    need = workspace_bytes(T, max_len, N, S)
+    need = workspace_bytes(T, max_len, N, S, Q)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=demands.device)
     _check(lib.split_eval_device(_dptr(tours), _dptr(lens), T, int(max_len), _dptr(dist), N, _dptr(demands), S,
@@ -232,6 +247,41 @@ def split_count_cells_device(tours, lens, demands, N, Q, *, stream=None):
     _check(lib.split_count_cells_device(_dptr(tours), _dptr(lens), T, int(N), _dptr(demands), S, int(Q),
                                         _dptr(cells), _stream_handle(stream)))
     return cells
+
+
+def tune_device(tours, lens, dist, demands, Q, *, max_len=None, reps=5, stream=None) -> float:
+    """Time every compiled schedule on these device inputs (parity-gated) and
+    record the fastest for their shape bucket; returns its ms per evaluation."""
+    T = int(lens.numel())
+    if max_len is None:
+        max_len = int(lens.max().item()) if T else 0
+    best = ctypes.c_double()
+    _check(lib.split_tune_device(_dptr(tours), _dptr(lens), T, int(max_len), _dptr(dist), int(dist.shape[0] - 1),
+                                 _dptr(demands), int(demands.shape[0]), int(Q), int(reps), _stream_handle(stream),
+                                 ctypes.byref(best)))
+    return best.value
+
+
+def tune_lookup(num_tours, max_len, N, S, Q):
+    """Recorded (ring, first, every, waves, path) for the shape, or None."""
+    out = (ctypes.c_int32 * 5)()
+    rc = lib.split_tune_lookup(int(num_tours), int(max_len), int(N), int(S), int(Q), out)
+    if rc == SPLIT_EAGAIN:
+        return None
+    _check(rc)
+    return tuple(int(x) for x in out)
+
+
+def tune_save(path):
+    _check(lib.split_tune_save(str(path).encode()))
+
+
+def tune_load(path):
+    _check(lib.split_tune_load(str(path).encode()))
+
+
+def tune_clear():
+    _check(lib.split_tune_clear())
 
 
 class Plan:

@@ -141,21 +141,6 @@ HostCtx g_ctx;
 
 splitk::Schedule g_override = {0, 0, 0, 0, 0}; // ring 0 = automatic
 
-splitk::Schedule pick_schedule(int32_t N, int64_t S, int32_t Q)
-{
-    return g_override.ring ? g_override : splitk::default_schedule(N, S, Q);
-}
-
-// Whether the ordered path (permute + stream) runs for this call.
-bool ordered_for(int32_t T, int32_t N, int32_t max_len)
-{
-    if (!splitk::ordered_path_possible(N, max_len))
-        return false;
-    if (g_override.ring && g_override.path)
-        return g_override.path == 2;
-    return splitk::use_ordered_path(T, N, max_len);
-}
-
 // Event pairs around main-kernel launches while profiling is enabled.
 struct Profiler {
     std::mutex mu;
@@ -209,6 +194,27 @@ hipError_t ensure(HostCtx::Buf &b, size_t bytes)
 
 } // namespace
 
+namespace splitk {
+
+// Schedule for a call: an explicit override, else the tuned entry for the
+// shape bucket, else the built-in default; `ordered` tells which path runs.
+Schedule choose_schedule(int32_t T, int32_t max_len, int32_t N, int64_t S, int32_t Q,
+                         bool *ordered)
+{
+    Schedule s;
+    if (g_override.ring)
+        s = g_override;
+    else if (!tuned_schedule(tune_key(T, max_len, N, S, Q), &s))
+        s = default_schedule(N, S, Q);
+    bool ord = s.path ? s.path == 2 : use_ordered_path(T, N, max_len);
+    if (!ordered_path_possible(N, max_len))
+        ord = false;
+    *ordered = ord;
+    return s;
+}
+
+} // namespace splitk
+
 extern "C" {
 
 const char *split_last_error(void) { return g_err; }
@@ -232,11 +238,13 @@ int split_set_schedule(int32_t ring, int32_t first, int32_t every, int32_t waves
     return SPLIT_OK;
 }
 
-size_t split_workspace_bytes(int32_t num_tours, int32_t max_len, int32_t N, int64_t S)
+size_t split_workspace_bytes(int32_t num_tours, int32_t max_len, int32_t N, int64_t S, int32_t Q)
 {
     if (num_tours < 1 || max_len < 0 || S < 1 || N < 1)
         return 0;
-    return splitk::workspace_bytes(num_tours, max_len, N, S, ordered_for(num_tours, N, max_len));
+    bool ordered = false;
+    (void)splitk::choose_schedule(num_tours, max_len, N, S, Q, &ordered);
+    return splitk::workspace_bytes(num_tours, max_len, N, S, ordered);
 }
 
 int split_eval_device(const int32_t *d_tours, const int32_t *d_lens, int32_t num_tours,
@@ -256,12 +264,13 @@ int split_eval_device(const int32_t *d_tours, const int32_t *d_lens, int32_t num
         return fail(SPLIT_EINVAL, "demands must be 16-byte aligned");
     if (reinterpret_cast<uintptr_t>(d_workspace) % 256)
         return fail(SPLIT_EINVAL, "workspace must be 256-byte aligned");
-    const size_t need = splitk::workspace_bytes(num_tours, max_len, N, S, ordered_for(num_tours, N, max_len));
+    bool ordered = false;
+    const splitk::Schedule sched = splitk::choose_schedule(num_tours, max_len, N, S, Q, &ordered);
+    const size_t need = splitk::workspace_bytes(num_tours, max_len, N, S, ordered);
     if (ws_bytes < need)
         return fail(SPLIT_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
-    const splitk::Workspace ws = splitk::carve_workspace(d_workspace, num_tours, max_len, N, S,
-                                                         ordered_for(num_tours, N, max_len));
-    const splitk::Schedule sched = pick_schedule(N, S, Q);
+    const splitk::Workspace ws =
+        splitk::carve_workspace(d_workspace, num_tours, max_len, N, S, ordered);
     splitk::LaunchEvents ev;
     bool use_ev = false;
     HIP_TRY(profile_events(&ev, &use_ev), "profile events");
@@ -327,7 +336,9 @@ int split_eval(const int32_t *tours, const int32_t *lens, int32_t num_tours, con
     }
     hipStream_t st = g_ctx.stream;
     const size_t n1sq = ((size_t)N + 1) * ((size_t)N + 1);
-    const size_t ws_bytes = splitk::workspace_bytes(num_tours, max_len, N, S, ordered_for(num_tours, N, max_len));
+    bool ordered = false;
+    const splitk::Schedule sched = splitk::choose_schedule(num_tours, max_len, N, S, Q, &ordered);
+    const size_t ws_bytes = splitk::workspace_bytes(num_tours, max_len, N, S, ordered);
     HIP_TRY(ensure(g_ctx.tours, (size_t)total * 4), "alloc tours");
     HIP_TRY(ensure(g_ctx.lens, (size_t)num_tours * 4), "alloc lens");
     HIP_TRY(ensure(g_ctx.dist, n1sq * 4), "alloc dist");
@@ -346,9 +357,7 @@ int split_eval(const int32_t *tours, const int32_t *lens, int32_t num_tours, con
     HIP_TRY(hipMemcpyAsync(g_ctx.demands.p, demands, (size_t)S * N * 2, hipMemcpyHostToDevice, st),
             "copy demands");
     const splitk::Workspace ws =
-        splitk::carve_workspace(g_ctx.ws.p, num_tours, max_len, N, S,
-                                ordered_for(num_tours, N, max_len));
-    const splitk::Schedule sched = pick_schedule(N, S, Q);
+        splitk::carve_workspace(g_ctx.ws.p, num_tours, max_len, N, S, ordered);
     HIP_TRY(splitk::launch_eval(static_cast<int32_t *>(g_ctx.tours.p),
                                 static_cast<int32_t *>(g_ctx.lens.p), num_tours, max_len,
                                 static_cast<int32_t *>(g_ctx.dist.p), N,
@@ -416,7 +425,7 @@ int split_plan_create(split_plan **plan, const int32_t *d_tours, const int32_t *
     if (rc)
         return rc;
     split_plan *p = new split_plan();
-    const size_t bytes = splitk::workspace_bytes(num_tours, max_len, N, S, ordered_for(num_tours, N, max_len));
+    const size_t bytes = split_workspace_bytes(num_tours, max_len, N, S, Q);
     hipError_t e = hipMalloc(&p->ws, bytes);
     if (e != hipSuccess) {
         delete p;

@@ -72,9 +72,28 @@ hipError_t launch_count_cells(const int32_t *tours, const int32_t *lens, int32_t
 
 Schedule default_schedule(int32_t N, int64_t S, int32_t Q);
 
+// Schedule for a call (override > tuned entry > default) and its path.
+Schedule choose_schedule(int32_t T, int32_t max_len, int32_t N, int64_t S, int32_t Q,
+                         bool *ordered);
+
 // Thread-local error text returned by split_last_error().
 int set_error(int code, const char *fmt, ...);
 void clear_error();
 bool schedule_supported(const Schedule &s);
+
+hipError_t launch_count_mismatch(const int32_t *a, const int32_t *b, int64_t n, int64_t *out,
+                                 hipStream_t stream);
+
+// Every compiled (ring, first, every) triple, in a fixed order.
+int compiled_schedules(Schedule *out, int cap);
+
+// Shape bucket used by the tuning table.
+struct TuneKey {
+    int tours, len, pool, scen, cap;
+    bool operator<(const TuneKey &o) const;
+};
+TuneKey tune_key(int32_t T, int32_t max_len, int32_t N, int64_t S, int32_t Q);
+// Tuned schedule for this shape if one was recorded (split_tune_device / load).
+bool tuned_schedule(const TuneKey &k, Schedule *out);
 
 } // namespace splitk

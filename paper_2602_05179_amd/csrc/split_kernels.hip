@@ -838,6 +838,21 @@ __global__ __launch_bounds__(kWave) void count_cells_kernel(const int32_t *__res
 }
 
 // ---------------------------------------------------------------------------
+// tuner support: number of positions where two int32 arrays differ
+// ---------------------------------------------------------------------------
+__global__ void count_mismatch_kernel(const int32_t *__restrict__ a, const int32_t *__restrict__ b,
+                                      int64_t n, unsigned long long *__restrict__ out)
+{
+    long long c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        c += a[i] != b[i];
+    c = wave_sum_i64(c);
+    if ((threadIdx.x & (kWave - 1)) == 0 && c)
+        atomicAdd(out, (unsigned long long)c);
+}
+
+// ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
 __global__ void zero_i64_kernel(int64_t *p, int32_t n)
@@ -943,7 +958,20 @@ Schedule default_schedule(int32_t N, int64_t S, int32_t Q)
     s.first = Q > 200 ? 16 : 8;
     s.every = 3;
     s.waves = 0;
+    s.path = 0;
     return s;
+}
+
+int compiled_schedules(Schedule *out, int cap)
+{
+    int n = 0;
+#define SPLIT_LIST(R_, F_, E_)                                                                   \
+    if (n < cap)                                                                                 \
+        out[n] = Schedule{R_, F_, E_, 0, 0};                                                     \
+    ++n;
+    SPLIT_WINDOW_VARIANTS(SPLIT_LIST)
+#undef SPLIT_LIST
+    return n;
 }
 
 bool schedule_supported(const Schedule &s)
@@ -1046,6 +1074,19 @@ hipError_t launch_eval(const int32_t *tours, const int32_t *lens, int32_t T, int
     }
     hipLaunchKernelGGL(fallback_final_kernel, dim3(kFallbackBlocks), dim3(kWave), 0, stream,
                        demands, N, S, Q, T, costs, sums, means, ws);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_mismatch(const int32_t *a, const int32_t *b, int64_t n, int64_t *out,
+                                 hipStream_t stream)
+{
+    hipLaunchKernelGGL(zero_i64_kernel, dim3(1), dim3(64), 0, stream, out, 1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    const int64_t blocks = n / (256 * 16) + 1 < 2048 ? n / (256 * 16) + 1 : 2048;
+    hipLaunchKernelGGL(count_mismatch_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, a, b,
+                       n, reinterpret_cast<unsigned long long *>(out));
     return hipGetLastError();
 }
 

@@ -174,7 +174,10 @@ struct split_server {
             return SPLIT_EDEVICE;
         const splitk::Workspace ws =
             splitk::carve_workspace(base + ws_off, 1, n, r->N, r->S, r->ordered);
-        const splitk::Schedule sched = splitk::default_schedule(r->N, r->S, r->Q);
+        bool ordered = false;
+        splitk::Schedule sched = splitk::choose_schedule(1, n, r->N, r->S, r->Q, &ordered);
+        if (ordered != r->ordered) // the footprint was sized for r->ordered
+            sched = splitk::default_schedule(r->N, r->S, r->Q);
         e = splitk::launch_eval(d_in + 1, d_in, 1, n, r->d_dist, r->N, r->d_demands, r->S, r->Q,
                                 d_costs, d_sum, d_mean, ws, st, sched);
         if (e != hipSuccess)
@@ -315,7 +318,7 @@ int split_server_submit(split_server *s, const int32_t *tour, int32_t n, const i
     r->S = S;
     r->Q = Q;
     r->costs_out = costs_out;
-    r->ordered = splitk::use_ordered_path(1, N, n);
+    (void)splitk::choose_schedule(1, n, N, S, Q, &r->ordered);
     size_t a, b, c;
     r->bytes = split_server::footprint(*r, &a, &b, &c);
     if (r->bytes > s->arena.capacity()) {

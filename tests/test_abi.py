@@ -37,11 +37,40 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_workspace_size_is_positive_and_monotone():
-    a = binding.workspace_bytes(1, 200, 200, 1_000_000)
-    b = binding.workspace_bytes(2, 200, 200, 1_000_000)
-    c = binding.workspace_bytes(1, 400, 200, 1_000_000)
+    a = binding.workspace_bytes(1, 200, 200, 1_000_000, 150)
+    b = binding.workspace_bytes(2, 200, 200, 1_000_000, 150)
+    c = binding.workspace_bytes(1, 400, 200, 1_000_000, 150)
     assert 0 < a < b and a < c
-    assert binding.workspace_bytes(0, 10, 10, 10) == 0
+    assert binding.workspace_bytes(0, 10, 10, 10, 5) == 0
+    # a large pool with one tour takes the ordered path: room for the tour-ordered copy
+    big = binding.workspace_bytes(1, 1000, 1000, 100_000, 150)
+    assert big >= 100_000 * 1000
+
+
+def test_tuning_table_save_load_roundtrip(tmp_path):
+    binding.tune_clear()
+    assert binding.tune_lookup(1, 200, 200, 1_000_000, 150) is None
+    f = tmp_path / "tune.txt"
+    # a table written by hand in the documented text format
+    from paper_2602_05179_amd import binding as b
+    import ctypes
+    key = (0, 7, 7, 9, 7)  # one tour, n~200, N~200, S~1e6, Q~150
+    f.write_text("# tours len pool scen cap -> ring first every waves path\n"
+                 "%d %d %d %d %d 32 8 2 1 1\n" % key)
+    b.tune_load(f)
+    assert b.tune_lookup(1, 200, 200, 1_000_000, 150) == (32, 8, 2, 1, 1)
+    g = tmp_path / "tune2.txt"
+    b.tune_save(g)
+    b.tune_clear()
+    assert b.tune_lookup(1, 200, 200, 1_000_000, 150) is None
+    b.tune_load(g)
+    assert b.tune_lookup(1, 200, 200, 1_000_000, 150) == (32, 8, 2, 1, 1)
+    b.tune_clear()
+    bad = tmp_path / "bad.txt"
+    bad.write_text("0 7 7 9 7 33 8 2 1 1\n")
+    with pytest.raises(b.SplitError):
+        b.tune_load(bad)
+    del ctypes
 
 
 def _small():

@@ -291,3 +291,18 @@ def test_repeated_runs_are_bit_identical(binding):
     a = _device_eval(binding, tours, lens, dist, dem, inst.Q)
     b = _device_eval(binding, tours, lens, dist, dem, inst.Q)
     _assert_same(a, b, "repeat")
+
+
+def test_tuner_records_a_parity_gated_schedule(binding):
+    binding.tune_clear()
+    for inst in (W.plain_paper_scale(14, S=30_000), W.batched_ragged(15, num_tours=20, S=2000)):
+        tours, lens, dist, dem = W.as_arrays(inst)
+        t, l, d, q = _to_dev(tours, lens, dist, dem)
+        ms = binding.tune_device(t, l, d, q, inst.Q, reps=2)
+        assert ms > 0
+        rec = binding.tune_lookup(inst.num_tours, int(lens.max()), inst.N, inst.S, inst.Q)
+        assert rec is not None and rec[4] in (1, 2)
+        _say("tuned %s -> %s (%.3f ms)" % (inst.name, rec, ms))
+        # the next evaluation in this bucket runs the tuned schedule
+        _run_both(binding, inst, label=inst.name + " tuned")
+    binding.tune_clear()
