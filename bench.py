@@ -227,7 +227,7 @@ def main():
                     help="also run a plain device copy of the demand tensor (HBM counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build evaluates on one GPU; --gpus %d is not supported (use --gpus 1)" % args.gpus,
+        print("bench.py: the evaluator runs on one GPU; --gpus %d is not supported (use --gpus 1)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
