@@ -133,17 +133,28 @@ int split_count_cells_device(const int32_t *d_tours, const int32_t *d_lens, int3
  * split_set_schedule -- schedule override for every later call in the
  * process (the tuner uses it).  ring = 32 or 64 is the register-ring length
  * of the main kernel (longer windows are recomputed by the exact fallback,
- * so results never depend on it); first = cells of the first head group
- * validated with a single check (0 = pairs only); every = tail cells
- * between exits on an empty lane mask; waves = tours per workgroup that
- * share one staged scenario tile (1, 2, 4 or 8; 0 = automatic); path =
+ * so results never depend on it); first = cells of the first head group,
+ * validated with one check issued a position early; group = cells of each
+ * later head group, validated with one check each (0 = none); every = tail
+ * cells between exits on an empty lane mask; waves = tours per workgroup
+ * that share one staged scenario tile (1, 2, 4 or 8; 0 = automatic); path =
  * 1 stages whole scenario rows in LDS and gathers through the tour, 2 first
  * rewrites the demands in tour order and streams them (0 = automatic, by
  * the LDS each wave would need).  ring = 0 restores the automatic choice.
- * split_workspace_bytes accounts for the override in force when called.  Unsupported triples return SPLIT_EINVAL.  Not thread-safe
- * against concurrent evaluations.
+ * split_workspace_bytes accounts for the override in force when called.
+ * A (ring, first, group, every) window variant that is not compiled in
+ * returns SPLIT_EINVAL.  Not thread-safe against concurrent evaluations.
  */
-int split_set_schedule(int32_t ring, int32_t first, int32_t every, int32_t waves, int32_t path);
+int split_set_schedule(int32_t ring, int32_t first, int32_t group, int32_t every, int32_t waves,
+                       int32_t path);
+
+/*
+ * split_list_variants -- the compiled window variants, for split_set_schedule.
+ * Writes up to `cap` entries of 4 int32 {ring, first, group, every} to
+ * `out` (host memory, caller-owned, 4*cap words; may be NULL when cap = 0)
+ * and returns the total number compiled in (which may exceed cap).
+ */
+int split_list_variants(int32_t *out, int32_t cap);
 
 /*
  * Autotuning.  split_tune_device times every compiled schedule (ring length,
@@ -157,7 +168,7 @@ int split_set_schedule(int32_t ring, int32_t first, int32_t every, int32_t waves
  * SPLIT_EDEVICE is returned and nothing is recorded.  It allocates its own
  * device buffers.  best_ms (may be NULL) receives the winner's time per
  * evaluation.  split_tune_lookup reports the recorded schedule as
- * {ring, first, every, waves, path} (SPLIT_EAGAIN if none);
+ * {ring, first, group, every, waves, path} (SPLIT_EAGAIN if none);
  * split_tune_save / split_tune_load write / read the table as text;
  * split_tune_clear forgets it.
  */
@@ -166,7 +177,7 @@ int split_tune_device(const int32_t *d_tours, const int32_t *d_lens, int32_t num
                       const int16_t *d_demands, int64_t S, int32_t Q, int32_t reps,
                       split_stream_t stream, double *best_ms);
 int split_tune_lookup(int32_t num_tours, int32_t max_len, int32_t N, int64_t S, int32_t Q,
-                      int32_t sched[5]);
+                      int32_t sched[6]);
 int split_tune_save(const char *path);
 int split_tune_load(const char *path);
 int split_tune_clear(void);

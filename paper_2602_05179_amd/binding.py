@@ -32,6 +32,7 @@ EXPORTED = (
     "split_plan_launch",
     "split_plan_destroy",
     "split_set_schedule",
+    "split_list_variants",
     "split_profile_enable",
     "split_profile_read",
     "split_server_create",
@@ -82,7 +83,9 @@ def _load():
     lib.split_plan_destroy.restype = ctypes.c_int
     lib.split_plan_destroy.argtypes = [P]
     lib.split_set_schedule.restype = ctypes.c_int
-    lib.split_set_schedule.argtypes = [i32, i32, i32, i32, i32]
+    lib.split_set_schedule.argtypes = [i32, i32, i32, i32, i32, i32]
+    lib.split_list_variants.restype = ctypes.c_int
+    lib.split_list_variants.argtypes = [ctypes.POINTER(i32), i32]
     lib.split_profile_enable.restype = ctypes.c_int
     lib.split_profile_enable.argtypes = [i32]
     lib.split_profile_read.restype = ctypes.c_int
@@ -126,16 +129,25 @@ def _check(rc: int):
         raise SplitError(rc, last_error())
 
 
-SCHEDULES = [(32, 0, 1), (32, 8, 2), (32, 8, 3), (32, 6, 3), (32, 4, 3), (32, 8, 4),
-             (64, 0, 1), (64, 8, 3), (64, 16, 3), (64, 24, 3)]
+def list_variants():
+    """Compiled window variants as (ring, first, group, every) tuples."""
+    n = lib.split_list_variants(None, 0)
+    buf = (ctypes.c_int32 * (4 * n))()
+    lib.split_list_variants(buf, n)
+    return [tuple(int(buf[4 * i + k]) for k in range(4)) for i in range(n)]
+
+
+SCHEDULES = list_variants()
 
 
 PATH_AUTO, PATH_FUSED, PATH_ORDERED = 0, 1, 2
 
 
-def set_schedule(ring: int, first: int = 8, every: int = 3, waves: int = 0, path: int = 0):
+def set_schedule(ring: int, first: int = 8, group: int = 0, every: int = 4, waves: int = 0,
+                 path: int = 0):
     """Force the main-kernel schedule; ring=0 restores the automatic choice."""
-    _check(lib.split_set_schedule(int(ring), int(first), int(every), int(waves), int(path)))
+    _check(lib.split_set_schedule(int(ring), int(first), int(group), int(every), int(waves),
+                                  int(path)))
 
 
 def profile_enable(on: bool = True):
@@ -263,8 +275,8 @@ def tune_device(tours, lens, dist, demands, Q, *, max_len=None, reps=5, stream=N
 
 
 def tune_lookup(num_tours, max_len, N, S, Q):
-    """Recorded (ring, first, every, waves, path) for the shape, or None."""
-    out = (ctypes.c_int32 * 5)()
+    """Recorded (ring, first, group, every, waves, path) for the shape, or None."""
+    out = (ctypes.c_int32 * 6)()
     rc = lib.split_tune_lookup(int(num_tours), int(max_len), int(N), int(S), int(Q), out)
     if rc == SPLIT_EAGAIN:
         return None

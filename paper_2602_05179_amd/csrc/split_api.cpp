@@ -219,23 +219,40 @@ extern "C" {
 
 const char *split_last_error(void) { return g_err; }
 
-int split_set_schedule(int32_t ring, int32_t first, int32_t every, int32_t waves, int32_t path)
+int split_set_schedule(int32_t ring, int32_t first, int32_t group, int32_t every, int32_t waves,
+                       int32_t path)
 {
     g_err[0] = 0;
     if (ring == 0) {
-        g_override = splitk::Schedule{0, 0, 0, 0, 0};
+        g_override = splitk::Schedule{0, 0, 0, 0, 0, 0};
         return SPLIT_OK;
     }
-    const splitk::Schedule s{ring, first, every, waves, path};
+    const splitk::Schedule s{ring, first, group, every, waves, path};
     if (path < 0 || path > 2)
         return fail(SPLIT_EINVAL, "path must be 0, 1 or 2 (got %d)", path);
     if (waves != 0 && waves != 1 && waves != 2 && waves != 4 && waves != 8)
         return fail(SPLIT_EINVAL, "waves must be 0, 1, 2, 4 or 8 (got %d)", waves);
     if (!splitk::schedule_supported(s))
-        return fail(SPLIT_EINVAL, "unsupported schedule ring=%d first=%d every=%d", ring, first,
-                    every);
+        return fail(SPLIT_EINVAL, "unsupported window variant ring=%d first=%d group=%d every=%d",
+                    ring, first, group, every);
     g_override = s;
     return SPLIT_OK;
+}
+
+int split_list_variants(int32_t *out, int32_t cap)
+{
+    g_err[0] = 0;
+    if (cap < 0 || (cap > 0 && !out))
+        return fail(SPLIT_EINVAL, "bad output buffer");
+    splitk::Schedule v[64];
+    const int n = splitk::compiled_schedules(v, 64);
+    for (int i = 0; i < n && i < cap && i < 64; ++i) {
+        out[4 * i] = v[i].ring;
+        out[4 * i + 1] = v[i].first;
+        out[4 * i + 2] = v[i].group;
+        out[4 * i + 3] = v[i].every;
+    }
+    return n;
 }
 
 size_t split_workspace_bytes(int32_t num_tours, int32_t max_len, int32_t N, int64_t S, int32_t Q)

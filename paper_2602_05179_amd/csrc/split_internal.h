@@ -18,7 +18,7 @@ struct TourRec {
 
 // Device scratch carved from one caller- or library-owned allocation.
 struct Workspace {
-    int2 *tab;             // [T * (max_len + 3)] {customer index, c_j}, padded
+    int2 *tab;             // [T * (max_len + kTabPad)] {customer index, c_j}, padded
     int2 *ab;              // [T * max_len] {a_j, b_j} (exact fallback)
     TourRec *rec;          // [T]
     long long *slots;      // [T * slots_per_tour(T) * kSlotStride] per-tour {sum, #inf}
@@ -31,10 +31,11 @@ struct Workspace {
     int max_len;
 };
 
-// How the main kernel runs (one instantiation per supported triple).
+// How the main kernel runs (one instantiation per compiled window variant).
 struct Schedule {
     int ring;  // register ring length R (32 or 64)
-    int first; // cells of the first head group, validated once (0 = pairs)
+    int first; // cells of the first head group (its check is issued one position early)
+    int group; // cells of each later head group (0 = none)
     int every; // tail cells between exits on an empty EXEC
     int waves; // tours (waves) per workgroup sharing one staged tile; 0 = automatic
     int path;  // 0 = automatic, 1 = fused (tile staged in LDS), 2 = ordered (permute + stream)
@@ -47,6 +48,7 @@ struct LaunchEvents {
 };
 
 constexpr int kTile = 64;            // scenarios per unit (one wave)
+constexpr int kTabPad = 4;           // table entries besides positions 1..n: index 0, n+1..n+3
 constexpr int kSlots = 64;           // partial-sum slots of a single tour (fewer when T > 1)
 constexpr int kSlotStride = 16;      // int64 words between slots (128 bytes)
 constexpr int kMaxLen = 65535;       // longest tour the library accepts
@@ -84,7 +86,7 @@ bool schedule_supported(const Schedule &s);
 hipError_t launch_count_mismatch(const int32_t *a, const int32_t *b, int64_t n, int64_t *out,
                                  hipStream_t stream);
 
-// Every compiled (ring, first, every) triple, in a fixed order.
+// Every compiled (ring, first, group, every) window variant, in a fixed order.
 int compiled_schedules(Schedule *out, int cap);
 
 // Shape bucket used by the tuning table.

@@ -108,8 +108,8 @@ __device__ __forceinline__ void add_unit_result(const Workspace &ws, int T, int 
 // ---------------------------------------------------------------------------
 // prep: per-tour table, validation, accumulator reset
 // grid = num_tours blocks of 256 threads
-// tab[t * (max_len + 3) + j] = {customer index of position j, c_j} for
-// j = 1..n, zero at j = 0 and for the padding entries n+1, n+2.
+// tab[t * (max_len + kTabPad) + j] = {customer index of position j, c_j} for
+// j = 1..n, zero at j = 0 and for the padding entries n+1..n+3.
 // ---------------------------------------------------------------------------
 constexpr int kPrepThreads = 256;
 
@@ -168,9 +168,9 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(
         s_carry = 0;
     __syncthreads();
 
-    int2 *tab = ws.tab + (int64_t)t * (max_len + 3);
+    int2 *tab = ws.tab + (int64_t)t * (max_len + kTabPad);
     int2 *ab = ws.ab + (int64_t)t * max_len;
-    for (int i = tid; i < 3; i += kPrepThreads)
+    for (int i = tid; i < kTabPad; i += kPrepThreads)
         tab[i == 0 ? 0 : nn + i] = make_int2(0, 0);
     int first_out = 0;
     for (int base = 0; base < nn; base += kPrepThreads) {
@@ -322,54 +322,62 @@ __device__ __forceinline__ bool stage_tile_u8(const int16_t *__restrict__ src, u
 // One DpState<...>::run advances every lane of the wave by one tour
 // position j (j = R*block + U); ring slot (j - d) mod R = (U - d) mod R holds
 // predecessor p = j - d, so every slot is a compile-time register.  Loads
-// are software-pipelined: the demand of j+1 and the table entry of j+2 are
-// in flight while position j is relaxed.
+// run one position ahead: while position j is relaxed the demand of j+2 and
+// the table entry of j+3 are in flight, and the demand of j+1 has arrived,
+// so the load L_{j+1} is known and the next position's first head check is
+// issued inside this position's window block.
 // ---------------------------------------------------------------------------
 #include "window_min_asm.inc"
 
 struct DpRegs {
-    int L;    // load of positions 1..j
-    int qn;   // demand of the next position (in flight)
-    int2 tn;  // table entry of the next position {customer, c}
-    int2 tnn; // table entry of the position after next (in flight)
-    int mres; // m of the last position relaxed (m_n after the loop)
-    int ovf;  // 1 when a window reached past the ring
+    int L;       // load of positions 1..j (at the start of position j)
+    int qa;      // demand of position j+1 (arrived)
+    int2 t0;     // table entry of position j {customer, c}
+    int2 t1;     // table entry of position j+1
+    int2 t2;     // table entry of position j+2 (in flight)
+    uint64_t cp; // lanes rejecting d = F at position j (computed at j-1)
+    int mres;    // m of the last position relaxed (m_n after the loop)
+    int ovf;     // 1 when a window reached past the ring
 };
 
-template <int R, int FIRST, int EVERY, int U> struct DpState {
+template <int R, int F, int G, int E, int U> struct DpState {
     __device__ __forceinline__ static bool run(int (&f)[R], int (&lq)[R], DpRegs &r,
                                                const uint8_t *row, CInt *tab, int j0, int n,
                                                int Q)
     {
         const int j = j0 + U;
-        if (j == 0)
+        if (U == 0 && j == 0)
             return true;
         if (j > n)
             return false;
-        const int q = r.qn;
-        const int cj = r.tn.y;
-        r.tn = r.tnn;
-        r.qn = row[r.tn.x];
-        r.tnn = tab_at(tab, j + 2);
-        r.L += q;
-        const int m = WindowMin<R, FIRST, EVERY>::template run<U>(f, lq, r.L, j, r.ovf);
+        const int cj = r.t0.y;
+        const int Ln = r.L + r.qa;
+        r.qa = row[r.t2.x];
+        const int2 t3 = tab_at(tab, j + 3);
+        uint64_t cn;
+        const int m = WindowMin<R, F, G, E>::template run<U>(f, lq, r.L, Ln, j, r.cp, cn, r.ovf);
         r.mres = m; // the last position relaxed is j = n
         f[U] = m + cj;
         lq[U] = r.L + Q;
+        r.L = Ln;
+        r.cp = cn;
+        r.t0 = r.t1;
+        r.t1 = r.t2;
+        r.t2 = t3;
         return true;
     }
 };
 
-template <int R, int FIRST, int EVERY, int... Us>
+template <int R, int F, int G, int E, int... Us>
 __device__ __forceinline__ bool dp_block(int (&f)[R], int (&lq)[R], DpRegs &r, const uint8_t *row,
                                          CInt *tab, int j0, int n, int Q,
                                          std::integer_sequence<int, Us...>)
 {
-    return (DpState<R, FIRST, EVERY, Us>::run(f, lq, r, row, tab, j0, n, Q) && ...);
+    return (DpState<R, F, G, E, Us>::run(f, lq, r, row, tab, j0, n, Q) && ...);
 }
 
 // Returns m_n of the lane's scenario; sets ovf when a window left the ring.
-template <int R, int FIRST, int EVERY>
+template <int R, int F, int G, int E>
 __device__ __forceinline__ int dp_lane(const uint8_t *row, CInt *tab, int n, int f0, int Q,
                                        bool &ovf)
 {
@@ -382,15 +390,17 @@ __device__ __forceinline__ int dp_lane(const uint8_t *row, CInt *tab, int n, int
     f[0] = f0; // p = 0: V(0) + a_1
     lq[0] = Q; // L_0 + Q
     DpRegs r;
-    r.L = 0;
     r.mres = kInf;
     r.ovf = 0;
-    r.tn = tab_at(tab, 1);
-    r.qn = row[r.tn.x];
-    r.tnn = tab_at(tab, 2);
+    r.cp = ~0ull; // position 1 starts in the tail
+    r.t0 = tab_at(tab, 1);
+    r.t1 = tab_at(tab, 2);
+    r.t2 = tab_at(tab, 3);
+    r.L = row[r.t0.x];
+    r.qa = row[r.t1.x];
     for (int j0 = 0; j0 <= n; j0 += R) {
-        if (!dp_block<R, FIRST, EVERY>(f, lq, r, row, tab, j0, n, Q,
-                                       std::make_integer_sequence<int, R>{}))
+        if (!dp_block<R, F, G, E>(f, lq, r, row, tab, j0, n, Q,
+                                  std::make_integer_sequence<int, R>{}))
             break;
     }
     ovf = r.ovf != 0;
@@ -401,7 +411,7 @@ __device__ __forceinline__ int dp_lane(const uint8_t *row, CInt *tab, int n, int
 // main evaluation kernel: a workgroup of W waves stages one tile of 64
 // scenario rows and runs W different tours over it (wave w takes tour
 // g*W + w), so tours sharing a scenario set share one LDS copy of it.
-// Workgroup b -> tile k = b / G, tour group g = b % G with G = ceil(T/W):
+// Workgroup b -> tile k = b / NG, tour group g = b % NG with NG = ceil(T/W):
 // all tours of a tile run close together in time, so a shared demand tile
 // is read from HBM about once per XCD.  The (tile, tour) unit id used by
 // the fallback list is u = k*T + t.
@@ -409,17 +419,17 @@ __device__ __forceinline__ int dp_lane(const uint8_t *row, CInt *tab, int n, int
 // ---------------------------------------------------------------------------
 constexpr int kMaxWavesPerGroup = 8;
 
-template <int R, int FIRST, int EVERY>
+template <int R, int F, int G, int E>
 __global__ __launch_bounds__(kWave *kMaxWavesPerGroup) void split_tile_kernel(
     const int16_t *__restrict__ demands, int32_t N, int64_t S, int32_t Q, int32_t T,
     int32_t *__restrict__ costs, Workspace ws, int32_t use_lds)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     const int W = blockDim.x / kWave;
-    const int G = (T + W - 1) / W;
+    const int NG = (T + W - 1) / W;
     const int64_t b = blockIdx.x;
-    const int64_t k = b / G;
-    const int g = (int)(b - k * G);
+    const int64_t k = b / NG;
+    const int g = (int)(b - k * NG);
     const int lane = threadIdx.x & (kWave - 1);
     // uniform within the wave; readfirstlane lets the compiler keep the
     // tour's scalars (length, table pointer) in SGPRs
@@ -447,11 +457,11 @@ __global__ __launch_bounds__(kWave *kMaxWavesPerGroup) void split_tile_kernel(
     }
     bool redo = true;
     if (ok) {
-        CInt *tab = (CInt *)(ws.tab + (int64_t)t * (ws.max_len + 3));
+        CInt *tab = (CInt *)(ws.tab + (int64_t)t * (ws.max_len + kTabPad));
         bool ovf = false;
         int v = 0;
         if (lane < rows) {
-            const int m = dp_lane<R, FIRST, EVERY>(lds + (int64_t)lane * N, tab, rec.n, rec.f0,
+            const int m = dp_lane<R, F, G, E>(lds + (int64_t)lane * N, tab, rec.n, rec.f0,
                                                    Q, ovf);
             v = m + rec.bn;
         }
@@ -507,7 +517,7 @@ __global__ __launch_bounds__(kPermThreads) void permute_tile_kernel(
     for (int t = 0; t < T; ++t) {
         const TourRec rec = ws.rec[t];
         const int n = rec.status == ST_OK ? rec.n : 0;
-        const int2 *tab = ws.tab + (int64_t)t * (ws.max_len + 3);
+        const int2 *tab = ws.tab + (int64_t)t * (ws.max_len + kTabPad);
         __syncthreads();
         for (int j = threadIdx.x; j < n; j += blockDim.x)
             cust[j] = (uint16_t)tab[j + 1].x;
@@ -536,11 +546,12 @@ __global__ __launch_bounds__(kPermThreads) void permute_tile_kernel(
 }
 
 struct DpRegsO {
-    int L;    // load of positions 1..j
-    int2 tn;  // table entry of the next position {customer, c}
-    int2 tnn; // table entry of the position after next (in flight)
-    int mres; // m of the last position relaxed (m_n after the loop)
-    int ovf;  // 1 when a window reached past the ring
+    int L;       // load of positions 1..j (at the start of position j)
+    int2 t0;     // table entry of position j {customer, c}
+    int2 t1;     // table entry of position j+1 (in flight)
+    uint64_t cp; // lanes rejecting d = F at position j (computed at j-1)
+    int mres;    // m of the last position relaxed (m_n after the loop)
+    int ovf;     // 1 when a window reached past the ring
     u32x4 cur[2], nxt[2]; // demand bytes of the current / next 32 positions
 };
 
@@ -553,25 +564,30 @@ __device__ __forceinline__ int byte_at(const u32x4 (&seg)[2], int b)
 }
 
 // position j = j0 + 1 + U of a block of R positions (j0 a multiple of R)
-template <int R, int FIRST, int EVERY, int U> struct DpStateO {
+template <int R, int F, int G, int E, int U> struct DpStateO {
     __device__ __forceinline__ static bool run(int (&f)[R], int (&lq)[R], DpRegsO &r,
                                                const u32x4 *row, int64_t segs, CInt *tab,
                                                int j0, int n, int Q)
     {
         constexpr int SL = (U + 1) & (R - 1);
+        constexpr int B = U & 31; // byte of position j in the current segment
         const int j = j0 + 1 + U;
         if (j > n)
             return false;
-        const int q = byte_at(r.cur, U & 31);
-        const int cj = r.tn.y;
-        r.tn = r.tnn;
-        r.tnn = tab_at(tab, j + 2);
-        r.L += q;
-        const int m = WindowMin<R, FIRST, EVERY>::template run<SL>(f, lq, r.L, j, r.ovf);
+        const int qn = B == 31 ? byte_at(r.nxt, 0) : byte_at(r.cur, B + 1);
+        const int cj = r.t0.y;
+        const int Ln = r.L + qn;
+        r.t0 = r.t1;
+        r.t1 = tab_at(tab, j + 2);
+        uint64_t cn;
+        const int m =
+            WindowMin<R, F, G, E>::template run<SL>(f, lq, r.L, Ln, j, r.cp, cn, r.ovf);
         r.mres = m;
         f[SL] = m + cj;
         lq[SL] = r.L + Q;
-        if ((U & 31) == 31) { // next 32 positions: rotate and prefetch the one after
+        r.L = Ln;
+        r.cp = cn;
+        if (B == 31) { // next 32 positions: rotate and prefetch the one after
             r.cur[0] = r.nxt[0];
             r.cur[1] = r.nxt[1];
             const int64_t seg = (j + 32) >> 5; // segment holding positions j+33..j+64
@@ -584,15 +600,15 @@ template <int R, int FIRST, int EVERY, int U> struct DpStateO {
     }
 };
 
-template <int R, int FIRST, int EVERY, int... Us>
+template <int R, int F, int G, int E, int... Us>
 __device__ __forceinline__ bool dp_block_o(int (&f)[R], int (&lq)[R], DpRegsO &r, const u32x4 *row,
                                            int64_t segs, CInt *tab, int j0, int n, int Q,
                                            std::integer_sequence<int, Us...>)
 {
-    return (DpStateO<R, FIRST, EVERY, Us>::run(f, lq, r, row, segs, tab, j0, n, Q) && ...);
+    return (DpStateO<R, F, G, E, Us>::run(f, lq, r, row, segs, tab, j0, n, Q) && ...);
 }
 
-template <int R, int FIRST, int EVERY>
+template <int R, int F, int G, int E>
 __device__ __forceinline__ int dp_lane_ordered(const uint8_t *rowb, int pitch, CInt *tab, int n,
                                                int f0, int Q, bool &ovf)
 {
@@ -605,11 +621,11 @@ __device__ __forceinline__ int dp_lane_ordered(const uint8_t *rowb, int pitch, C
     f[0] = f0;
     lq[0] = Q;
     DpRegsO r;
-    r.L = 0;
     r.mres = kInf;
     r.ovf = 0;
-    r.tn = tab_at(tab, 1);
-    r.tnn = tab_at(tab, 2);
+    r.cp = ~0ull; // position 1 starts in the tail
+    r.t0 = tab_at(tab, 1);
+    r.t1 = tab_at(tab, 2);
     const u32x4 *row = reinterpret_cast<const u32x4 *>(rowb);
     const int64_t segs = pitch / 32;
     r.cur[0] = __builtin_nontemporal_load(row);
@@ -621,9 +637,10 @@ __device__ __forceinline__ int dp_lane_ordered(const uint8_t *rowb, int pitch, C
         r.nxt[0] = r.cur[0];
         r.nxt[1] = r.cur[1];
     }
+    r.L = byte_at(r.cur, 0);
     for (int j0 = 0; j0 < n; j0 += R) {
-        if (!dp_block_o<R, FIRST, EVERY>(f, lq, r, row, segs, tab, j0, n, Q,
-                                         std::make_integer_sequence<int, R>{}))
+        if (!dp_block_o<R, F, G, E>(f, lq, r, row, segs, tab, j0, n, Q,
+                                    std::make_integer_sequence<int, R>{}))
             break;
     }
     ovf = r.ovf != 0;
@@ -631,7 +648,7 @@ __device__ __forceinline__ int dp_lane_ordered(const uint8_t *rowb, int pitch, C
 }
 
 // grid = units (u -> tile u / T, tour u % T), one wave each
-template <int R, int FIRST, int EVERY>
+template <int R, int F, int G, int E>
 __global__ __launch_bounds__(kWave) void split_ordered_kernel(int64_t S, int32_t Q, int32_t T,
                                                               int32_t pitch,
                                                               int32_t *__restrict__ costs,
@@ -652,12 +669,12 @@ __global__ __launch_bounds__(kWave) void split_ordered_kernel(int64_t S, int32_t
     }
     bool redo = ws.tile_bad[k] != 0;
     if (!redo) {
-        CInt *tab = (CInt *)(ws.tab + (int64_t)t * (ws.max_len + 3));
+        CInt *tab = (CInt *)(ws.tab + (int64_t)t * (ws.max_len + kTabPad));
         bool ovf = false;
         int v = 0;
         if (lane < rows) {
             const uint8_t *rowb = ws.perm + ((int64_t)t * S + s0 + lane) * pitch;
-            const int m = dp_lane_ordered<R, FIRST, EVERY>(rowb, pitch, tab, rec.n, rec.f0, Q, ovf);
+            const int m = dp_lane_ordered<R, F, G, E>(rowb, pitch, tab, rec.n, rec.f0, Q, ovf);
             v = m + rec.bn;
         }
         redo = ballot(ovf) != 0;
@@ -701,7 +718,7 @@ __global__ __launch_bounds__(kWave) void fallback_final_kernel(const int16_t *__
         const int64_t s0 = k * kWave;
         const int rows = (int)min<int64_t>(kWave, S - s0);
         const TourRec rec = ws.rec[t];
-        const int2 *tab = ws.tab + (int64_t)t * (ws.max_len + 3);
+        const int2 *tab = ws.tab + (int64_t)t * (ws.max_len + kTabPad);
         const int2 *ab = ws.ab + (int64_t)t * ws.max_len;
         const int n = rec.n;
         int v = 0;
@@ -902,7 +919,7 @@ size_t workspace_bytes(int32_t T, int32_t max_len, int32_t N, int64_t S, bool or
     (void)N;
     const size_t units = (size_t)T * (size_t)num_tiles(S);
     size_t b = 0;
-    b += align256((size_t)T * ((size_t)max_len + 3) * sizeof(int2));
+    b += align256((size_t)T * ((size_t)max_len + kTabPad) * sizeof(int2));
     b += align256((size_t)T * max_len * sizeof(int2));
     b += align256((size_t)T * sizeof(TourRec));
     b += align256((size_t)T * slots_per_tour(T) * kSlotStride * sizeof(long long));
@@ -924,7 +941,7 @@ Workspace carve_workspace(void *base, int32_t T, int32_t max_len, int32_t N, int
     char *p = static_cast<char *>(base);
     Workspace ws;
     ws.tab = reinterpret_cast<int2 *>(p);
-    p += align256((size_t)T * ((size_t)max_len + 3) * sizeof(int2));
+    p += align256((size_t)T * ((size_t)max_len + kTabPad) * sizeof(int2));
     ws.ab = reinterpret_cast<int2 *>(p);
     p += align256((size_t)T * max_len * sizeof(int2));
     ws.rec = reinterpret_cast<TourRec *>(p);
@@ -955,8 +972,9 @@ Schedule default_schedule(int32_t N, int64_t S, int32_t Q)
     (void)S;
     Schedule s;
     s.ring = Q > 200 ? 64 : 32;
-    s.first = Q > 200 ? 16 : 8;
-    s.every = 3;
+    s.first = Q > 200 ? 16 : Q <= 100 ? 6 : 8;
+    s.group = 0;
+    s.every = Q > 200 ? 6 : 4;
     s.waves = 0;
     s.path = 0;
     return s;
@@ -965,9 +983,9 @@ Schedule default_schedule(int32_t N, int64_t S, int32_t Q)
 int compiled_schedules(Schedule *out, int cap)
 {
     int n = 0;
-#define SPLIT_LIST(R_, F_, E_)                                                                   \
+#define SPLIT_LIST(R_, F_, G_, E_)                                                               \
     if (n < cap)                                                                                 \
-        out[n] = Schedule{R_, F_, E_, 0, 0};                                                     \
+        out[n] = Schedule{R_, F_, G_, E_, 0, 0};                                                 \
     ++n;
     SPLIT_WINDOW_VARIANTS(SPLIT_LIST)
 #undef SPLIT_LIST
@@ -976,20 +994,20 @@ int compiled_schedules(Schedule *out, int cap)
 
 bool schedule_supported(const Schedule &s)
 {
-#define SPLIT_SUPPORTED(R_, F_, E_)                                                              \
-    if (s.ring == R_ && s.first == F_ && s.every == E_)                                          \
+#define SPLIT_SUPPORTED(R_, F_, G_, E_)                                                          \
+    if (s.ring == R_ && s.first == F_ && s.group == G_ && s.every == E_)                         \
         return true;
     SPLIT_WINDOW_VARIANTS(SPLIT_SUPPORTED)
 #undef SPLIT_SUPPORTED
     return false;
 }
 
-template <int R, int FIRST, int EVERY>
+template <int R, int F, int G, int E>
 static hipError_t launch_tiles(const int16_t *demands, int32_t N, int64_t S, int32_t Q, int32_t T,
                                int32_t *costs, const Workspace &ws, hipStream_t stream, int W)
 {
-    const int G = (T + W - 1) / W;
-    const int64_t groups = (int64_t)G * num_tiles(S);
+    const int NG = (T + W - 1) / W;
+    const int64_t groups = (int64_t)NG * num_tiles(S);
     const size_t lds = (((size_t)kTile * (size_t)N + 15) & ~(size_t)15) + 16; // rows + flag
     static int lds_limit = -1;
     if (lds_limit < 0) {
@@ -1001,7 +1019,7 @@ static hipError_t launch_tiles(const int16_t *demands, int32_t N, int64_t S, int
             return e;
         lim = lim < kLdsLimit ? lim : kLdsLimit;
         e = hipFuncSetAttribute(
-            reinterpret_cast<const void *>(&split_tile_kernel<R, FIRST, EVERY>),
+            reinterpret_cast<const void *>(&split_tile_kernel<R, F, G, E>),
             hipFuncAttributeMaxDynamicSharedMemorySize, lim);
         if (e != hipSuccess)
             return e;
@@ -1009,7 +1027,7 @@ static hipError_t launch_tiles(const int16_t *demands, int32_t N, int64_t S, int
     }
     const int use_lds = lds <= (size_t)lds_limit ? 1 : 0;
     const size_t lds_bytes = use_lds ? lds : 0;
-    hipLaunchKernelGGL((split_tile_kernel<R, FIRST, EVERY>), dim3((unsigned)groups),
+    hipLaunchKernelGGL((split_tile_kernel<R, F, G, E>), dim3((unsigned)groups),
                        dim3(kWave * W), lds_bytes, stream, demands, N, S, Q, T, costs, ws,
                        use_lds);
     return hipGetLastError();
@@ -1050,18 +1068,18 @@ hipError_t launch_eval(const int32_t *tours, const int32_t *lens, int32_t T, int
         if (e != hipSuccess)
             return e;
         const int64_t units = (int64_t)T * num_tiles(S);
-#define SPLIT_LAUNCH_O(R_, F_, E_)                                                               \
-    if (sched.ring == R_ && sched.first == F_ && sched.every == E_)                               \
-        hipLaunchKernelGGL((split_ordered_kernel<R_, F_, E_>), dim3((unsigned)units), dim3(kWave), \
-                           0, stream, S, Q, T, pitch, costs, ws);
+#define SPLIT_LAUNCH_O(R_, F_, G_, E_)                                                           \
+    if (sched.ring == R_ && sched.first == F_ && sched.group == G_ && sched.every == E_)          \
+        hipLaunchKernelGGL((split_ordered_kernel<R_, F_, G_, E_>), dim3((unsigned)units),          \
+                           dim3(kWave), 0, stream, S, Q, T, pitch, costs, ws);
         SPLIT_WINDOW_VARIANTS(SPLIT_LAUNCH_O)
 #undef SPLIT_LAUNCH_O
         e = hipGetLastError();
     } else {
-#define SPLIT_LAUNCH(R_, F_, E_)                                                                 \
-    if (sched.ring == R_ && sched.first == F_ && sched.every == E_)                               \
-        e = launch_tiles<R_, F_, E_>(demands, N, S, Q, T, costs, ws, stream,                \
-                                     sched.waves ? sched.waves : waves_per_group(T, N));
+#define SPLIT_LAUNCH(R_, F_, G_, E_)                                                             \
+    if (sched.ring == R_ && sched.first == F_ && sched.group == G_ && sched.every == E_)          \
+        e = launch_tiles<R_, F_, G_, E_>(demands, N, S, Q, T, costs, ws, stream,                  \
+                                         sched.waves ? sched.waves : waves_per_group(T, N));
         SPLIT_WINDOW_VARIANTS(SPLIT_LAUNCH)
 #undef SPLIT_LAUNCH
     }

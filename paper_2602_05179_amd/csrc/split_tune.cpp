@@ -93,7 +93,7 @@ int split_tune_device(const int32_t *d_tours, const int32_t *d_lens, int32_t num
         return set_error(SPLIT_EINVAL, "demands must be 16-byte aligned");
     hipStream_t st = static_cast<hipStream_t>(stream);
 
-    // candidates: every compiled triple x path x tours per workgroup
+    // candidates: every compiled window variant x path x tours per workgroup
     Schedule triples[64];
     const int nt = compiled_schedules(triples, 64);
     std::vector<Schedule> cand;
@@ -183,9 +183,9 @@ int split_tune_device(const int32_t *d_tours, const int32_t *d_lens, int32_t num
                 (void)hipMemcpy(&mismatch, d_mis, 8, hipMemcpyDeviceToHost);
                 if (mismatch != 0 || hsum != hsum_ref) {
                     rc = set_error(SPLIT_EDEVICE,
-                                   "schedule ring=%d first=%d every=%d waves=%d path=%d differs "
-                                   "from the reference in %lld costs",
-                                   s.ring, s.first, s.every, s.waves, s.path,
+                                   "schedule ring=%d first=%d group=%d every=%d waves=%d path=%d "
+                                   "differs from the reference in %lld costs",
+                                   s.ring, s.first, s.group, s.every, s.waves, s.path,
                                    (long long)mismatch);
                     goto done;
                 }
@@ -219,7 +219,7 @@ done:
 }
 
 int split_tune_lookup(int32_t num_tours, int32_t max_len, int32_t N, int64_t S, int32_t Q,
-                      int32_t sched[5])
+                      int32_t sched[6])
 {
     splitk::clear_error();
     if (!sched)
@@ -229,9 +229,10 @@ int split_tune_lookup(int32_t num_tours, int32_t max_len, int32_t N, int64_t S, 
         return SPLIT_EAGAIN;
     sched[0] = s.ring;
     sched[1] = s.first;
-    sched[2] = s.every;
-    sched[3] = s.waves;
-    sched[4] = s.path;
+    sched[2] = s.group;
+    sched[3] = s.every;
+    sched[4] = s.waves;
+    sched[5] = s.path;
     return SPLIT_OK;
 }
 
@@ -242,11 +243,11 @@ int split_tune_save(const char *path)
     if (!f)
         return splitk::set_error(SPLIT_EINVAL, "cannot open %s", path ? path : "(null)");
     std::lock_guard<std::mutex> lk(splitk::g_tune_mu);
-    fprintf(f, "# tours len pool scen cap -> ring first every waves path\n");
+    fprintf(f, "# tours len pool scen cap -> ring first group every waves path\n");
     for (const auto &kv : splitk::g_table)
-        fprintf(f, "%d %d %d %d %d %d %d %d %d %d\n", kv.first.tours, kv.first.len, kv.first.pool,
-                kv.first.scen, kv.first.cap, kv.second.ring, kv.second.first, kv.second.every,
-                kv.second.waves, kv.second.path);
+        fprintf(f, "%d %d %d %d %d %d %d %d %d %d %d\n", kv.first.tours, kv.first.len,
+                kv.first.pool, kv.first.scen, kv.first.cap, kv.second.ring, kv.second.first,
+                kv.second.group, kv.second.every, kv.second.waves, kv.second.path);
     fclose(f);
     return SPLIT_OK;
 }
@@ -265,8 +266,8 @@ int split_tune_load(const char *path)
             continue;
         splitk::TuneKey k;
         splitk::Schedule s;
-        if (sscanf(line, "%d %d %d %d %d %d %d %d %d %d", &k.tours, &k.len, &k.pool, &k.scen,
-                   &k.cap, &s.ring, &s.first, &s.every, &s.waves, &s.path) == 10 &&
+        if (sscanf(line, "%d %d %d %d %d %d %d %d %d %d %d", &k.tours, &k.len, &k.pool, &k.scen,
+                   &k.cap, &s.ring, &s.first, &s.group, &s.every, &s.waves, &s.path) == 11 &&
             splitk::schedule_supported(s) && s.path >= 1 && s.path <= 2 && s.waves >= 0 &&
             s.waves <= 8) {
             splitk::g_table[k] = s;

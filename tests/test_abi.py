@@ -55,19 +55,19 @@ def test_tuning_table_save_load_roundtrip(tmp_path):
     from paper_2602_05179_amd import binding as b
     import ctypes
     key = (0, 7, 7, 9, 7)  # one tour, n~200, N~200, S~1e6, Q~150
-    f.write_text("# tours len pool scen cap -> ring first every waves path\n"
-                 "%d %d %d %d %d 32 8 2 1 1\n" % key)
+    f.write_text("# tours len pool scen cap -> ring first group every waves path\n"
+                 "%d %d %d %d %d 32 8 2 3 1 1\n" % key)
     b.tune_load(f)
-    assert b.tune_lookup(1, 200, 200, 1_000_000, 150) == (32, 8, 2, 1, 1)
+    assert b.tune_lookup(1, 200, 200, 1_000_000, 150) == (32, 8, 2, 3, 1, 1)
     g = tmp_path / "tune2.txt"
     b.tune_save(g)
     b.tune_clear()
     assert b.tune_lookup(1, 200, 200, 1_000_000, 150) is None
     b.tune_load(g)
-    assert b.tune_lookup(1, 200, 200, 1_000_000, 150) == (32, 8, 2, 1, 1)
+    assert b.tune_lookup(1, 200, 200, 1_000_000, 150) == (32, 8, 2, 3, 1, 1)
     b.tune_clear()
     bad = tmp_path / "bad.txt"
-    bad.write_text("0 7 7 9 7 33 8 2 1 1\n")
+    bad.write_text("0 7 7 9 7 33 8 2 3 1 1\n")
     with pytest.raises(b.SplitError):
         b.tune_load(bad)
     del ctypes
@@ -124,3 +124,24 @@ def test_shape_mismatch_is_rejected_in_the_binding():
     tours, lens, dist, dem, Q = _small()
     with pytest.raises(binding.SplitError):
         binding.split_eval(tours, lens, dist, np.zeros((4, 3), np.int16), Q)
+
+
+def test_window_variants_listed_and_validated():
+    """The compiled variants are listed; set_schedule accepts exactly those."""
+    vs = binding.list_variants()
+    assert vs and all(len(v) == 4 for v in vs)
+    assert {v[0] for v in vs} == {32, 64}
+    for ring, first, group, every in vs:
+        assert 2 <= first < ring and group >= 0 and every >= 1
+    try:
+        for v in vs:
+            binding.set_schedule(*v, waves=0, path=1)
+        bad = (32, 9, 0, 4) if (32, 9, 0, 4) not in vs else (32, 31, 31, 31)
+        with pytest.raises(binding.SplitError):
+            binding.set_schedule(*bad)
+        with pytest.raises(binding.SplitError):
+            binding.set_schedule(*vs[0], waves=3)
+        with pytest.raises(binding.SplitError):
+            binding.set_schedule(*vs[0], path=3)
+    finally:
+        binding.set_schedule(0)

@@ -85,7 +85,7 @@ def test_paper_scale_full(binding):
 def test_batched_tours_per_workgroup(binding, waves):
     """Tours sharing a staged tile: any grouping gives the oracle's results."""
     inst = W.batched_ragged(12, num_tours=37, S=1500)
-    binding.set_schedule(32, 8, 3, waves, 1)
+    binding.set_schedule(32, 8, 0, 4, waves, 1)
     try:
         _run_both(binding, inst, label="%s waves=%d" % (inst.name, waves))
     finally:
@@ -148,14 +148,19 @@ def _edge_instances():
     return out
 
 
+# one variant without and one with later head groups, per ring length
+_EDGE_VARIANTS = [(32, 8, 0, 4), (32, 8, 2, 3), (64, 16, 0, 4), (64, 8, 4, 4)]
+
+
 @pytest.mark.parametrize("path", [1, 2])
-@pytest.mark.parametrize("ring", [32, 64])
+@pytest.mark.parametrize("variant", _EDGE_VARIANTS)
 @pytest.mark.parametrize("k", range(len(_edge_instances())))
-def test_edge_cases(binding, k, ring, path):
+def test_edge_cases(binding, k, variant, path):
     inst = _edge_instances()[k]
-    binding.set_schedule(ring, 8, 3, 0, path)
+    binding.set_schedule(*variant, waves=0, path=path)
     try:
-        _run_both(binding, inst, label="%s ring=%d path=%d" % (inst.name, ring, path), host_form=True)
+        _run_both(binding, inst, label="%s variant=%s path=%d" % (inst.name, variant, path),
+                  host_form=True)
     finally:
         binding.set_schedule(0)
 
@@ -166,7 +171,7 @@ def test_served_shapes_both_paths(binding, Q, path):
     """n=1000 requests (the served mix): LDS-staged and tour-ordered paths."""
     inst = W.plain_normal(20 + Q, 1000, 3000, Q)
     if path:
-        binding.set_schedule(64 if Q > 200 else 32, 16 if Q > 200 else 8, 3, 0, path)
+        binding.set_schedule(64 if Q > 200 else 32, 16 if Q > 200 else 8, 0, 4, 0, path)
     try:
         _run_both(binding, inst, label="%s path=%d" % (inst.name, path))
     finally:
@@ -175,7 +180,7 @@ def test_served_shapes_both_paths(binding, Q, path):
 
 def test_batched_ordered_path(binding):
     inst = W.batched_ragged(13, num_tours=9, S=700)
-    binding.set_schedule(32, 8, 3, 0, 2)
+    binding.set_schedule(32, 8, 0, 4, 0, 2)
     try:
         _run_both(binding, inst, label=inst.name + " ordered")
     finally:
@@ -187,13 +192,16 @@ def test_every_schedule_on_paper_shape(binding):
     inst = W.plain_paper_scale(11, S=20_000)
     tours, lens, dist, dem = W.as_arrays(inst)
     ref = oracle.split_eval(tours, lens, dist, dem, inst.Q, nthreads=THREADS)
+    assert binding.SCHEDULES
     for sched in binding.SCHEDULES:
-        _say("schedule %s" % (sched,))
-        binding.set_schedule(*sched)
-        try:
-            _assert_same(_device_eval(binding, tours, lens, dist, dem, inst.Q), ref, "schedule %s" % (sched,))
-        finally:
-            binding.set_schedule(0)
+        for path in (1, 2):
+            _say("schedule %s path %d" % (sched, path))
+            binding.set_schedule(*sched, waves=0, path=path)
+            try:
+                _assert_same(_device_eval(binding, tours, lens, dist, dem, inst.Q), ref,
+                             "schedule %s path %d" % (sched, path))
+            finally:
+                binding.set_schedule(0)
 
 
 def test_large_customer_pool_beyond_lds(binding):
@@ -301,7 +309,7 @@ def test_tuner_records_a_parity_gated_schedule(binding):
         ms = binding.tune_device(t, l, d, q, inst.Q, reps=2)
         assert ms > 0
         rec = binding.tune_lookup(inst.num_tours, int(lens.max()), inst.N, inst.S, inst.Q)
-        assert rec is not None and rec[4] in (1, 2)
+        assert rec is not None and rec[5] in (1, 2)
         _say("tuned %s -> %s (%.3f ms)" % (inst.name, rec, ms))
         # the next evaluation in this bucket runs the tuned schedule
         _run_both(binding, inst, label=inst.name + " tuned")
