@@ -7,27 +7,29 @@ passes the ring slots rotated), so one text serves every unrolled position.
 
 Inputs : L (load of positions 1..j), Ln (load of positions 1..j+1),
          j (uniform), f_d, lq_d for d = 1..R (potential V(p) + a_{p+1} and
-         threshold L_p + Q of p = j - d), cp (lanes that reject d = F at
-         this position, computed by the previous position's block).
+         threshold L_p + Q of p = j - d), cp1 / cp2 (lanes that reject
+         d = F / d = F + G at this position, computed by the previous
+         position's block).
 Outputs: m  = min over admissible d of f_d (2^30 if none),
-         cn = lanes that will reject d = F at position j + 1
-              (Ln > lq of p = j + 1 - F, i.e. this block's operand F - 1),
+         cn1 / cn2 = the same two masks for position j + 1 (Ln against the
+              thresholds of p = j + 1 - F and p = j + 1 - F - G, which are
+              this block's operands F - 1 and F + G - 1),
          ov = 1 on lanes that admit d = R while j > R (window past the ring).
 
 Admissible predecessors of a lane form the contiguous range d = 1..w, so a
 lane that rejects d rejects every larger d.  A block has two regimes:
 
   head : cells every active lane admits, folded with v_min3 (two potentials
-         per instruction).  The first group, cells 1..F, is validated by a
-         mask computed one position earlier, so its branch never waits on a
-         fresh vector compare.  Later groups of G cells (G = 0: none) are
-         validated on their farthest cell by v_cmp into VCC and a branch on
-         VCC.  A failing group sends control to the tail entry at the
-         group's first cell.
+         per instruction): cells 1..F, then (G > 0) cells F+1..F+G.  Each
+         group is validated by a mask computed one position earlier, so its
+         branch is a scalar test that never waits on a vector compare.  A
+         failing group sends control to the tail entry at its first cell.
   tail : v_cmpx narrows EXEC to the lanes still admitting d, then v_min.
          Every E cells a branch leaves once EXEC is empty (cells executed
          after EXEC emptied are no-ops).  EXEC is restored once.
 
+The path where every group passes falls straight into the tail; the other
+tail entries are laid out after it and jump back in.
 Variants (F, G, E) are named V<F>_<G>_<E>.
 """
 import os
@@ -36,57 +38,27 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 INF_IMM = "2.0"  # inline constant with bit pattern 0x40000000 = 2^30
 # (first, group, every) schedules compiled for each ring length
 VARIANTS = {
-    32: ((8, 0, 4), (8, 0, 3), (8, 0, 6), (6, 0, 4), (10, 0, 4), (8, 4, 4), (8, 2, 3)),
-    64: ((16, 0, 6), (16, 0, 4), (24, 0, 4), (16, 4, 4), (8, 4, 4)),
+    32: ((8, 3, 3), (8, 0, 4), (8, 3, 2), (8, 2, 2), (6, 3, 3), (6, 2, 2), (10, 3, 3)),
+    64: ((16, 4, 4), (16, 0, 6), (20, 4, 3), (12, 6, 2), (24, 4, 4)),
 }
 RINGS = tuple(VARIANTS)
 
 
-def head_groups(R, first, group):
-    """[(lo, hi)] cell ranges of the head groups, in order."""
-    groups = [(1, first)]
-    d = first + 1
-    while group and d + group - 1 <= R:
-        groups.append((d, d + group - 1))
-        d += group
-    return groups
-
-
-def exits(R, first, every):
+def exits(R, head_end, every):
     """Tail cells after which an empty EXEC leaves the block."""
-    xs = set(range(every, first, every))
-    xs.update(range(first + every, R + 1, every))
+    xs = set(range(every, head_end, every))
+    xs.update(range(head_end + every, R + 1, every))
     xs.add(R)
     return xs
 
 
 def block(R: int, first: int, group: int, every: int) -> list:
-    assert 2 <= first < R and group >= 0 and every >= 1
+    assert 2 <= first and first + group < R and group >= 0 and every >= 1
+    assert group != 1
     L = []
     a = L.append
-    a("s_mov_b64 %[sv], exec")
-    a("v_cmp_gt_i32_e64 %%[cn], %%[Ln], %%[q%d]" % (first - 1))
-    a("s_cmp_lg_u64 %[cp], 0")
-    a("s_cbranch_scc1 .Lt1_%=")
-    groups = head_groups(R, first, group)
-    for gi, (lo, hi) in enumerate(groups):
-        cells = list(range(lo, hi + 1))
-        k = 0
-        if gi == 0:
-            a("v_min_i32_e32 %%[m], %%[f%d], %%[f%d]" % (cells[0], cells[1]))
-            k = 2
-        else:
-            a("v_cmp_gt_i32_e32 vcc, %%[L], %%[q%d]" % hi)
-            a("s_cbranch_vccnz .Lt%d_%%=" % lo)
-        while k < len(cells):
-            if k + 1 < len(cells):
-                a("v_min3_i32 %%[m], %%[m], %%[f%d], %%[f%d]" % (cells[k], cells[k + 1]))
-                k += 2
-            else:
-                a("v_min_i32_e32 %%[m], %%[m], %%[f%d]" % cells[k])
-                k += 1
-    head_end = groups[-1][1]
-    xs = exits(R, first, every)
+    head_end = first + group
+    xs = exits(R, head_end, every)
 
     def cell(d):
         a("v_cmpx_le_i32_e32 vcc, %%[L], %%[q%d]" % d)
@@ -94,7 +66,32 @@ def block(R: int, first: int, group: int, every: int) -> list:
             a("s_cbranch_execz .Ldone_%=")
         a("v_min_i32_e32 %%[m], %%[m], %%[f%d]" % d)
 
-    # hot tail: falls through from the head, cells head_end+1..R
+    def fold(lo, hi, start):
+        cells = list(range(lo, hi + 1))
+        k = 0
+        if start:
+            a("v_min_i32_e32 %%[m], %%[f%d], %%[f%d]" % (cells[0], cells[1]))
+            k = 2
+        while k < len(cells):
+            if k + 1 < len(cells):
+                a("v_min3_i32 %%[m], %%[m], %%[f%d], %%[f%d]" % (cells[k], cells[k + 1]))
+                k += 2
+            else:
+                a("v_min_i32_e32 %%[m], %%[m], %%[f%d]" % cells[k])
+                k += 1
+
+    a("s_mov_b64 %[sv], exec")
+    a("v_cmp_gt_i32_e64 %%[cn1], %%[Ln], %%[q%d]" % (first - 1))
+    if group:
+        a("v_cmp_gt_i32_e64 %%[cn2], %%[Ln], %%[q%d]" % (head_end - 1))
+    a("s_cmp_lg_u64 %[cp1], 0")
+    a("s_cbranch_scc1 .Lt1_%=")
+    fold(1, first, True)
+    if group:
+        a("s_cmp_lg_u64 %[cp2], 0")
+        a("s_cbranch_scc1 .Lt%d_%%=" % (first + 1))
+        fold(first + 1, head_end, False)
+    # hot tail: every head group passed, cells head_end+1..R
     a(".Lt%d_%%=:" % (head_end + 1))
     for d in range(head_end + 1, R + 1):
         cell(d)
@@ -103,16 +100,18 @@ def block(R: int, first: int, group: int, every: int) -> list:
     a("s_cbranch_scc0 .Ldone_%=")
     a("v_mov_b32_e32 %[ov], 1")
     a("s_branch .Ldone_%=")
-    # cold tail: entered when a head group fails, cells 1..head_end, then
-    # back into the hot tail
-    entries = {lo for lo, _ in groups}
+    if group:
+        # the second group failed: its cells, then back into the hot tail
+        a(".Lt%d_%%=:" % (first + 1))
+        for d in range(first + 1, head_end + 1):
+            cell(d)
+        a("s_branch .Lt%d_%%=" % (head_end + 1))
+    # the first group failed: cells 1..F, then on as above
     a(".Lt1_%=:")
     a("v_mov_b32_e32 %%[m], %s" % INF_IMM)
-    for d in range(1, head_end + 1):
-        if d in entries and d > 1:
-            a(".Lt%d_%%=:" % d)
+    for d in range(1, first + 1):
         cell(d)
-    a("s_branch .Lt%d_%%=" % (head_end + 1))
+    a("s_branch .Lt%d_%%=" % (first + 1))
     a(".Ldone_%=:")
     a("s_mov_b64 exec, %[sv]")
     return L
@@ -144,21 +143,30 @@ def emit_operands(R: int) -> str:
 
 
 def emit_wrapper(R: int, first: int, group: int, every: int) -> str:
+    if group:
+        outs = ('                     : [m] "=&v"(m), [ov] "+v"(ov), [sv] "=&s"(sv), [cn1] "=&s"(cn1),\n'
+                '                       [cn2] "=&s"(cn2)')
+        ins = '                     : [L] "v"(L), [Ln] "v"(Ln), [j] "s"(j), [cp1] "s"(cp1), [cp2] "s"(cp2),'
+        tail = ""
+    else:
+        outs = '                     : [m] "=&v"(m), [ov] "+v"(ov), [sv] "=&s"(sv), [cn1] "=&s"(cn1)'
+        ins = '                     : [L] "v"(L), [Ln] "v"(Ln), [j] "s"(j), [cp1] "s"(cp1),'
+        tail = "        (void)cp2;\n        cn2 = 0;\n"
     return "\n".join([
         "template <> struct WindowMin<%d, %d, %d, %d> {" % (R, first, group, every),
         "    template <int U>",
         "    __device__ __forceinline__ static int run(const int (&f)[%d], const int (&lq)[%d], int L," % (R, R),
-        "                                              int Ln, int j, uint64_t cp, uint64_t &cn,",
-        "                                              int &ov)",
+        "                                              int Ln, int j, uint64_t cp1, uint64_t cp2,",
+        "                                              uint64_t &cn1, uint64_t &cn2, int &ov)",
         "    {",
         "        int m;",
         "        uint64_t sv;",
         "        asm volatile(SPLIT_WINDOW_ASM_R%d_%s" % (R, name(first, group, every)),
-        "                     : [m] \"=&v\"(m), [ov] \"+v\"(ov), [sv] \"=&s\"(sv), [cn] \"=&s\"(cn)",
-        "                     : [L] \"v\"(L), [Ln] \"v\"(Ln), [j] \"s\"(j), [cp] \"s\"(cp),",
+        outs,
+        ins,
         "                       SPLIT_WINDOW_OPERANDS_R%d(f, lq, U)" % R,
-        "                     : \"vcc\", \"scc\");",
-        "        return m;",
+        '                     : "vcc", "scc");',
+        tail + "        return m;",
         "    }",
         "};",
         ""])
@@ -167,7 +175,7 @@ def emit_wrapper(R: int, first: int, group: int, every: int) -> str:
 def main():
     text = ["// window_min_asm.inc -- GENERATED by gen_window_asm.py; do not edit.",
             "// Masked window minimum of one tour position (see gen_window_asm.py).",
-            "// WindowMin<R, F, G, E>::run<U>(f, lq, L, Ln, j, cp, cn, ov) returns m.",
+            "// WindowMin<R, F, G, E>::run<U>(f, lq, L, Ln, j, cp1, cp2, cn1, cn2, ov) returns m.",
             "",
             "template <int R, int F, int G, int E> struct WindowMin;",
             ""]

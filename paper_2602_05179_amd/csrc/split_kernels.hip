@@ -324,7 +324,7 @@ __device__ __forceinline__ bool stage_tile_u8(const int16_t *__restrict__ src, u
 // predecessor p = j - d, so every slot is a compile-time register.  Loads
 // run one position ahead: while position j is relaxed the demand of j+2 and
 // the table entry of j+3 are in flight, and the demand of j+1 has arrived,
-// so the load L_{j+1} is known and the next position's first head check is
+// so the load L_{j+1} is known and the next position's head checks are
 // issued inside this position's window block.
 // ---------------------------------------------------------------------------
 #include "window_min_asm.inc"
@@ -335,9 +335,10 @@ struct DpRegs {
     int2 t0;     // table entry of position j {customer, c}
     int2 t1;     // table entry of position j+1
     int2 t2;     // table entry of position j+2 (in flight)
-    uint64_t cp; // lanes rejecting d = F at position j (computed at j-1)
-    int mres;    // m of the last position relaxed (m_n after the loop)
-    int ovf;     // 1 when a window reached past the ring
+    uint64_t cp1; // lanes rejecting d = F at position j (computed at j-1)
+    uint64_t cp2; // lanes rejecting d = F + G at position j (computed at j-1)
+    int mres;     // m of the last position relaxed (m_n after the loop)
+    int ovf;      // 1 when a window reached past the ring
 };
 
 template <int R, int F, int G, int E, int U> struct DpState {
@@ -354,13 +355,15 @@ template <int R, int F, int G, int E, int U> struct DpState {
         const int Ln = r.L + r.qa;
         r.qa = row[r.t2.x];
         const int2 t3 = tab_at(tab, j + 3);
-        uint64_t cn;
-        const int m = WindowMin<R, F, G, E>::template run<U>(f, lq, r.L, Ln, j, r.cp, cn, r.ovf);
+        uint64_t cn1, cn2;
+        const int m = WindowMin<R, F, G, E>::template run<U>(f, lq, r.L, Ln, j, r.cp1, r.cp2, cn1,
+                                                             cn2, r.ovf);
         r.mres = m; // the last position relaxed is j = n
         f[U] = m + cj;
         lq[U] = r.L + Q;
         r.L = Ln;
-        r.cp = cn;
+        r.cp1 = cn1;
+        r.cp2 = cn2;
         r.t0 = r.t1;
         r.t1 = r.t2;
         r.t2 = t3;
@@ -392,7 +395,8 @@ __device__ __forceinline__ int dp_lane(const uint8_t *row, CInt *tab, int n, int
     DpRegs r;
     r.mres = kInf;
     r.ovf = 0;
-    r.cp = ~0ull; // position 1 starts in the tail
+    r.cp1 = ~0ull; // position 1 starts in the tail
+    r.cp2 = ~0ull;
     r.t0 = tab_at(tab, 1);
     r.t1 = tab_at(tab, 2);
     r.t2 = tab_at(tab, 3);
@@ -462,7 +466,7 @@ __global__ __launch_bounds__(kWave *kMaxWavesPerGroup) void split_tile_kernel(
         int v = 0;
         if (lane < rows) {
             const int m = dp_lane<R, F, G, E>(lds + (int64_t)lane * N, tab, rec.n, rec.f0,
-                                                   Q, ovf);
+                                              Q, ovf);
             v = m + rec.bn;
         }
         redo = ballot(ovf) != 0;
@@ -549,9 +553,10 @@ struct DpRegsO {
     int L;       // load of positions 1..j (at the start of position j)
     int2 t0;     // table entry of position j {customer, c}
     int2 t1;     // table entry of position j+1 (in flight)
-    uint64_t cp; // lanes rejecting d = F at position j (computed at j-1)
-    int mres;    // m of the last position relaxed (m_n after the loop)
-    int ovf;     // 1 when a window reached past the ring
+    uint64_t cp1; // lanes rejecting d = F at position j (computed at j-1)
+    uint64_t cp2; // lanes rejecting d = F + G at position j (computed at j-1)
+    int mres;     // m of the last position relaxed (m_n after the loop)
+    int ovf;      // 1 when a window reached past the ring
     u32x4 cur[2], nxt[2]; // demand bytes of the current / next 32 positions
 };
 
@@ -579,14 +584,15 @@ template <int R, int F, int G, int E, int U> struct DpStateO {
         const int Ln = r.L + qn;
         r.t0 = r.t1;
         r.t1 = tab_at(tab, j + 2);
-        uint64_t cn;
-        const int m =
-            WindowMin<R, F, G, E>::template run<SL>(f, lq, r.L, Ln, j, r.cp, cn, r.ovf);
+        uint64_t cn1, cn2;
+        const int m = WindowMin<R, F, G, E>::template run<SL>(f, lq, r.L, Ln, j, r.cp1, r.cp2,
+                                                              cn1, cn2, r.ovf);
         r.mres = m;
         f[SL] = m + cj;
         lq[SL] = r.L + Q;
         r.L = Ln;
-        r.cp = cn;
+        r.cp1 = cn1;
+        r.cp2 = cn2;
         if (B == 31) { // next 32 positions: rotate and prefetch the one after
             r.cur[0] = r.nxt[0];
             r.cur[1] = r.nxt[1];
@@ -623,7 +629,8 @@ __device__ __forceinline__ int dp_lane_ordered(const uint8_t *rowb, int pitch, C
     DpRegsO r;
     r.mres = kInf;
     r.ovf = 0;
-    r.cp = ~0ull; // position 1 starts in the tail
+    r.cp1 = ~0ull; // position 1 starts in the tail
+    r.cp2 = ~0ull;
     r.t0 = tab_at(tab, 1);
     r.t1 = tab_at(tab, 2);
     const u32x4 *row = reinterpret_cast<const u32x4 *>(rowb);
@@ -972,9 +979,9 @@ Schedule default_schedule(int32_t N, int64_t S, int32_t Q)
     (void)S;
     Schedule s;
     s.ring = Q > 200 ? 64 : 32;
-    s.first = Q > 200 ? 16 : Q <= 100 ? 6 : 8;
-    s.group = 0;
-    s.every = Q > 200 ? 6 : 4;
+    s.first = Q > 200 ? 16 : Q > 100 ? 8 : 6;
+    s.group = Q > 200 ? 4 : 3;
+    s.every = Q > 200 ? 4 : 3;
     s.waves = 0;
     s.path = 0;
     return s;

@@ -56,18 +56,18 @@ def test_tuning_table_save_load_roundtrip(tmp_path):
     import ctypes
     key = (0, 7, 7, 9, 7)  # one tour, n~200, N~200, S~1e6, Q~150
     f.write_text("# tours len pool scen cap -> ring first group every waves path\n"
-                 "%d %d %d %d %d 32 8 2 3 1 1\n" % key)
+                 "%d %d %d %d %d 32 8 3 2 1 1\n" % key)
     b.tune_load(f)
-    assert b.tune_lookup(1, 200, 200, 1_000_000, 150) == (32, 8, 2, 3, 1, 1)
+    assert b.tune_lookup(1, 200, 200, 1_000_000, 150) == (32, 8, 3, 2, 1, 1)
     g = tmp_path / "tune2.txt"
     b.tune_save(g)
     b.tune_clear()
     assert b.tune_lookup(1, 200, 200, 1_000_000, 150) is None
     b.tune_load(g)
-    assert b.tune_lookup(1, 200, 200, 1_000_000, 150) == (32, 8, 2, 3, 1, 1)
+    assert b.tune_lookup(1, 200, 200, 1_000_000, 150) == (32, 8, 3, 2, 1, 1)
     b.tune_clear()
     bad = tmp_path / "bad.txt"
-    bad.write_text("0 7 7 9 7 33 8 2 3 1 1\n")
+    bad.write_text("0 7 7 9 7 33 8 3 3 1 1\n")
     with pytest.raises(b.SplitError):
         b.tune_load(bad)
     del ctypes

@@ -148,8 +148,8 @@ def _edge_instances():
     return out
 
 
-# one variant without and one with later head groups, per ring length
-_EDGE_VARIANTS = [(32, 8, 0, 4), (32, 8, 2, 3), (64, 16, 0, 4), (64, 8, 4, 4)]
+# one variant without and one with a second head group, per ring length
+_EDGE_VARIANTS = [(32, 8, 0, 4), (32, 8, 3, 2), (64, 16, 0, 6), (64, 12, 6, 2)]
 
 
 @pytest.mark.parametrize("path", [1, 2])
@@ -171,7 +171,8 @@ def test_served_shapes_both_paths(binding, Q, path):
     """n=1000 requests (the served mix): LDS-staged and tour-ordered paths."""
     inst = W.plain_normal(20 + Q, 1000, 3000, Q)
     if path:
-        binding.set_schedule(64 if Q > 200 else 32, 16 if Q > 200 else 8, 0, 4, 0, path)
+        v = (64, 16, 0, 6) if Q > 200 else (32, 8, 0, 4)
+        binding.set_schedule(*v, waves=0, path=path)
     try:
         _run_both(binding, inst, label="%s path=%d" % (inst.name, path))
     finally:
