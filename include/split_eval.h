@@ -183,6 +183,17 @@ int split_tune_load(const char *path);
 int split_tune_clear(void);
 
 /*
+ * split_probe_valu_peak -- measured int32 vector-ALU rate of the current
+ * device, as a roofline reference (a measurement helper, not part of the
+ * method).  Runs a kernel of independent v_min_i32 chains with eight waves
+ * per SIMD on `stream`, waits for it, and stores lane-operations per second
+ * in *lane_ops_per_s (host pointer).  Allocates and frees a 4-byte device
+ * buffer.  SPLIT_EINVAL for a null pointer, SPLIT_EDEVICE/ENOMEM on device
+ * errors.
+ */
+int split_probe_valu_peak(double *lane_ops_per_s, split_stream_t stream);
+
+/*
  * Measurement.  While enabled, every launch of the main evaluation kernel
  * is bracketed by a pair of HIP events recorded on the launch stream.
  * split_profile_read waits for the recorded events, returns the summed

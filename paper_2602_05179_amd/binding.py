@@ -33,6 +33,7 @@ EXPORTED = (
     "split_plan_destroy",
     "split_set_schedule",
     "split_list_variants",
+    "split_probe_valu_peak",
     "split_profile_enable",
     "split_profile_read",
     "split_server_create",
@@ -84,6 +85,8 @@ def _load():
     lib.split_plan_destroy.argtypes = [P]
     lib.split_set_schedule.restype = ctypes.c_int
     lib.split_set_schedule.argtypes = [i32, i32, i32, i32, i32, i32]
+    lib.split_probe_valu_peak.restype = ctypes.c_int
+    lib.split_probe_valu_peak.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]
     lib.split_list_variants.restype = ctypes.c_int
     lib.split_list_variants.argtypes = [ctypes.POINTER(i32), i32]
     lib.split_profile_enable.restype = ctypes.c_int
@@ -148,6 +151,13 @@ def set_schedule(ring: int, first: int = 8, group: int = 0, every: int = 4, wave
     """Force the main-kernel schedule; ring=0 restores the automatic choice."""
     _check(lib.split_set_schedule(int(ring), int(first), int(group), int(every), int(waves),
                                   int(path)))
+
+
+def probe_valu_peak(stream=None) -> float:
+    """Measured int32 VALU lane-operations per second of the current device."""
+    v = ctypes.c_double()
+    _check(lib.split_probe_valu_peak(ctypes.byref(v), _stream_handle(stream)))
+    return v.value
 
 
 def profile_enable(on: bool = True):

@@ -10,7 +10,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsplit_eval.so")
 SOURCES = [os.path.join(CSRC, "split_kernels.hip"), os.path.join(CSRC, "split_api.cpp"),
-           os.path.join(CSRC, "split_server.cpp"), os.path.join(CSRC, "split_tune.cpp")]
+           os.path.join(CSRC, "split_server.cpp"), os.path.join(CSRC, "split_tune.cpp"),
+           os.path.join(CSRC, "split_probe.hip")]
 HEADERS = [os.path.join(INCLUDE, "split_eval.h"), os.path.join(CSRC, "split_internal.h"),
            os.path.join(CSRC, "window_min_asm.inc")]
 ARCH = "gfx950"

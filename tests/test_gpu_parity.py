@@ -315,3 +315,11 @@ def test_tuner_records_a_parity_gated_schedule(binding):
         # the next evaluation in this bucket runs the tuned schedule
         _run_both(binding, inst, label=inst.name + " tuned")
     binding.tune_clear()
+
+
+def test_valu_probe_reports_a_plausible_rate(binding):
+    """The roofline reference kernel: an int32 VALU rate within the device's range."""
+    rate = binding.probe_valu_peak()
+    _say("measured VALU rate %.3e lane-ops/s" % rate)
+    # 256 CUs x 64 lanes x 2.4 GHz = 3.9e13 at most; a healthy device is far above 1e12
+    assert 1e12 < rate < 6e13
