@@ -38,6 +38,8 @@ def _load():
         lib.oracle_split_sample.restype = ctypes.c_int
         lib.oracle_split_values.argtypes = [P, i32, P, i32, P, i64, ctypes.c_int, P, P]
         lib.oracle_split_values.restype = ctypes.c_int
+        lib.oracle_split_routes.argtypes = [P, i32, P, i32, P, i64, i32, P, P, P, P, ctypes.c_int]
+        lib.oracle_split_routes.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -112,5 +114,35 @@ def split_values(tour, dist, qvis, Q, *, use_break=True):
     return [None if v == INF64 else int(v) for v in V], int(cells[0])
 
 
-__all__ = ["split_eval", "split_sample", "split_values", "brute", "build_oracle", "LIB", "INF32",
-           "INF64", "OracleError"]
+NO_PRED = 0xFFFF
+
+
+def split_routes(tour, dist, demands, Q, *, nthreads=1):
+    """Route recovery for one tour over every scenario (smallest minimising
+    predecessor, then backtracking from n).
+
+    Returns dict(costs=int32[S], pred=uint16[S, n] (NO_PRED where J(i) is
+    +inf), cuts=uint16[S, n] (route ends in increasing order, zeros after),
+    nroutes=int32[S])."""
+    lib = _load()
+    tour = np.ascontiguousarray(tour, np.int32)
+    dist = np.ascontiguousarray(dist, np.int32)
+    demands = np.ascontiguousarray(demands, np.int16)
+    n = int(tour.size)
+    S = int(demands.shape[0])
+    N = int(dist.shape[0] - 1)
+    if demands.ndim != 2 or demands.shape[1] != N or dist.shape != (N + 1, N + 1):
+        raise OracleError("shape mismatch")
+    costs = np.empty(S, np.int32)
+    pred = np.empty((S, n), np.uint16)
+    cuts = np.empty((S, n), np.uint16)
+    nroutes = np.empty(S, np.int32)
+    rc = lib.oracle_split_routes(_p(tour), n, _p(dist), N, _p(demands), S, int(Q), _p(costs),
+                                 _p(pred), _p(cuts), _p(nroutes), int(nthreads))
+    if rc != 0:
+        raise OracleError("oracle_split_routes returned %d" % rc)
+    return dict(costs=costs, pred=pred, cuts=cuts, nroutes=nroutes)
+
+
+__all__ = ["split_eval", "split_sample", "split_values", "split_routes", "brute", "build_oracle", "LIB",
+           "INF32", "INF64", "NO_PRED", "OracleError"]

@@ -60,3 +60,44 @@ def all_splits(n):
         cuts = [k + 1 for k in range(n - 1) if mask >> k & 1]
         bounds = [0] + cuts + [n]
         yield tuple(zip(bounds[:-1], bounds[1:]))
+
+
+def smallest_last_cut(tour, qvis, dist, Q):
+    """For every prefix j = 1..n: the smallest p such that some cheapest
+    admissible split of sigma_1..sigma_j has its last route p+1..j (None if
+    the prefix has no admissible split).  By enumeration of all cut sets of
+    each prefix, independent of any recursion."""
+    out = []
+    for j in range(1, len(tour) + 1):
+        best, starts = None, set()
+        for mask in range(1 << (j - 1)):
+            cuts = [k + 1 for k in range(j - 1) if mask >> k & 1]
+            bounds = [0] + cuts + [j]
+            total, ok = 0, True
+            for a, b in zip(bounds[:-1], bounds[1:]):
+                if sum(qvis[a:b]) > Q:
+                    ok = False
+                    break
+                total += route_cost(tour[a:b], dist)
+            if not ok:
+                continue
+            if best is None or total < best:
+                best, starts = total, {bounds[-2]}
+            elif total == best:
+                starts.add(bounds[-2])
+        out.append(min(starts) if best is not None else None)
+    return out
+
+
+def split_cost(tour, qvis, dist, Q, ends):
+    """Cost of the split whose routes end at positions `ends` (increasing,
+    last = n), or None if a route is over capacity or `ends` is malformed."""
+    n = len(tour)
+    if not ends or ends[-1] != n or any(b <= a for a, b in zip([0] + ends[:-1], ends)):
+        return None
+    total = 0
+    for a, b in zip([0] + ends[:-1], ends):
+        if sum(qvis[a:b]) > Q:
+            return None
+        total += route_cost(tour[a:b], dist)
+    return total

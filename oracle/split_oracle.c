@@ -282,3 +282,159 @@ int oracle_split_values(const int32_t *tour, int32_t n, const int32_t *dist, int
     free(q);
     return 0;
 }
+
+/*
+ * Route recovery.  The giant tour is cut into routes by the split (App. A:
+ * routes are recovered from the giant tour by the split operator), and a
+ * DP that records each minimiser is backtracked to recover the decisions
+ * (App. B, batched DP with backtracking).  Readings where the paper is
+ * silent: pred(i) is the SMALLEST predecessor p attaining J(i) =
+ * J(p) + A(p,i) (ties broken towards longer last routes), 0xFFFF when
+ * J(i) = +inf; the cut points are i_k = n, i_{k-1} = pred(i_k), ..., down
+ * to 0, reported in increasing order (the route ends), so route r covers
+ * positions i_{r-1}+1 .. i_r with i_0 = 0.
+ */
+#define OR_NO_PRED 0xFFFFu
+
+static int64_t split_one_pred(const int32_t *tour, int32_t n, const int32_t *dist, int32_t N1,
+                              const int64_t *q, int64_t Q, int64_t *V, uint16_t *pred)
+{
+    V[0] = 0;
+    for (int32_t i = 1; i <= n; ++i) {
+        const int32_t last = tour[i - 1];
+        const int64_t back = dist[(int64_t)last * N1 + 0];
+        int64_t best = OR_INF;
+        int32_t arg = -1;
+        int64_t load = 0;
+        int64_t inner = 0;
+        for (int32_t p = i - 1; p >= 0; --p) { /* p decreasing: "<=" keeps the smallest */
+            const int32_t first = tour[p];
+            load += q[p + 1];
+            if (p + 1 <= i - 1)
+                inner += dist[(int64_t)first * N1 + tour[p + 1]];
+            if (load > Q)
+                break;
+            const int64_t w = dist[first] + inner + back;
+            if (V[p] != OR_INF && V[p] + w <= best) {
+                best = V[p] + w;
+                arg = p;
+            }
+        }
+        V[i] = best;
+        pred[i - 1] = arg < 0 ? (uint16_t)OR_NO_PRED : (uint16_t)arg;
+    }
+    return V[n];
+}
+
+typedef struct {
+    const int32_t *tour;
+    int32_t n;
+    const int32_t *dist;
+    int32_t N;
+    const int16_t *demands;
+    int64_t s_begin, s_end;
+    int64_t Q;
+    int32_t *costs;
+    uint16_t *pred;
+    uint16_t *cuts;
+    int32_t *nroutes;
+    int status;
+} routes_job_t;
+
+static void *run_routes_job(void *arg)
+{
+    routes_job_t *jb = (routes_job_t *)arg;
+    const int32_t n = jb->n;
+    int64_t *V = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+    int64_t *q = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+    uint16_t *pr = (uint16_t *)malloc(sizeof(uint16_t) * ((size_t)n + 1));
+    if (!V || !q || !pr) {
+        jb->status = -2;
+        free(V);
+        free(q);
+        free(pr);
+        return NULL;
+    }
+    for (int64_t s = jb->s_begin; s < jb->s_end; ++s) {
+        const int16_t *row = jb->demands + s * (int64_t)jb->N;
+        q[0] = 0;
+        for (int32_t k = 1; k <= n; ++k)
+            q[k] = row[jb->tour[k - 1] - 1];
+        const int64_t v = split_one_pred(jb->tour, n, jb->dist, jb->N + 1, q, jb->Q, V, pr);
+        jb->costs[s] = v == OR_INF ? INT32_MAX : (int32_t)v;
+        if (jb->pred)
+            memcpy(jb->pred + s * (int64_t)n, pr, sizeof(uint16_t) * (size_t)n);
+        uint16_t *cut = jb->cuts ? jb->cuts + s * (int64_t)n : NULL;
+        if (cut)
+            memset(cut, 0, sizeof(uint16_t) * (size_t)n);
+        int32_t k = 0;
+        if (v != OR_INF) {
+            for (int32_t i = n; i > 0; i = pr[i - 1])
+                ++k;
+            int32_t r = k;
+            for (int32_t i = n; i > 0; i = pr[i - 1])
+                if (cut)
+                    cut[--r] = (uint16_t)i;
+        }
+        jb->nroutes[s] = k;
+    }
+    free(V);
+    free(q);
+    free(pr);
+    return NULL;
+}
+
+/*
+ * Route recovery for one tour over every scenario: costs[s] = J_s(n)
+ * (INT32_MAX if no split exists), pred[s*n + i-1] = pred_s(i) (may be
+ * NULL), cuts[s*n + r-1] = end position of route r (r = 1..nroutes[s],
+ * zeros after; may be NULL), nroutes[s] = number of routes (0 for an
+ * infeasible scenario or an empty tour).  n must fit 16-bit positions.
+ */
+int oracle_split_routes(const int32_t *tour, int32_t n, const int32_t *dist, int32_t N,
+                        const int16_t *demands, int64_t S, int32_t Q, int32_t *costs,
+                        uint16_t *pred, uint16_t *cuts, int32_t *nroutes, int nthreads)
+{
+    int32_t lens = n;
+    if (check_args(tour, &lens, 1, dist, N, demands, S, Q) != 0 || !costs || !nroutes ||
+        n > 65535)
+        return -1;
+    if (nthreads < 1)
+        nthreads = 1;
+    if (nthreads > 64)
+        nthreads = 64;
+    if ((int64_t)nthreads > S)
+        nthreads = (int)S;
+    routes_job_t jobs[64];
+    pthread_t th[64];
+    for (int w = 0; w < nthreads; ++w) {
+        routes_job_t *jb = &jobs[w];
+        jb->tour = tour;
+        jb->n = n;
+        jb->dist = dist;
+        jb->N = N;
+        jb->demands = demands;
+        jb->s_begin = S * w / nthreads;
+        jb->s_end = S * (w + 1) / nthreads;
+        jb->Q = Q;
+        jb->costs = costs;
+        jb->pred = pred;
+        jb->cuts = cuts;
+        jb->nroutes = nroutes;
+        jb->status = 0;
+    }
+    int created[64] = {0};
+    for (int w = 1; w < nthreads; ++w)
+        created[w] = pthread_create(&th[w], NULL, run_routes_job, &jobs[w]) == 0;
+    run_routes_job(&jobs[0]);
+    int rc = jobs[0].status;
+    for (int w = 1; w < nthreads; ++w) {
+        if (created[w])
+            pthread_join(th[w], NULL);
+        else
+            run_routes_job(&jobs[w]); /* no thread: run it here */
+        if (jobs[w].status && !rc)
+            rc = jobs[w].status;
+    }
+    return rc;
+}
