@@ -118,6 +118,64 @@ int split_eval_device(const int32_t *d_tours, const int32_t *d_lens, int32_t num
                       split_stream_t stream);
 
 /*
+ * Route recovery (App. A: the giant tour is cut into routes by the split
+ * operator; App. B: a batched DP that records each minimiser and is then
+ * backtracked recovers the decisions).  For ONE giant tour over every
+ * scenario s:
+ *   pred_s(i) = the smallest p with V_s(i) = V_s(p) + W(p,i), admissible
+ *               (ties go to the longest last route), or SPLIT_NO_PRED when
+ *               V_s(i) = +inf;
+ *   cut points i_k = n, i_{k-1} = pred_s(i_k), ..., down to 0; route r
+ *   covers tour positions i_{r-1}+1 .. i_r (i_0 = 0).
+ *
+ * split_routes_device -- DEVICE pointers, enqueued on `stream` (nothing is
+ * allocated, no host synchronisation).
+ *   d_tour    int32 [n]          customer ids 1..N (n in [0, 65535])
+ *   d_dist, N, d_demands, S, Q   as in split_eval (d_demands 16-byte aligned)
+ *   d_costs   out int32 [S]      V_s(n), SPLIT_INF if no split exists
+ *   d_pred    out uint16 [n*S]   POSITION-MAJOR: d_pred[(i-1)*S + s] = pred_s(i)
+ *   d_cuts    out uint16 [n*S]   POSITION-MAJOR: d_cuts[(r-1)*S + s] = i_r for
+ *                                r = 1..nroutes_s (increasing); entries past
+ *                                nroutes_s are not written
+ *   d_nroutes out int32 [S]      number of routes k (0 when V_s(n) = +inf
+ *                                or n = 0; -1 when the inputs failed
+ *                                device-side validation)
+ *   d_workspace, ws_bytes        caller-owned device scratch of at least
+ *                                split_routes_workspace_bytes(n, N, S)
+ *                                bytes, 256-byte aligned
+ * d_tour, d_pred and d_cuts may be NULL when n = 0.  Host-checkable
+ * arguments are validated before anything is enqueued (SPLIT_EINVAL).  The
+ * tour's ids, costs and the int32 guard, and the demands' signs, are
+ * checked on the device: on failure every d_costs entry is SPLIT_INF and
+ * every d_nroutes entry -1.  The library touches the buffers only until
+ * the enqueued work completes; two calls sharing a workspace must be
+ * ordered on one stream.  Tiles whose 64 x N demand bytes do not fit in
+ * LDS, whose demands exceed 255, or whose windows exceed the register
+ * ring are recomputed by an exact (slower) kernel; results never depend
+ * on the path taken.
+ */
+#define SPLIT_NO_PRED 0xFFFF
+
+size_t split_routes_workspace_bytes(int32_t n, int32_t N, int64_t S);
+int split_routes_device(const int32_t *d_tour, int32_t n, const int32_t *d_dist, int32_t N,
+                        const int16_t *d_demands, int64_t S, int32_t Q, int32_t *d_costs,
+                        uint16_t *d_pred, uint16_t *d_cuts, int32_t *d_nroutes,
+                        void *d_workspace, size_t ws_bytes, split_stream_t stream);
+
+/*
+ * split_routes_set_variant -- window variant of the route-recovery kernel
+ * for every later call in the process: ring = 32 or 64 registers, first =
+ * head cells validated by one check issued a position early (0 = none),
+ * every = masked cells between exits on an empty lane mask.  ring = 0
+ * restores the automatic choice (by Q).  SPLIT_EINVAL for a variant that is
+ * not compiled in.  split_routes_list_variants writes up to `cap` entries
+ * of 3 int32 {ring, first, every} to `out` (host memory) and returns the
+ * number compiled in.  Not thread-safe against concurrent calls.
+ */
+int split_routes_set_variant(int32_t ring, int32_t first, int32_t every);
+int split_routes_list_variants(int32_t *out, int32_t cap);
+
+/*
  * split_count_cells_device -- Bellman-cell counter (measurement utility).
  * For each tour writes the number of capacity-admissible relaxations
  * (s, p, i), i.e. sum over scenarios and positions i of the number of

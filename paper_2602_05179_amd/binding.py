@@ -21,6 +21,7 @@ SPLIT_EDEVICE = -3
 SPLIT_EAGAIN = -4
 SPLIT_INF = np.iinfo(np.int32).max
 SPLIT_SUM_INVALID = np.iinfo(np.int64).min
+SPLIT_NO_PRED = 0xFFFF
 
 EXPORTED = (
     "split_last_error",
@@ -47,6 +48,10 @@ EXPORTED = (
     "split_tune_save",
     "split_tune_load",
     "split_tune_clear",
+    "split_routes_workspace_bytes",
+    "split_routes_device",
+    "split_routes_set_variant",
+    "split_routes_list_variants",
 )
 
 
@@ -117,6 +122,14 @@ def _load():
     lib.split_tune_load.argtypes = [ctypes.c_char_p]
     lib.split_tune_clear.restype = ctypes.c_int
     lib.split_tune_clear.argtypes = []
+    lib.split_routes_workspace_bytes.restype = sz
+    lib.split_routes_workspace_bytes.argtypes = [i32, i32, i64]
+    lib.split_routes_device.restype = ctypes.c_int
+    lib.split_routes_device.argtypes = [P, i32, P, i32, P, i64, i32, P, P, P, P, P, sz, P]
+    lib.split_routes_set_variant.restype = ctypes.c_int
+    lib.split_routes_set_variant.argtypes = [i32, i32, i32]
+    lib.split_routes_list_variants.restype = ctypes.c_int
+    lib.split_routes_list_variants.argtypes = [ctypes.POINTER(i32), i32]
     return lib
 
 
@@ -269,6 +282,75 @@ def split_count_cells_device(tours, lens, demands, N, Q, *, stream=None):
     _check(lib.split_count_cells_device(_dptr(tours), _dptr(lens), T, int(N), _dptr(demands), S, int(Q),
                                         _dptr(cells), _stream_handle(stream)))
     return cells
+
+
+# ---------------------------------------------------------------------------
+# route recovery (one giant tour, device tensors)
+# ---------------------------------------------------------------------------
+def list_route_variants():
+    """Compiled route-recovery window variants as (ring, first, every) tuples."""
+    n = lib.split_routes_list_variants(None, 0)
+    buf = (ctypes.c_int32 * (3 * n))()
+    lib.split_routes_list_variants(buf, n)
+    return [tuple(int(buf[3 * i + k]) for k in range(3)) for i in range(n)]
+
+
+ROUTE_VARIANTS = list_route_variants()
+
+
+def set_route_variant(ring: int, first: int = 0, every: int = 3):
+    """Force the route-recovery window variant; ring=0 restores the automatic choice."""
+    _check(lib.split_routes_set_variant(int(ring), int(first), int(every)))
+
+
+def routes_workspace_bytes(n: int, N: int, S: int) -> int:
+    return int(lib.split_routes_workspace_bytes(int(n), int(N), int(S)))
+
+
+class RouteOutputs:
+    """costs int32 [S]; pred and cuts position-major [n, S] 16-bit words
+    (held as int16 tensors, unsigned values: see host()); nroutes int32 [S]."""
+
+    def __init__(self, n: int, S: int, device):
+        torch = _torch()
+        self.n, self.S = n, S
+        self.costs = torch.empty(S, dtype=torch.int32, device=device)
+        self.pred = torch.empty((n, S), dtype=torch.int16, device=device)
+        self.cuts = torch.empty((n, S), dtype=torch.int16, device=device)
+        self.nroutes = torch.empty(S, dtype=torch.int32, device=device)
+
+    def host(self):
+        """Copies as numpy: costs, pred uint16 [n, S], cuts uint16 [n, S] (entries
+        past nroutes unspecified), nroutes."""
+        return dict(costs=self.costs.cpu().numpy(), pred=self.pred.cpu().numpy().view(np.uint16),
+                    cuts=self.cuts.cpu().numpy().view(np.uint16), nroutes=self.nroutes.cpu().numpy())
+
+
+def split_routes_device(tour, dist, demands, Q, *, out=None, workspace=None, stream=None):
+    """Enqueue route recovery of one giant tour over every scenario.
+
+    tour int32 [n], dist int32 [N+1, N+1], demands int16 [S, N] (16-byte
+    aligned), all on the same GPU.  Returns RouteOutputs."""
+    torch = _torch()
+    n = int(tour.numel())
+    N = int(dist.shape[0] - 1)
+    S = int(demands.shape[0])
+    for name, t, dt in (("tour", tour, torch.int32), ("dist", dist, torch.int32),
+                        ("demands", demands, torch.int16)):
+        if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+            raise SplitError(SPLIT_EINVAL, "%s must be a contiguous %s CUDA tensor" % (name, dt))
+    if out is None:
+        out = RouteOutputs(n, S, demands.device)
+    elif out.n != n or out.S != S:
+        raise SplitError(SPLIT_EINVAL, "outputs sized for n=%d S=%d" % (out.n, out.S))
+    need = routes_workspace_bytes(n, N, S)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=demands.device)
+    _check(lib.split_routes_device(_dptr(tour), n, _dptr(dist), N, _dptr(demands), S, int(Q),
+                                   _dptr(out.costs), _dptr(out.pred), _dptr(out.cuts), _dptr(out.nroutes),
+                                   _dptr(workspace), int(workspace.numel()), _stream_handle(stream)))
+    out.workspace = workspace
+    return out
 
 
 def tune_device(tours, lens, dist, demands, Q, *, max_len=None, reps=5, stream=None) -> float:

@@ -298,6 +298,73 @@ int split_eval_device(const int32_t *d_tours, const int32_t *d_lens, int32_t num
     return SPLIT_OK;
 }
 
+size_t split_routes_workspace_bytes(int32_t n, int32_t N, int64_t S)
+{
+    if (n < 0 || n > splitk::kMaxLen || S < 1 || N < 1)
+        return 0;
+    return splitk::routes_workspace_bytes(n, N, S);
+}
+
+int split_routes_set_variant(int32_t ring, int32_t first, int32_t every)
+{
+    g_err[0] = 0;
+    if (ring == 0) {
+        splitk::set_route_override(splitk::RouteVariant{0, 0, 0});
+        return SPLIT_OK;
+    }
+    const splitk::RouteVariant v{ring, first, every};
+    if (!splitk::route_variant_supported(v))
+        return fail(SPLIT_EINVAL, "unsupported route variant ring=%d first=%d every=%d", ring,
+                    first, every);
+    splitk::set_route_override(v);
+    return SPLIT_OK;
+}
+
+int split_routes_list_variants(int32_t *out, int32_t cap)
+{
+    g_err[0] = 0;
+    if (cap < 0 || (cap > 0 && !out))
+        return fail(SPLIT_EINVAL, "bad output buffer");
+    splitk::RouteVariant v[64];
+    const int n = splitk::compiled_route_variants(v, 64);
+    for (int i = 0; i < n && i < cap && i < 64; ++i) {
+        out[3 * i] = v[i].ring;
+        out[3 * i + 1] = v[i].first;
+        out[3 * i + 2] = v[i].every;
+    }
+    return n;
+}
+
+int split_routes_device(const int32_t *d_tour, int32_t n, const int32_t *d_dist, int32_t N,
+                        const int16_t *d_demands, int64_t S, int32_t Q, int32_t *d_costs,
+                        uint16_t *d_pred, uint16_t *d_cuts, int32_t *d_nroutes,
+                        void *d_workspace, size_t ws_bytes, split_stream_t stream)
+{
+    g_err[0] = 0;
+    int rc = check_scalars(1, N, S, Q, n);
+    if (rc)
+        return rc;
+    if (!d_dist || !d_demands || !d_costs || !d_nroutes || !d_workspace ||
+        (n > 0 && (!d_tour || !d_pred || !d_cuts)))
+        return fail(SPLIT_EINVAL, "null pointer argument");
+    if (reinterpret_cast<uintptr_t>(d_demands) % 16)
+        return fail(SPLIT_EINVAL, "demands must be 16-byte aligned");
+    if (reinterpret_cast<uintptr_t>(d_workspace) % 256)
+        return fail(SPLIT_EINVAL, "workspace must be 256-byte aligned");
+    const size_t need = splitk::routes_workspace_bytes(n, N, S);
+    if (ws_bytes < need)
+        return fail(SPLIT_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+    const splitk::Workspace ws = splitk::carve_workspace(d_workspace, 1, n, N, S, false);
+    splitk::LaunchEvents ev;
+    bool use_ev = false;
+    HIP_TRY(profile_events(&ev, &use_ev), "profile events");
+    HIP_TRY(splitk::launch_routes(d_tour, n, d_dist, N, d_demands, S, Q, d_costs, d_pred, d_cuts,
+                                  d_nroutes, ws, static_cast<hipStream_t>(stream),
+                                  splitk::choose_route_variant(Q), use_ev ? &ev : nullptr),
+            "launch");
+    return SPLIT_OK;
+}
+
 int split_profile_enable(int32_t on)
 {
     g_err[0] = 0;

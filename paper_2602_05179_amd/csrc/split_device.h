@@ -1,0 +1,93 @@
+// split_device.h -- device-side helpers shared by the evaluation and the
+// route-recovery kernels (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "split_internal.h"
+
+namespace splitk {
+
+constexpr int kWave = 64;
+constexpr int kInf = 1 << 30;    // "+inf" potential sentinel
+constexpr int kNeg = -(1 << 30); // threshold of ring slots before the tour start
+
+enum : int { ST_OK = 0, ST_BAD_TOUR = 1, ST_BAD_DEMAND = 2 };
+
+typedef const __attribute__((address_space(4))) int CInt; // scalar-loadable table words
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// table entry j of a per-tour table viewed as scalar-loadable words
+__device__ __forceinline__ int2 tab_at(CInt *tab, int j) { return make_int2(tab[2 * j], tab[2 * j + 1]); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+__device__ __forceinline__ long long wave_sum_i64(long long v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum_i32(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// tile staging: int16 rows [rows x N] (contiguous) -> LDS bytes [rows x N]
+// returns false (uniformly) when some value is outside [0, 255]
+// s_bad: an LDS word outside the staged bytes (the block-wide "bad" flag)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool stage_tile_u8(const int16_t *__restrict__ src, uint8_t *lds,
+                                              int64_t elems, int tid, int nthreads, int &s_bad)
+{
+    if (tid == 0)
+        s_bad = 0;
+    __syncthreads();
+    const int64_t chunks = elems >> 3; // full 8-element (16-byte) chunks
+    uint32_t bad = 0;
+    const u32x4 *src4 = reinterpret_cast<const u32x4 *>(src);
+    uint2 *dst8 = reinterpret_cast<uint2 *>(lds);
+    int64_t i = tid;
+    for (; i + 3 * nthreads < chunks; i += 4 * nthreads) {
+        u32x4 v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            v[r] = __builtin_nontemporal_load(&src4[i + r * nthreads]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t x0 = v[r].x, x1 = v[r].y, x2 = v[r].z, x3 = v[r].w;
+            bad |= (x0 | x1 | x2 | x3) & 0xFF00FF00u;
+            uint2 o;
+            o.x = __builtin_amdgcn_perm(x1, x0, 0x06040200u);
+            o.y = __builtin_amdgcn_perm(x3, x2, 0x06040200u);
+            dst8[i + r * nthreads] = o;
+        }
+    }
+    for (; i < chunks; i += nthreads) {
+        const u32x4 v = __builtin_nontemporal_load(&src4[i]);
+        const uint32_t x0 = v.x, x1 = v.y, x2 = v.z, x3 = v.w;
+        bad |= (x0 | x1 | x2 | x3) & 0xFF00FF00u;
+        uint2 o;
+        o.x = __builtin_amdgcn_perm(x1, x0, 0x06040200u);
+        o.y = __builtin_amdgcn_perm(x3, x2, 0x06040200u);
+        dst8[i] = o;
+    }
+    for (int64_t e = (chunks << 3) + tid; e < elems; e += nthreads) {
+        const int v = src[e];
+        bad |= (v < 0 || v > 255) ? 1u : 0u;
+        lds[e] = (uint8_t)v;
+    }
+    if (ballot(bad != 0) != 0 && (tid & (kWave - 1)) == 0)
+        atomicOr(&s_bad, 1);
+    __syncthreads();
+    return s_bad == 0;
+}
+
+} // namespace splitk

@@ -53,6 +53,7 @@ constexpr int kSlots = 64;           // partial-sum slots of a single tour (fewe
 constexpr int kSlotStride = 16;      // int64 words between slots (128 bytes)
 constexpr int kMaxLen = 65535;       // longest tour the library accepts
 constexpr int kLdsLimit = 160 * 1024; // LDS bytes one workgroup may use on gfx950
+constexpr int kFallbackBlocks = 64;  // waves of an exact-fallback launch (sizes the V scratch)
 
 int64_t num_tiles(int64_t S);
 size_t workspace_bytes(int32_t T, int32_t max_len, int32_t N, int64_t S, bool ordered);
@@ -61,6 +62,11 @@ Workspace carve_workspace(void *base, int32_t T, int32_t max_len, int32_t N, int
 int waves_per_group(int32_t T, int32_t N);
 bool ordered_path_possible(int32_t N, int32_t max_len);
 bool use_ordered_path(int32_t T, int32_t N, int32_t max_len);
+
+// Per-tour tables, validation and accumulator reset for T tours (lens ==
+// nullptr: one tour of length max_len).
+hipError_t launch_prep(const int32_t *tours, const int32_t *lens, int32_t T, int32_t max_len,
+                       const int32_t *dist, int32_t N, const Workspace &ws, hipStream_t stream);
 
 hipError_t launch_eval(const int32_t *tours, const int32_t *lens, int32_t T, int32_t max_len,
                        const int32_t *dist, int32_t N, const int16_t *demands, int64_t S,
@@ -88,6 +94,23 @@ hipError_t launch_count_mismatch(const int32_t *a, const int32_t *b, int64_t n, 
 
 // Every compiled (ring, first, group, every) window variant, in a fixed order.
 int compiled_schedules(Schedule *out, int cap);
+
+// Route recovery (one giant tour over S scenarios).
+struct RouteVariant {
+    int ring;  // register ring length R (32 or 64)
+    int first; // head cells validated by one check issued a position early (0 = none)
+    int every; // masked cells between exits on an empty EXEC
+};
+bool route_variant_supported(const RouteVariant &v);
+int compiled_route_variants(RouteVariant *out, int cap);
+RouteVariant choose_route_variant(int32_t Q); // override, else the default for Q
+void set_route_override(const RouteVariant &v); // ring 0 = automatic
+size_t routes_workspace_bytes(int32_t n, int32_t N, int64_t S);
+hipError_t launch_routes(const int32_t *tour, int32_t n, const int32_t *dist, int32_t N,
+                         const int16_t *demands, int64_t S, int32_t Q, int32_t *costs,
+                         uint16_t *pred, uint16_t *cuts, int32_t *nroutes, const Workspace &ws,
+                         hipStream_t stream, const RouteVariant &v,
+                         const LaunchEvents *ev = nullptr);
 
 // Shape bucket used by the tuning table.
 struct TuneKey {

@@ -46,41 +46,10 @@
 #include <utility>
 
 #include "split_eval.h"
+#include "split_device.h"
 #include "split_internal.h"
 
 namespace splitk {
-
-constexpr int kWave = 64;
-constexpr int kInf = 1 << 30;    // "+inf" potential sentinel
-constexpr int kNeg = -(1 << 30); // threshold of ring slots before the tour start
-
-enum : int { ST_OK = 0, ST_BAD_TOUR = 1, ST_BAD_DEMAND = 2 };
-
-typedef const __attribute__((address_space(4))) int CInt; // scalar-loadable table words
-
-// table entry j of a per-tour table viewed as scalar-loadable words
-__device__ __forceinline__ int2 tab_at(CInt *tab, int j) { return make_int2(tab[2 * j], tab[2 * j + 1]); }
-
-// ---------------------------------------------------------------------------
-// small helpers
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
-
-__device__ __forceinline__ long long wave_sum_i64(long long v)
-{
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1)
-        v += __shfl_xor(v, o, kWave);
-    return v;
-}
-
-__device__ __forceinline__ int wave_sum_i32(int v)
-{
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1)
-        v += __shfl_xor(v, o, kWave);
-    return v;
-}
 
 // Partial-sum slots per tour: enough that no slot sees many atomics (a
 // tour has ceil(S/64) units), few enough that the final fold stays short.
@@ -110,6 +79,7 @@ __device__ __forceinline__ void add_unit_result(const Workspace &ws, int T, int 
 // grid = num_tours blocks of 256 threads
 // tab[t * (max_len + kTabPad) + j] = {customer index of position j, c_j} for
 // j = 1..n, zero at j = 0 and for the padding entries n+1..n+3.
+// lens == nullptr: a single tour of length max_len.
 // ---------------------------------------------------------------------------
 constexpr int kPrepThreads = 256;
 
@@ -140,7 +110,7 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(
     long long off = 0;
     int prev_bad = 0;
     for (int i = tid; i < t; i += kPrepThreads) {
-        const int li = lens[i];
+        const int li = lens ? lens[i] : max_len;
         prev_bad |= (li < 0 || li > max_len) ? 1 : 0;
         off += li;
     }
@@ -160,7 +130,7 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(
     }
     __syncthreads();
 
-    const int n = lens[t];
+    const int n = lens ? lens[t] : max_len;
     int bad = (n < 0 || n > max_len || prev_bad) ? 1 : 0;
     const int nn = bad ? 0 : n;
     int maxc = 0;
@@ -261,59 +231,6 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(
         r.status = allbad ? ST_BAD_TOUR : ST_OK;
         ws.rec[t] = r;
     }
-}
-
-// ---------------------------------------------------------------------------
-// tile staging: int16 rows [rows x N] (contiguous) -> LDS bytes [rows x N]
-// returns false (uniformly) when some value is outside [0, 255]
-// ---------------------------------------------------------------------------
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-// s_bad: an LDS word outside the staged bytes (the block-wide "bad" flag)
-__device__ __forceinline__ bool stage_tile_u8(const int16_t *__restrict__ src, uint8_t *lds,
-                                              int64_t elems, int tid, int nthreads, int &s_bad)
-{
-    if (tid == 0)
-        s_bad = 0;
-    __syncthreads();
-    const int64_t chunks = elems >> 3; // full 8-element (16-byte) chunks
-    uint32_t bad = 0;
-    const u32x4 *src4 = reinterpret_cast<const u32x4 *>(src);
-    uint2 *dst8 = reinterpret_cast<uint2 *>(lds);
-    int64_t i = tid;
-    for (; i + 3 * nthreads < chunks; i += 4 * nthreads) {
-        u32x4 v[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            v[r] = __builtin_nontemporal_load(&src4[i + r * nthreads]);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const uint32_t x0 = v[r].x, x1 = v[r].y, x2 = v[r].z, x3 = v[r].w;
-            bad |= (x0 | x1 | x2 | x3) & 0xFF00FF00u;
-            uint2 o;
-            o.x = __builtin_amdgcn_perm(x1, x0, 0x06040200u);
-            o.y = __builtin_amdgcn_perm(x3, x2, 0x06040200u);
-            dst8[i + r * nthreads] = o;
-        }
-    }
-    for (; i < chunks; i += nthreads) {
-        const u32x4 v = __builtin_nontemporal_load(&src4[i]);
-        const uint32_t x0 = v.x, x1 = v.y, x2 = v.z, x3 = v.w;
-        bad |= (x0 | x1 | x2 | x3) & 0xFF00FF00u;
-        uint2 o;
-        o.x = __builtin_amdgcn_perm(x1, x0, 0x06040200u);
-        o.y = __builtin_amdgcn_perm(x3, x2, 0x06040200u);
-        dst8[i] = o;
-    }
-    for (int64_t e = (chunks << 3) + tid; e < elems; e += nthreads) {
-        const int v = src[e];
-        bad |= (v < 0 || v > 255) ? 1u : 0u;
-        lds[e] = (uint8_t)v;
-    }
-    if (ballot(bad != 0) != 0 && (tid & (kWave - 1)) == 0)
-        atomicOr(&s_bad, 1);
-    __syncthreads();
-    return s_bad == 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -707,8 +624,6 @@ __global__ __launch_bounds__(kWave) void split_ordered_kernel(int64_t S, int32_t
 // straight from the definition with the value history in global scratch;
 // the last block to finish folds every tour's slots into its sum and mean
 // ---------------------------------------------------------------------------
-constexpr int kFallbackBlocks = 64;
-
 __global__ __launch_bounds__(kWave) void fallback_final_kernel(const int16_t *__restrict__ demands,
                                                                int32_t N, int64_t S, int32_t Q,
                                                                int32_t T, int32_t *costs,
@@ -888,6 +803,14 @@ __global__ void zero_i64_kernel(int64_t *p, int32_t n)
 
 int64_t num_tiles(int64_t S) { return (S + kTile - 1) / kTile; }
 
+hipError_t launch_prep(const int32_t *tours, const int32_t *lens, int32_t T, int32_t max_len,
+                       const int32_t *dist, int32_t N, const Workspace &ws, hipStream_t stream)
+{
+    hipLaunchKernelGGL(prep_kernel, dim3(T), dim3(kPrepThreads), 0, stream, tours, lens, T,
+                       max_len, dist, N, ws);
+    return hipGetLastError();
+}
+
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int32_t ordered_pitch(int32_t max_len) { return ((max_len + 31) / 32) * 32 + 32; }
@@ -1048,9 +971,7 @@ hipError_t launch_eval(const int32_t *tours, const int32_t *lens, int32_t T, int
 {
     if (!schedule_supported(sched))
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(prep_kernel, dim3(T), dim3(kPrepThreads), 0, stream, tours, lens, T,
-                       max_len, dist, N, ws);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_prep(tours, lens, T, max_len, dist, N, ws, stream);
     if (e != hipSuccess)
         return e;
     if (ev && ev->before) {

@@ -1,0 +1,392 @@
+// split_routes.hip -- route recovery: the per-scenario minimising
+// predecessors of the split recursion and the route cut points obtained by
+// backtracking them (the giant tour is cut into routes by the split, App. A;
+// a batched DP that records its minimisers is backtracked to recover the
+// decisions, App. B).
+//
+// Recursion and potential form as in split_kernels.hip: with
+// f_p = V(p) + a_{p+1}, position i takes m_i = min over the admissible
+// window of f_p, and pred(i) is the SMALLEST admissible p with f_p = m_i
+// (among equal route costs the longest last route).  Equal f_p means equal
+// V(p) + W(p,i), since b_i is common to the window, so the tie-break is
+// exact.  V(i) is +inf exactly when m_i >= 2^29: feasible potentials stay
+// below 2^29 in magnitude under the int32 cost guard (3 n maxcost < 2^29),
+// and potentials reached only through infeasible prefixes stay above it.
+//
+// Layout (position-major, so one wave's stores per position are a single
+// 128-byte line):  pred[(i-1)*S + s]  and  cuts[(r-1)*S + s].
+//
+// Kernels:
+//   prep (shared with the evaluator, one tour);
+//   routes_tile_kernel<R,F,E>: one wave per tile of 64 scenarios, the
+//     tile's demand rows staged in LDS as bytes, the window argmin of
+//     window_argmin_asm.inc, pred written per position; then each lane
+//     walks its chain back from n (the column it just wrote, still in L2),
+//     counting the routes, and walks it again writing the route ends;
+//   routes_fallback_kernel: exact recomputation (any window length, any
+//     demand value) of the tiles the main kernel listed, then the same
+//     backtracking; its last block marks every scenario invalid when the
+//     tour or a demand failed validation.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <utility>
+
+#include "split_device.h"
+#include "split_eval.h"
+#include "split_internal.h"
+
+namespace splitk {
+
+namespace {
+
+constexpr int kFeasible = 1 << 29; // m_i below this <=> V(i) finite
+constexpr uint16_t kNoPred = 0xFFFF;
+
+#include "window_argmin_asm.inc"
+
+// Backtracking of one scenario from position n.  pcol / ccol point at the
+// scenario's column of pred / cuts (stride S).  Returns the number of
+// routes, or -1 if the chain does not descend (never for a finite V(n)).
+__device__ __forceinline__ int backtrack(const uint16_t *pcol, uint16_t *ccol, int64_t S, int n)
+{
+    int k = 0;
+    for (int i = n; i > 0;) {
+        const int p = pcol[(int64_t)(i - 1) * S];
+        if (p >= i)
+            return -1;
+        ++k;
+        i = p;
+    }
+    int r = k;
+    for (int i = n; i > 0 && r > 0;) {
+        ccol[(int64_t)(--r) * S] = (uint16_t)i;
+        const int p = pcol[(int64_t)(i - 1) * S];
+        if (p >= i)
+            break;
+        i = p;
+    }
+    return k;
+}
+
+struct RtRegs {
+    int L;          // load of positions 1..j (at the start of position j)
+    int qa;         // demand of position j+1 (arrived)
+    int2 t0, t1, t2; // table entries of positions j, j+1, j+2
+    uint64_t cp1;   // lanes rejecting d = F at position j (computed at j-1)
+    int mres;       // m of the last position relaxed
+    int ovf;        // 1 when a window reached past the ring
+    uint16_t *prow; // pred row of position j (wave-uniform), advanced by S
+};
+
+template <int R, int F, int E, int U> struct RtState {
+    __device__ __forceinline__ static bool run(int (&f)[R], int (&lq)[R], RtRegs &r,
+                                               const uint8_t *row, CInt *tab, int j0, int n,
+                                               int Q, int64_t S, int lane)
+    {
+        const int j = j0 + U;
+        if (U == 0 && j == 0)
+            return true;
+        if (j > n)
+            return false;
+        const int cj = r.t0.y;
+        const int Ln = r.L + r.qa;
+        r.qa = row[r.t2.x];
+        const int2 t3 = tab_at(tab, j + 3);
+        uint64_t cn1;
+        int a;
+        const int m = WindowArgmin<R, F, E>::template run<U>(f, lq, r.L, Ln, j, r.cp1, cn1, a,
+                                                             r.ovf);
+        r.mres = m;
+        f[U] = m + cj;
+        lq[U] = r.L + Q;
+        r.L = Ln;
+        r.cp1 = cn1;
+        r.t0 = r.t1;
+        r.t1 = r.t2;
+        r.t2 = t3;
+        r.prow[lane] = m < kFeasible ? (uint16_t)(j - a) : kNoPred;
+        r.prow += S;
+        return true;
+    }
+};
+
+template <int R, int F, int E, int... Us>
+__device__ __forceinline__ bool rt_block(int (&f)[R], int (&lq)[R], RtRegs &r, const uint8_t *row,
+                                         CInt *tab, int j0, int n, int Q, int64_t S, int lane,
+                                         std::integer_sequence<int, Us...>)
+{
+    return (RtState<R, F, E, Us>::run(f, lq, r, row, tab, j0, n, Q, S, lane) && ...);
+}
+
+// Writes pred(1..n) of the lane's scenario; returns m_n, sets ovf when a
+// window left the ring.  prow0 = pred + s0 (the tile's first column).
+template <int R, int F, int E>
+__device__ __forceinline__ int rt_lane(const uint8_t *row, CInt *tab, int n, int f0, int Q,
+                                       uint16_t *prow0, int64_t S, int lane, bool &ovf)
+{
+    int f[R], lq[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        f[i] = kInf;
+        lq[i] = kNeg;
+    }
+    f[0] = f0; // p = 0: V(0) + a_1
+    lq[0] = Q; // L_0 + Q
+    RtRegs r;
+    r.mres = kInf;
+    r.ovf = 0;
+    r.cp1 = ~0ull; // position 1 starts in the masked path
+    r.t0 = tab_at(tab, 1);
+    r.t1 = tab_at(tab, 2);
+    r.t2 = tab_at(tab, 3);
+    r.L = row[r.t0.x];
+    r.qa = row[r.t1.x];
+    r.prow = prow0;
+    for (int j0 = 0; j0 <= n; j0 += R) {
+        if (!rt_block<R, F, E>(f, lq, r, row, tab, j0, n, Q, S, lane,
+                               std::make_integer_sequence<int, R>{}))
+            break;
+    }
+    ovf = r.ovf != 0;
+    return r.mres;
+}
+
+// grid = tiles, one wave each; LDS: 64 x N demand bytes + flag word
+template <int R, int F, int E>
+__global__ __launch_bounds__(kWave) void routes_tile_kernel(
+    const int16_t *__restrict__ demands, int32_t N, int64_t S, int32_t Q,
+    int32_t *__restrict__ costs, uint16_t *pred, uint16_t *cuts, int32_t *__restrict__ nroutes,
+    Workspace ws, int32_t use_lds)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    const int64_t k = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t s0 = k * kWave;
+    const int rows = (int)min<int64_t>(kWave, S - s0);
+    bool ok = false;
+    if (use_lds) {
+        int &s_bad = *reinterpret_cast<int *>(lds + (((size_t)kWave * N + 15) & ~(size_t)15));
+        ok = stage_tile_u8(demands + s0 * N, lds, (int64_t)rows * N, lane, kWave, s_bad);
+    }
+    const TourRec rec = ws.rec[0];
+    if (rec.status != ST_OK)
+        return; // the fallback kernel's last block marks every scenario
+    if (rec.n == 0) {
+        if (lane < rows) {
+            costs[s0 + lane] = 0;
+            nroutes[s0 + lane] = 0;
+        }
+        return;
+    }
+    bool redo = true;
+    if (ok) {
+        CInt *tab = (CInt *)ws.tab;
+        bool ovf = false;
+        int m = kInf;
+        if (lane < rows)
+            m = rt_lane<R, F, E>(lds + (int64_t)lane * N, tab, rec.n, rec.f0, Q, pred + s0, S,
+                                 lane, ovf);
+        redo = ballot(ovf) != 0;
+        if (!redo && lane < rows) {
+            const int64_t s = s0 + lane;
+            if (m < kFeasible) {
+                costs[s] = m + rec.bn;
+                nroutes[s] = backtrack(pred + s, cuts + s, S, rec.n);
+            } else {
+                costs[s] = SPLIT_INF;
+                nroutes[s] = 0;
+            }
+        }
+    }
+    if (redo && lane == 0) {
+        const int slot = atomicAdd(ws.list_count, 1);
+        ws.list[slot] = (int)k;
+    }
+}
+
+// grid = kFallbackBlocks waves; exact recursion for listed tiles with
+// the value history in workspace scratch ([j][lane] per block)
+__global__ __launch_bounds__(kWave) void routes_fallback_kernel(
+    const int16_t *__restrict__ demands, int32_t N, int64_t S, int32_t Q, int32_t *costs,
+    uint16_t *pred, uint16_t *cuts, int32_t *nroutes, Workspace ws)
+{
+    const int lane = threadIdx.x;
+    const int count = *ws.list_count;
+    int *V = ws.vscratch + (int64_t)blockIdx.x * kWave * (ws.max_len + 1);
+    const TourRec rec = ws.rec[0];
+    const int n = rec.n;
+    const int2 *tab = ws.tab;
+    const int2 *ab = ws.ab;
+    for (int li = blockIdx.x; li < count && rec.status == ST_OK; li += gridDim.x) {
+        const int64_t k = ws.list[li];
+        const int64_t s0 = k * kWave;
+        const int rows = (int)min<int64_t>(kWave, S - s0);
+        bool negq = false;
+        if (lane < rows) {
+            const int64_t s = s0 + lane;
+            const int16_t *qrow = demands + s * N;
+            V[lane] = 0; // V(0)
+            for (int j = 1; j <= n; ++j) {
+                const int bj = ab[j - 1].y;
+                int best = kInf, arg = -1, load = 0;
+                for (int p = j - 1; p >= 0; --p) { // p decreasing: "<=" keeps the smallest
+                    const int q = qrow[tab[p + 1].x];
+                    negq = negq || q < 0;
+                    load += q;
+                    if (load > Q)
+                        break;
+                    const int vp = V[(int64_t)p * kWave + lane];
+                    if (vp < kInf) {
+                        const int c = vp + ab[p].x + bj;
+                        if (c <= best) {
+                            best = c;
+                            arg = p;
+                        }
+                    }
+                }
+                V[(int64_t)j * kWave + lane] = best;
+                pred[(int64_t)(j - 1) * S + s] = arg < 0 ? kNoPred : (uint16_t)arg;
+            }
+            const int v = V[(int64_t)n * kWave + lane];
+            if (v < kInf) {
+                costs[s] = v;
+                nroutes[s] = backtrack(pred + s, cuts + s, S, n);
+            } else {
+                costs[s] = SPLIT_INF;
+                nroutes[s] = 0;
+            }
+        }
+        if (ballot(negq) != 0 && lane == 0)
+            atomicOr(&ws.rec[0].status, ST_BAD_DEMAND);
+    }
+
+    int last = 0;
+    if (lane == 0) {
+        __threadfence();
+        last = atomicAdd(ws.done, 1) == (int)gridDim.x - 1;
+    }
+    last = __shfl(last, 0, kWave);
+    if (!last)
+        return;
+    __threadfence();
+    const int status =
+        __hip_atomic_load(&ws.rec[0].status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (status == ST_OK)
+        return;
+    for (int64_t s = lane; s < S; s += kWave) {
+        costs[s] = SPLIT_INF;
+        nroutes[s] = -1;
+    }
+}
+
+// ring length by capacity (longer windows for larger Q), head and exit
+// spacing as in the evaluator's defaults
+RouteVariant default_route_variant(int32_t Q)
+{
+    if (Q > 200)
+        return RouteVariant{64, 12, 4};
+    return RouteVariant{32, 6, 3};
+}
+
+RouteVariant g_route_override = {0, 0, 0};
+
+template <int R, int F, int E>
+hipError_t launch_route_tiles(const int16_t *demands, int32_t N, int64_t S, int32_t Q,
+                              int32_t *costs, uint16_t *pred, uint16_t *cuts, int32_t *nroutes,
+                              const Workspace &ws, hipStream_t stream)
+{
+    const size_t lds = (((size_t)kTile * (size_t)N + 15) & ~(size_t)15) + 16; // rows + flag
+    static int lds_limit = -1;
+    if (lds_limit < 0) {
+        int dev = 0, lim = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess)
+            e = hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (e != hipSuccess)
+            return e;
+        lim = lim < kLdsLimit ? lim : kLdsLimit;
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&routes_tile_kernel<R, F, E>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        if (e != hipSuccess)
+            return e;
+        lds_limit = lim;
+    }
+    const int use_lds = lds <= (size_t)lds_limit ? 1 : 0;
+    hipLaunchKernelGGL((routes_tile_kernel<R, F, E>), dim3((unsigned)num_tiles(S)), dim3(kWave),
+                       use_lds ? lds : 0, stream, demands, N, S, Q, costs, pred, cuts, nroutes, ws,
+                       use_lds);
+    return hipGetLastError();
+}
+
+} // namespace
+
+bool route_variant_supported(const RouteVariant &v)
+{
+#define SPLIT_RV_SUPPORTED(R_, F_, E_)                                                           \
+    if (v.ring == R_ && v.first == F_ && v.every == E_)                                          \
+        return true;
+    SPLIT_ARGMIN_VARIANTS(SPLIT_RV_SUPPORTED)
+#undef SPLIT_RV_SUPPORTED
+    return false;
+}
+
+int compiled_route_variants(RouteVariant *out, int cap)
+{
+    int n = 0;
+#define SPLIT_RV_LIST(R_, F_, E_)                                                                \
+    if (n < cap)                                                                                 \
+        out[n] = RouteVariant{R_, F_, E_};                                                       \
+    ++n;
+    SPLIT_ARGMIN_VARIANTS(SPLIT_RV_LIST)
+#undef SPLIT_RV_LIST
+    return n;
+}
+
+RouteVariant choose_route_variant(int32_t Q)
+{
+    return g_route_override.ring ? g_route_override : default_route_variant(Q);
+}
+
+size_t routes_workspace_bytes(int32_t n, int32_t N, int64_t S)
+{
+    return workspace_bytes(1, n, N, S, false);
+}
+
+hipError_t launch_routes(const int32_t *tour, int32_t n, const int32_t *dist, int32_t N,
+                         const int16_t *demands, int64_t S, int32_t Q, int32_t *costs,
+                         uint16_t *pred, uint16_t *cuts, int32_t *nroutes, const Workspace &ws,
+                         hipStream_t stream, const RouteVariant &v, const LaunchEvents *ev)
+{
+    if (!route_variant_supported(v))
+        return hipErrorInvalidValue;
+    hipError_t e = launch_prep(tour, nullptr, 1, n, dist, N, ws, stream);
+    if (e != hipSuccess)
+        return e;
+    if (ev && ev->before) {
+        e = hipEventRecord(ev->before, stream);
+        if (e != hipSuccess)
+            return e;
+    }
+#define SPLIT_RV_LAUNCH(R_, F_, E_)                                                              \
+    if (v.ring == R_ && v.first == F_ && v.every == E_)                                          \
+        e = launch_route_tiles<R_, F_, E_>(demands, N, S, Q, costs, pred, cuts, nroutes, ws,     \
+                                           stream);
+    SPLIT_ARGMIN_VARIANTS(SPLIT_RV_LAUNCH)
+#undef SPLIT_RV_LAUNCH
+    if (e != hipSuccess)
+        return e;
+    if (ev && ev->after) {
+        e = hipEventRecord(ev->after, stream);
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(routes_fallback_kernel, dim3(kFallbackBlocks), dim3(kWave), 0, stream,
+                       demands, N, S, Q, costs, pred, cuts, nroutes, ws);
+    return hipGetLastError();
+}
+
+void set_route_override(const RouteVariant &v) { g_route_override = v; }
+
+} // namespace splitk

@@ -145,3 +145,44 @@ def test_window_variants_listed_and_validated():
             binding.set_schedule(*vs[0], path=3)
     finally:
         binding.set_schedule(0)
+
+
+def test_route_variants_listed_and_validated():
+    vs = binding.list_route_variants()
+    assert vs and all(len(v) == 3 for v in vs)
+    assert {v[0] for v in vs} == {32, 64}
+    try:
+        for v in vs:
+            binding.set_route_variant(*v)
+        with pytest.raises(binding.SplitError):
+            binding.set_route_variant(32, 5, 3)
+        with pytest.raises(binding.SplitError):
+            binding.set_route_variant(48, 0, 3)
+    finally:
+        binding.set_route_variant(0)
+
+
+def test_routes_workspace_size():
+    a = binding.routes_workspace_bytes(200, 200, 1_000_000)
+    b = binding.routes_workspace_bytes(400, 400, 1_000_000)
+    assert 0 < a < b
+    assert binding.routes_workspace_bytes(0, 5, 10) > 0
+    assert binding.routes_workspace_bytes(-1, 5, 10) == 0
+    assert binding.routes_workspace_bytes(70000, 5, 10) == 0
+
+
+def test_routes_device_form_rejects_bad_arguments_before_device_work():
+    P = ctypes.c_void_p
+    fake = P(256)
+    f = binding.lib.split_routes_device
+    for n, N, S, Q in ((5, 0, 10, 3), (5, 5, 0, 3), (5, 5, 10, -2), (70000, 5, 10, 3), (-1, 5, 10, 3)):
+        rc = f(fake, n, fake, N, fake, S, Q, fake, fake, fake, fake, fake, 1 << 20, None)
+        assert rc == binding.SPLIT_EINVAL, (n, N, S, Q)
+    rc = f(fake, 5, fake, 5, P(258), 10, 3, fake, fake, fake, fake, fake, 1 << 20, None)
+    assert rc == binding.SPLIT_EINVAL and "aligned" in binding.last_error()
+    rc = f(fake, 5, fake, 5, fake, 10, 3, fake, fake, fake, fake, fake, 16, None)
+    assert rc == binding.SPLIT_EINVAL and "workspace" in binding.last_error()
+    rc = f(fake, 5, fake, 5, fake, 10, 3, fake, None, fake, fake, fake, 1 << 20, None)
+    assert rc == binding.SPLIT_EINVAL and "null" in binding.last_error()
+    rc = f(fake, 5, fake, 5, fake, 10, 3, fake, fake, fake, fake, P(300), 1 << 20, None)
+    assert rc == binding.SPLIT_EINVAL and "aligned" in binding.last_error()
