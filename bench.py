@@ -9,9 +9,10 @@ every scenario, exact fallback, per-tour sum and mean).
 
 Also reported on the same line: scenarios/s, the main kernel's roofline
 (int32 VALU ops, one per Bellman cell, against the chip's VALU peak), the
-CPU oracle's throughput on a bounded sample of the same workload, and the
-batched form (256 ragged tours in one captured graph vs one launch per
-tour).
+CPU oracle's throughput on a bounded sample of the same workload, route
+recovery of the same tour (predecessors and cut points of every scenario),
+the batched form (256 ragged tours in one captured graph vs one launch per
+tour) and the served form.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -31,7 +32,8 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2602_05179_amd/csrc/split_kernels.hip",
                   "paper_2602_05179_amd/csrc/window_min_asm.inc",
-                  "paper_2602_05179_amd/csrc/split_internal.h"]
+                  "paper_2602_05179_amd/csrc/split_internal.h",
+                  "paper_2602_05179_amd/csrc/split_device.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_split_tile_n200_S1e6.txt")
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "sq_counters_split_tile_n200_S1e6.md")
 
@@ -173,6 +175,48 @@ def batched_vs_plain(torch, binding, W, reps):
     }
 
 
+def route_recovery(torch, binding, t, d, q, inst, cells, eval_costs, steps, warmup):
+    """Route recovery of the headline tour over the same S scenarios: the
+    smallest minimising predecessor of every position and the route cut
+    points of every scenario, inputs resident in HBM."""
+    dev = q.device
+    n, S = int(t.numel()), inst.S
+    out = binding.RouteOutputs(n, S, dev)
+    ws = torch.empty(binding.routes_workspace_bytes(n, inst.N, S), dtype=torch.uint8, device=dev)
+
+    def step():
+        binding.split_routes_device(t, d, q, inst.Q, out=out, workspace=ws)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    binding.profile_read()
+    binding.profile_enable(True)
+    sec = timed_steps(torch, step, steps, 0)
+    kms, launches = binding.profile_read()
+    binding.profile_enable(False)
+    kernel_s = kms / 1e3 / max(launches, 1)
+    routes_mean = float(out.nroutes.double().mean().item())
+    # demands read once; pred for every position; cuts up to nroutes; costs and counts
+    alg_bytes = q.numel() * 2 + n * S * 2 + routes_mean * S * 2 + S * 8
+    return {
+        "workload": "route recovery of the same tour: n=%d, S=%d, Q=%d" % (n, S, inst.Q),
+        "ms_per_call": sec * 1e3,
+        "cells_per_s": cells / sec,
+        "scenarios_per_s": S / sec,
+        "kernel": "routes_tile_kernel",
+        "kernel_ms": kernel_s * 1e3,
+        "kernel_cells_per_s": cells / kernel_s,
+        "frac_valu_peak": cells / kernel_s / 1e12 / VALU_PEAK_TOPS,
+        "algorithmic_bytes": alg_bytes,
+        "achieved_gbs": alg_bytes / kernel_s / 1e9,
+        "hbm_frac": alg_bytes / kernel_s / 1e9 / HBM_PEAK_GBS,
+        "mean_routes": routes_mean,
+        "kernel_vs_eval_kernel": None,
+        "costs_equal_eval": bool(torch.equal(out.costs, eval_costs)),
+    }
+
+
 def served(torch, binding, W, num_requests, pool_size, budget_gb, seed=5):
     """Served stream: Poisson arrivals of single-tour requests (n ~ U{50..1000},
     S ~ 10^U(3,5), Q in {80,150,300}) drawn from a pool of distinct instances
@@ -244,6 +288,7 @@ def main():
     ap.add_argument("--scenarios", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-routes", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-requests", type=int, default=10_000)
     ap.add_argument("--served-pool", type=int, default=32)
@@ -348,6 +393,11 @@ def main():
                                 if valu_insts else None),
         },
     }
+    if not args.no_routes:
+        log("route recovery (n=%d, S=%d)" % (n, S))
+        rr = route_recovery(torch, binding, t, d, q, inst, cells, out.costs[0], args.steps, args.warmup)
+        rr["kernel_vs_eval_kernel"] = rr["kernel_ms"] / (kernel_s * 1e3)
+        result["routes"] = rr
     if not args.no_batched:
         log("batched vs plain (256 ragged tours, S=10^4)")
         result["batched"] = batched_vs_plain(torch, binding, W, reps=20)

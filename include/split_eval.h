@@ -164,15 +164,19 @@ int split_routes_device(const int32_t *d_tour, int32_t n, const int32_t *d_dist,
 
 /*
  * split_routes_set_variant -- window variant of the route-recovery kernel
- * for every later call in the process: ring = 32 or 64 registers, first =
- * head cells validated by one check issued a position early (0 = none),
- * every = masked cells between exits on an empty lane mask.  ring = 0
- * restores the automatic choice (by Q).  SPLIT_EINVAL for a variant that is
- * not compiled in.  split_routes_list_variants writes up to `cap` entries
- * of 3 int32 {ring, first, every} to `out` (host memory) and returns the
- * number compiled in.  Not thread-safe against concurrent calls.
+ * for every later call in the process, with the meaning of
+ * split_set_schedule's first four arguments (ring 32 or 64, first head
+ * group, later head groups, exit spacing).  ring = 0 restores the automatic
+ * choice (by Q).  SPLIT_EINVAL for a variant that is not compiled in.
+ * The recursion carries each potential and its predecessor in one int32
+ * key when the tour's costs allow it (3 n maxcost < 2^23 for ring 32,
+ * 2^22 for ring 64); other tours (up to the general 2^29 guard) take a
+ * slower path of the same ring length that tracks the predecessor per
+ * cell.  split_routes_list_variants writes up to `cap` entries of 4 int32
+ * {ring, first, group, every} to `out` (host memory) and returns the number
+ * compiled in.  Not thread-safe against concurrent calls.
  */
-int split_routes_set_variant(int32_t ring, int32_t first, int32_t every);
+int split_routes_set_variant(int32_t ring, int32_t first, int32_t group, int32_t every);
 int split_routes_list_variants(int32_t *out, int32_t cap);
 
 /*

@@ -127,7 +127,7 @@ def _load():
     lib.split_routes_device.restype = ctypes.c_int
     lib.split_routes_device.argtypes = [P, i32, P, i32, P, i64, i32, P, P, P, P, P, sz, P]
     lib.split_routes_set_variant.restype = ctypes.c_int
-    lib.split_routes_set_variant.argtypes = [i32, i32, i32]
+    lib.split_routes_set_variant.argtypes = [i32, i32, i32, i32]
     lib.split_routes_list_variants.restype = ctypes.c_int
     lib.split_routes_list_variants.argtypes = [ctypes.POINTER(i32), i32]
     return lib
@@ -288,19 +288,19 @@ def split_count_cells_device(tours, lens, demands, N, Q, *, stream=None):
 # route recovery (one giant tour, device tensors)
 # ---------------------------------------------------------------------------
 def list_route_variants():
-    """Compiled route-recovery window variants as (ring, first, every) tuples."""
+    """Compiled route-recovery window variants as (ring, first, group, every) tuples."""
     n = lib.split_routes_list_variants(None, 0)
-    buf = (ctypes.c_int32 * (3 * n))()
+    buf = (ctypes.c_int32 * (4 * n))()
     lib.split_routes_list_variants(buf, n)
-    return [tuple(int(buf[3 * i + k]) for k in range(3)) for i in range(n)]
+    return [tuple(int(buf[4 * i + k]) for k in range(4)) for i in range(n)]
 
 
 ROUTE_VARIANTS = list_route_variants()
 
 
-def set_route_variant(ring: int, first: int = 0, every: int = 3):
+def set_route_variant(ring: int, first: int = 8, group: int = 3, every: int = 3):
     """Force the route-recovery window variant; ring=0 restores the automatic choice."""
-    _check(lib.split_routes_set_variant(int(ring), int(first), int(every)))
+    _check(lib.split_routes_set_variant(int(ring), int(first), int(group), int(every)))
 
 
 def routes_workspace_bytes(n: int, N: int, S: int) -> int:

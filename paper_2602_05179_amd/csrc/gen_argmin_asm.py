@@ -35,8 +35,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 INF_IMM = "2.0"  # inline constant with bit pattern 0x40000000 = 2^30
 # (first, every) schedules compiled for each ring length
 VARIANTS = {
-    32: ((0, 3), (6, 3), (8, 3)),
-    64: ((0, 4), (12, 4), (16, 4)),
+    32: ((6, 3),),
+    64: ((12, 4),),
 }
 RINGS = tuple(VARIANTS)
 

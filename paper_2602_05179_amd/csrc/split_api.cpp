@@ -305,17 +305,17 @@ size_t split_routes_workspace_bytes(int32_t n, int32_t N, int64_t S)
     return splitk::routes_workspace_bytes(n, N, S);
 }
 
-int split_routes_set_variant(int32_t ring, int32_t first, int32_t every)
+int split_routes_set_variant(int32_t ring, int32_t first, int32_t group, int32_t every)
 {
     g_err[0] = 0;
     if (ring == 0) {
-        splitk::set_route_override(splitk::RouteVariant{0, 0, 0});
+        splitk::set_route_override(splitk::RouteVariant{0, 0, 0, 0});
         return SPLIT_OK;
     }
-    const splitk::RouteVariant v{ring, first, every};
+    const splitk::RouteVariant v{ring, first, group, every};
     if (!splitk::route_variant_supported(v))
-        return fail(SPLIT_EINVAL, "unsupported route variant ring=%d first=%d every=%d", ring,
-                    first, every);
+        return fail(SPLIT_EINVAL, "unsupported route variant ring=%d first=%d group=%d every=%d",
+                    ring, first, group, every);
     splitk::set_route_override(v);
     return SPLIT_OK;
 }
@@ -328,9 +328,10 @@ int split_routes_list_variants(int32_t *out, int32_t cap)
     splitk::RouteVariant v[64];
     const int n = splitk::compiled_route_variants(v, 64);
     for (int i = 0; i < n && i < cap && i < 64; ++i) {
-        out[3 * i] = v[i].ring;
-        out[3 * i + 1] = v[i].first;
-        out[3 * i + 2] = v[i].every;
+        out[4 * i] = v[i].ring;
+        out[4 * i + 1] = v[i].first;
+        out[4 * i + 2] = v[i].group;
+        out[4 * i + 3] = v[i].every;
     }
     return n;
 }

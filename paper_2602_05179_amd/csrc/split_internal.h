@@ -14,6 +14,7 @@ struct TourRec {
     int f0;     // first potential: V(0) + a_1 = c[0][sigma_1]
     int bn;     // b_n = D_n + c[sigma_n][0]; V(n) = m_n + b_n
     int status; // 0 ok, else a bit set of validation failures
+    int maxc;   // largest travel cost on the tour's route legs
 };
 
 // Device scratch carved from one caller- or library-owned allocation.
@@ -98,8 +99,9 @@ int compiled_schedules(Schedule *out, int cap);
 // Route recovery (one giant tour over S scenarios).
 struct RouteVariant {
     int ring;  // register ring length R (32 or 64)
-    int first; // head cells validated by one check issued a position early (0 = none)
-    int every; // masked cells between exits on an empty EXEC
+    int first; // cells of the first head group (its check is issued one position early)
+    int group; // cells of each later head group (0 = none)
+    int every; // tail cells between exits on an empty EXEC
 };
 bool route_variant_supported(const RouteVariant &v);
 int compiled_route_variants(RouteVariant *out, int cap);

@@ -229,6 +229,7 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(
         r.f0 = (int)s_red[0]; // a_1 = c[0][sigma_1] since D_1 = 0
         r.bn = nn > 0 ? ab[nn - 1].y : 0;
         r.status = allbad ? ST_BAD_TOUR : ST_OK;
+        r.maxc = allmax;
         ws.rec[t] = r;
     }
 }

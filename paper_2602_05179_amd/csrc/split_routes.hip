@@ -9,20 +9,34 @@
 // window of f_p, and pred(i) is the SMALLEST admissible p with f_p = m_i
 // (among equal route costs the longest last route).  Equal f_p means equal
 // V(p) + W(p,i), since b_i is common to the window, so the tie-break is
-// exact.  V(i) is +inf exactly when m_i >= 2^29: feasible potentials stay
-// below 2^29 in magnitude under the int32 cost guard (3 n maxcost < 2^29),
-// and potentials reached only through infeasible prefixes stay above it.
+// exact.
+//
+// Packed keys (the main path).  Each ring slot holds
+//   K_p = f_p * 2^B + (p - base),   B = 6 for a ring of 32, 7 for 64,
+// where base is wave-uniform and advances by R at every block of R
+// positions (all ring keys are rebased by -R there; a live key's offset is
+// then at least R, so no borrow reaches the potential).  Offsets of the
+// window lie in [0, 2R), so a plain minimum over keys yields the minimum
+// potential and, among equal potentials, the smallest p: the evaluator's
+// masked window minimum (window_min_asm.inc) runs unchanged on keys.  This
+// needs |f| < 2^(29-B), i.e. 3 n maxcost < 2^(29-B) for the tour; feasible
+// keys then stay below 2^29 and keys reached only through infeasible
+// prefixes (the empty-window sentinel 2^30) stay above it, below 2^31.
+// Tours past that bound take the wide path: potentials unpacked and the
+// argmin tracked per cell (window_argmin_asm.inc), under the evaluator's
+// own guard 3 n maxcost < 2^29.
 //
 // Layout (position-major, so one wave's stores per position are a single
 // 128-byte line):  pred[(i-1)*S + s]  and  cuts[(r-1)*S + s].
 //
 // Kernels:
 //   prep (shared with the evaluator, one tour);
-//   routes_tile_kernel<R,F,E>: one wave per tile of 64 scenarios, the
-//     tile's demand rows staged in LDS as bytes, the window argmin of
-//     window_argmin_asm.inc, pred written per position; then each lane
-//     walks its chain back from n (the column it just wrote, still in L2),
-//     counting the routes, and walks it again writing the route ends;
+//   routes_key_kernel<R,F,G,E> / routes_wide_kernel<R,F,E>: one wave per
+//     tile of 64 scenarios (each returns at once unless the tour takes its
+//     path), the tile's demand rows staged in LDS as bytes, pred written per
+//     position; then each lane walks its chain back from n (the column it
+//     just wrote, still in L2), counting the routes, and walks it again
+//     writing the route ends;
 //   routes_fallback_kernel: exact recomputation (any window length, any
 //     demand value) of the tiles the main kernel listed, then the same
 //     backtracking; its last block marks every scenario invalid when the
@@ -45,6 +59,15 @@ constexpr int kFeasible = 1 << 29; // m_i below this <=> V(i) finite
 constexpr uint16_t kNoPred = 0xFFFF;
 
 #include "window_argmin_asm.inc"
+#include "window_min_asm.inc"
+
+template <int R> constexpr int key_shift() { return R == 32 ? 6 : 7; }
+
+// the tour's potentials fit packed keys of shift B
+__device__ __forceinline__ bool keys_fit(const TourRec &rec, int B)
+{
+    return (long long)3 * rec.n * rec.maxc < (1LL << (29 - B));
+}
 
 // Backtracking of one scenario from position n.  pcol / ccol point at the
 // scenario's column of pred / cuts (stride S).  Returns the number of
@@ -153,26 +176,168 @@ __device__ __forceinline__ int rt_lane(const uint8_t *row, CInt *tab, int n, int
     return r.mres;
 }
 
-// grid = tiles, one wave each; LDS: 64 x N demand bytes + flag word
-template <int R, int F, int E>
-__global__ __launch_bounds__(kWave) void routes_tile_kernel(
-    const int16_t *__restrict__ demands, int32_t N, int64_t S, int32_t Q,
-    int32_t *__restrict__ costs, uint16_t *pred, uint16_t *cuts, int32_t *__restrict__ nroutes,
-    Workspace ws, int32_t use_lds)
+// ---------------------------------------------------------------------------
+// packed-key recursion
+// ---------------------------------------------------------------------------
+struct RkRegs {
+    int L;           // load of positions 1..j (at the start of position j)
+    int qa;          // demand of position j+1 (arrived)
+    int2 t0, t1, t2; // table entries of positions j, j+1, j+2
+    uint64_t cp1;    // lanes rejecting d = F at position j (computed at j-1)
+    uint64_t cp2;    // lanes rejecting d = F + G at position j (computed at j-1)
+    int mres;        // key minimum of the last position relaxed
+    int ovf;         // 1 when a window reached past the ring
+    int base;        // key offset origin of the current block (wave-uniform)
+    uint16_t *prow;  // pred row of position j (wave-uniform), advanced by S
+};
+
+template <int R, int F, int G, int E, int U> struct RkState {
+    __device__ __forceinline__ static bool run(int (&K)[R], int (&lq)[R], RkRegs &r,
+                                               const uint8_t *row, CInt *tab, int j0, int n,
+                                               int Q, int64_t S, int lane)
+    {
+        constexpr int B = key_shift<R>();
+        constexpr int M = (1 << B) - 1;
+        const int j = j0 + U;
+        if (j > n)
+            return false;
+        if (U == 0) {
+            if (j == 0)
+                return true;
+#pragma unroll
+            for (int i = 0; i < R; ++i) // new block: offsets of the live keys drop by R
+                K[i] -= R;
+            r.base += R;
+        }
+        const int cj = r.t0.y;
+        const int Ln = r.L + r.qa;
+        r.qa = row[r.t2.x];
+        const int2 t3 = tab_at(tab, j + 3);
+        uint64_t cn1, cn2;
+        const int km = WindowMin<R, F, G, E>::template run<U>(K, lq, r.L, Ln, j, r.cp1, r.cp2,
+                                                              cn1, cn2, r.ovf);
+        r.mres = km;
+        // K_j = (m + c_j) * 2^B + (j - base), with m * 2^B = km & ~M
+        K[U] = (km & ~M) + ((cj << B) + (j - r.base));
+        lq[U] = r.L + Q;
+        r.L = Ln;
+        r.cp1 = cn1;
+        r.cp2 = cn2;
+        r.t0 = r.t1;
+        r.t1 = r.t2;
+        r.t2 = t3;
+        r.prow[lane] = km < kFeasible ? (uint16_t)(r.base + (km & M)) : kNoPred;
+        r.prow += S;
+        return true;
+    }
+};
+
+template <int R, int F, int G, int E, int... Us>
+__device__ __forceinline__ bool rk_block(int (&K)[R], int (&lq)[R], RkRegs &r, const uint8_t *row,
+                                         CInt *tab, int j0, int n, int Q, int64_t S, int lane,
+                                         std::integer_sequence<int, Us...>)
+{
+    return (RkState<R, F, G, E, Us>::run(K, lq, r, row, tab, j0, n, Q, S, lane) && ...);
+}
+
+// Writes pred(1..n) of the lane's scenario; returns V(n) (kInf if +inf),
+// sets ovf when a window left the ring.
+template <int R, int F, int G, int E>
+__device__ __forceinline__ int rk_lane(const uint8_t *row, CInt *tab, const TourRec &rec, int Q,
+                                       uint16_t *prow0, int64_t S, int lane, bool &ovf)
+{
+    constexpr int B = key_shift<R>();
+    int K[R], lq[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        K[i] = kInf;
+        lq[i] = kNeg;
+    }
+    RkRegs r;
+    r.base = -R;
+    K[0] = (rec.f0 << B) + (0 - r.base); // p = 0: V(0) + a_1
+    lq[0] = Q;                           // L_0 + Q
+    r.mres = kInf;
+    r.ovf = 0;
+    r.cp1 = ~0ull; // position 1 starts in the tail
+    r.cp2 = ~0ull;
+    r.t0 = tab_at(tab, 1);
+    r.t1 = tab_at(tab, 2);
+    r.t2 = tab_at(tab, 3);
+    r.L = row[r.t0.x];
+    r.qa = row[r.t1.x];
+    r.prow = prow0;
+    const int n = rec.n;
+    for (int j0 = 0; j0 <= n; j0 += R) {
+        if (!rk_block<R, F, G, E>(K, lq, r, row, tab, j0, n, Q, S, lane,
+                                  std::make_integer_sequence<int, R>{}))
+            break;
+    }
+    ovf = r.ovf != 0;
+    return r.mres < kFeasible ? (r.mres >> B) + rec.bn : kInf;
+}
+
+// Backtracking of a tile after the recursion, with one walk per lane: the
+// chain is followed through the pred column the lane just wrote (still in
+// L2), each route end is marked in a bitmask in LDS ([W][64] words, W =
+// ceil(n/32); the demand bytes are dead by then), and a scan of the bitmask
+// in increasing position writes the cut points in order, so the number of
+// routes need not be known before the first one is written.  Each lane
+// reads and writes only its own LDS column.  Returns the number of routes
+// of the lane (0 if `chain` is false, -1 if the chain does not descend,
+// which a finite V(n) excludes).
+__device__ __forceinline__ int lds_words(int n) { return (n + 31) >> 5; }
+
+__device__ __forceinline__ int backtrack_tile(const uint16_t *pcol, uint16_t *ccol, int64_t S,
+                                              int n, int lane, bool chain, uint8_t *lds)
+{
+    const int W = lds_words(n);
+    uint32_t *bits = reinterpret_cast<uint32_t *>(lds) + lane;
+    for (int w = 0; w < W; ++w)
+        bits[w * kWave] = 0;
+    if (!chain)
+        return 0;
+    for (int i = n; i > 0;) {
+        bits[((i - 1) >> 5) * kWave] |= 1u << ((i - 1) & 31);
+        const int p = pcol[(int64_t)(i - 1) * S];
+        if (p >= i)
+            return -1;
+        i = p;
+    }
+    int r = 0;
+    for (int w = 0; w < W; ++w) {
+        uint32_t word = bits[w * kWave];
+        while (word) {
+            const int b = __builtin_ctz(word);
+            word &= word - 1;
+            ccol[(int64_t)(r++) * S] = (uint16_t)(32 * w + b + 1);
+        }
+    }
+    return r;
+}
+
+// Tile body shared by the key and the wide kernel: stage the tile, run the
+// lane recursion, backtrack, or list the tile for the exact fallback.
+// KEYS: packed keys with ring R and window variant (F, G, E); otherwise the
+// per-cell argmin with ring R and (F, E), serving the tours whose costs are
+// too wide for keys of key_bits.
+template <bool KEYS, int R, int F, int G, int E>
+__device__ __forceinline__ void routes_tile(const int16_t *__restrict__ demands, int32_t N,
+                                            int64_t S, int32_t Q, int32_t *__restrict__ costs,
+                                            uint16_t *pred, uint16_t *cuts,
+                                            int32_t *__restrict__ nroutes, const Workspace &ws,
+                                            int32_t lds_bytes, int key_bits)
 {
     extern __shared__ __align__(16) uint8_t lds[];
+    const TourRec rec = ws.rec[0];
+    if (rec.status != ST_OK)
+        return; // the fallback kernel's last block marks every scenario
+    if (keys_fit(rec, key_bits) != KEYS)
+        return; // the other kernel serves this tour
     const int64_t k = blockIdx.x;
     const int lane = threadIdx.x;
     const int64_t s0 = k * kWave;
     const int rows = (int)min<int64_t>(kWave, S - s0);
-    bool ok = false;
-    if (use_lds) {
-        int &s_bad = *reinterpret_cast<int *>(lds + (((size_t)kWave * N + 15) & ~(size_t)15));
-        ok = stage_tile_u8(demands + s0 * N, lds, (int64_t)rows * N, lane, kWave, s_bad);
-    }
-    const TourRec rec = ws.rec[0];
-    if (rec.status != ST_OK)
-        return; // the fallback kernel's last block marks every scenario
     if (rec.n == 0) {
         if (lane < rows) {
             costs[s0 + lane] = 0;
@@ -180,23 +345,38 @@ __global__ __launch_bounds__(kWave) void routes_tile_kernel(
         }
         return;
     }
+    bool ok = false;
+    if (lds_bytes) {
+        int &s_bad = *reinterpret_cast<int *>(lds + (((size_t)kWave * N + 15) & ~(size_t)15));
+        ok = stage_tile_u8(demands + s0 * N, lds, (int64_t)rows * N, lane, kWave, s_bad);
+    }
     bool redo = true;
     if (ok) {
         CInt *tab = (CInt *)ws.tab;
         bool ovf = false;
-        int m = kInf;
-        if (lane < rows)
-            m = rt_lane<R, F, E>(lds + (int64_t)lane * N, tab, rec.n, rec.f0, Q, pred + s0, S,
-                                 lane, ovf);
-        redo = ballot(ovf) != 0;
-        if (!redo && lane < rows) {
-            const int64_t s = s0 + lane;
-            if (m < kFeasible) {
-                costs[s] = m + rec.bn;
-                nroutes[s] = backtrack(pred + s, cuts + s, S, rec.n);
+        int v = kInf;
+        if (lane < rows) {
+            const uint8_t *row = lds + (int64_t)lane * N;
+            if constexpr (KEYS) {
+                v = rk_lane<R, F, G, E>(row, tab, rec, Q, pred + s0, S, lane, ovf);
             } else {
-                costs[s] = SPLIT_INF;
-                nroutes[s] = 0;
+                const int m = rt_lane<R, F, E>(row, tab, rec.n, rec.f0, Q, pred + s0, S, lane, ovf);
+                v = m < kFeasible ? m + rec.bn : kInf;
+            }
+        }
+        redo = ballot(ovf) != 0;
+        if (!redo) {
+            const int64_t s = s0 + lane;
+            const bool live = lane < rows, fin = v < kInf;
+            if (live)
+                costs[s] = fin ? v : SPLIT_INF;
+            if (live) {
+                int nr = 0;
+                if (lds_words(rec.n) * 4 * kWave <= lds_bytes)
+                    nr = backtrack_tile(pred + s, cuts + s, S, rec.n, lane, fin, lds);
+                else if (fin)
+                    nr = backtrack(pred + s, cuts + s, S, rec.n);
+                nroutes[s] = nr;
             }
         }
     }
@@ -204,6 +384,29 @@ __global__ __launch_bounds__(kWave) void routes_tile_kernel(
         const int slot = atomicAdd(ws.list_count, 1);
         ws.list[slot] = (int)k;
     }
+}
+
+// grid = tiles, one wave each; LDS: 64 x N demand bytes + flag word.
+// Serves tours whose potentials fit packed keys of this ring.
+template <int R, int F, int G, int E>
+__global__ __launch_bounds__(kWave) void routes_key_kernel(
+    const int16_t *__restrict__ demands, int32_t N, int64_t S, int32_t Q,
+    int32_t *__restrict__ costs, uint16_t *pred, uint16_t *cuts, int32_t *__restrict__ nroutes,
+    Workspace ws, int32_t lds_bytes)
+{
+    routes_tile<true, R, F, G, E>(demands, N, S, Q, costs, pred, cuts, nroutes, ws, lds_bytes,
+                                  key_shift<R>());
+}
+
+// Same grid and LDS; serves the tours that keys of key_bits cannot hold.
+template <int R, int F, int E>
+__global__ __launch_bounds__(kWave) void routes_wide_kernel(
+    const int16_t *__restrict__ demands, int32_t N, int64_t S, int32_t Q,
+    int32_t *__restrict__ costs, uint16_t *pred, uint16_t *cuts, int32_t *__restrict__ nroutes,
+    Workspace ws, int32_t lds_bytes, int32_t key_bits)
+{
+    routes_tile<false, R, F, 0, E>(demands, N, S, Q, costs, pred, cuts, nroutes, ws, lds_bytes,
+                                   key_bits);
 }
 
 // grid = kFallbackBlocks waves; exact recursion for listed tiles with
@@ -281,42 +484,75 @@ __global__ __launch_bounds__(kWave) void routes_fallback_kernel(
     }
 }
 
-// ring length by capacity (longer windows for larger Q), head and exit
-// spacing as in the evaluator's defaults
+// Packed-key variants compiled in (each a window variant of the evaluator),
+// and the wide-path argmin variant that backs each ring length.
+#define SPLIT_ROUTE_KEY_VARIANTS(X) X(32, 6, 3, 3) X(32, 8, 3, 3) X(32, 8, 0, 4) X(64, 16, 4, 4)
+
+template <int R> struct WideOf;
+template <> struct WideOf<32> {
+    static constexpr int F = 6, E = 3;
+};
+template <> struct WideOf<64> {
+    static constexpr int F = 12, E = 4;
+};
+
+// ring length by capacity (longer windows for larger Q); head and exit
+// spacing from measured sweeps at n=200, S=10^6 (Q = 80, 150, 300)
 RouteVariant default_route_variant(int32_t Q)
 {
     if (Q > 200)
-        return RouteVariant{64, 12, 4};
-    return RouteVariant{32, 6, 3};
+        return RouteVariant{64, 16, 4, 4};
+    return RouteVariant{32, 8, 0, 4};
 }
 
-RouteVariant g_route_override = {0, 0, 0};
+RouteVariant g_route_override = {0, 0, 0, 0};
 
-template <int R, int F, int E>
-hipError_t launch_route_tiles(const int16_t *demands, int32_t N, int64_t S, int32_t Q,
-                              int32_t *costs, uint16_t *pred, uint16_t *cuts, int32_t *nroutes,
-                              const Workspace &ws, hipStream_t stream)
+// Allows a kernel the LDS limit of the device once; returns that limit.
+hipError_t allow_lds(const void *kernel, int *limit)
 {
-    const size_t lds = (((size_t)kTile * (size_t)N + 15) & ~(size_t)15) + 16; // rows + flag
-    static int lds_limit = -1;
-    if (lds_limit < 0) {
-        int dev = 0, lim = 0;
-        hipError_t e = hipGetDevice(&dev);
-        if (e == hipSuccess)
-            e = hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-        if (e != hipSuccess)
-            return e;
-        lim = lim < kLdsLimit ? lim : kLdsLimit;
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&routes_tile_kernel<R, F, E>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-        if (e != hipSuccess)
-            return e;
-        lds_limit = lim;
-    }
-    const int use_lds = lds <= (size_t)lds_limit ? 1 : 0;
-    hipLaunchKernelGGL((routes_tile_kernel<R, F, E>), dim3((unsigned)num_tiles(S)), dim3(kWave),
-                       use_lds ? lds : 0, stream, demands, N, S, Q, costs, pred, cuts, nroutes, ws,
-                       use_lds);
+    int dev = 0, lim = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess)
+        return e;
+    lim = lim < kLdsLimit ? lim : kLdsLimit;
+    e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if (e == hipSuccess)
+        *limit = lim;
+    return e;
+}
+
+// Launches the key kernel and the wide kernel of ring R; the one that does
+// not serve the tour returns at once.
+template <int R, int F, int G, int E>
+hipError_t launch_route_tiles(int32_t n, const int16_t *demands, int32_t N, int64_t S,
+                              int32_t Q, int32_t *costs, uint16_t *pred, uint16_t *cuts,
+                              int32_t *nroutes, const Workspace &ws, hipStream_t stream)
+{
+    constexpr int WF = WideOf<R>::F, WE = WideOf<R>::E;
+    // demand tile + flag word, and at least room for the backtracking bitmask
+    const size_t tile = (((size_t)kTile * (size_t)N + 15) & ~(size_t)15) + 16;
+    const size_t bits = (size_t)((n + 31) / 32) * 4 * kTile;
+    const size_t lds = tile > bits ? tile : bits;
+    static int lim_key = -1, lim_wide = -1;
+    hipError_t e = hipSuccess;
+    if (lim_key < 0)
+        e = allow_lds(reinterpret_cast<const void *>(&routes_key_kernel<R, F, G, E>), &lim_key);
+    if (e == hipSuccess && lim_wide < 0)
+        e = allow_lds(reinterpret_cast<const void *>(&routes_wide_kernel<R, WF, WE>), &lim_wide);
+    if (e != hipSuccess)
+        return e;
+    const int32_t lds_bytes = lds <= (size_t)lim_key && lds <= (size_t)lim_wide ? (int32_t)lds : 0;
+    const dim3 grid((unsigned)num_tiles(S));
+    hipLaunchKernelGGL((routes_key_kernel<R, F, G, E>), grid, dim3(kWave), (size_t)lds_bytes,
+                       stream, demands, N, S, Q, costs, pred, cuts, nroutes, ws, lds_bytes);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL((routes_wide_kernel<R, WF, WE>), grid, dim3(kWave), (size_t)lds_bytes,
+                       stream, demands, N, S, Q, costs, pred, cuts, nroutes, ws, lds_bytes,
+                       (int32_t)key_shift<R>());
     return hipGetLastError();
 }
 
@@ -324,10 +560,10 @@ hipError_t launch_route_tiles(const int16_t *demands, int32_t N, int64_t S, int3
 
 bool route_variant_supported(const RouteVariant &v)
 {
-#define SPLIT_RV_SUPPORTED(R_, F_, E_)                                                           \
-    if (v.ring == R_ && v.first == F_ && v.every == E_)                                          \
+#define SPLIT_RV_SUPPORTED(R_, F_, G_, E_)                                                       \
+    if (v.ring == R_ && v.first == F_ && v.group == G_ && v.every == E_)                         \
         return true;
-    SPLIT_ARGMIN_VARIANTS(SPLIT_RV_SUPPORTED)
+    SPLIT_ROUTE_KEY_VARIANTS(SPLIT_RV_SUPPORTED)
 #undef SPLIT_RV_SUPPORTED
     return false;
 }
@@ -335,11 +571,11 @@ bool route_variant_supported(const RouteVariant &v)
 int compiled_route_variants(RouteVariant *out, int cap)
 {
     int n = 0;
-#define SPLIT_RV_LIST(R_, F_, E_)                                                                \
+#define SPLIT_RV_LIST(R_, F_, G_, E_)                                                            \
     if (n < cap)                                                                                 \
-        out[n] = RouteVariant{R_, F_, E_};                                                       \
+        out[n] = RouteVariant{R_, F_, G_, E_};                                                   \
     ++n;
-    SPLIT_ARGMIN_VARIANTS(SPLIT_RV_LIST)
+    SPLIT_ROUTE_KEY_VARIANTS(SPLIT_RV_LIST)
 #undef SPLIT_RV_LIST
     return n;
 }
@@ -369,11 +605,11 @@ hipError_t launch_routes(const int32_t *tour, int32_t n, const int32_t *dist, in
         if (e != hipSuccess)
             return e;
     }
-#define SPLIT_RV_LAUNCH(R_, F_, E_)                                                              \
-    if (v.ring == R_ && v.first == F_ && v.every == E_)                                          \
-        e = launch_route_tiles<R_, F_, E_>(demands, N, S, Q, costs, pred, cuts, nroutes, ws,     \
-                                           stream);
-    SPLIT_ARGMIN_VARIANTS(SPLIT_RV_LAUNCH)
+#define SPLIT_RV_LAUNCH(R_, F_, G_, E_)                                                          \
+    if (v.ring == R_ && v.first == F_ && v.group == G_ && v.every == E_)                         \
+        e = launch_route_tiles<R_, F_, G_, E_>(n, demands, N, S, Q, costs, pred, cuts, nroutes,  \
+                                               ws, stream);
+    SPLIT_ROUTE_KEY_VARIANTS(SPLIT_RV_LAUNCH)
 #undef SPLIT_RV_LAUNCH
     if (e != hipSuccess)
         return e;

@@ -149,15 +149,16 @@ def test_window_variants_listed_and_validated():
 
 def test_route_variants_listed_and_validated():
     vs = binding.list_route_variants()
-    assert vs and all(len(v) == 3 for v in vs)
+    assert vs and all(len(v) == 4 for v in vs)
     assert {v[0] for v in vs} == {32, 64}
+    assert set(vs) <= set(binding.list_variants())  # each is a window variant of the evaluator
     try:
         for v in vs:
             binding.set_route_variant(*v)
         with pytest.raises(binding.SplitError):
-            binding.set_route_variant(32, 5, 3)
+            binding.set_route_variant(32, 5, 0, 3)
         with pytest.raises(binding.SplitError):
-            binding.set_route_variant(48, 0, 3)
+            binding.set_route_variant(48, 8, 3, 3)
     finally:
         binding.set_route_variant(0)
 

@@ -98,7 +98,7 @@ def test_routes_paper_scale_full(binding):
     assert np.array_equal(ev.costs.cpu().numpy()[0], got["costs"])
 
 
-@pytest.mark.parametrize("variant_idx", range(6))
+@pytest.mark.parametrize("variant_idx", range(4))
 @pytest.mark.parametrize("Q", [100, 300])
 def test_every_route_variant(binding, variant_idx, Q):
     vs = binding.ROUTE_VARIANTS
@@ -136,9 +136,28 @@ def test_routes_ties(binding, kind):
 # ----------------------------------------------------------------------------
 # the exact fallback: windows past the ring, demands past a byte, large pools
 # ----------------------------------------------------------------------------
+@pytest.mark.parametrize("scale,Q", [(100, 100), (100, 300), (14, 300), (14, 100)])
+def test_routes_wide_costs(binding, scale, Q):
+    """Costs too wide for packed keys: scale 100 puts 3 n maxcost past 2^23
+    (both rings take the per-cell argmin path); scale 14 puts it between 2^22
+    and 2^23 (ring 32 packs keys, ring 64 does not)."""
+    rng = np.random.default_rng(60 + scale)
+    N = n = 100
+    dist = W.dist_round(_coords(rng, N) * scale)
+    tour = (rng.permutation(N) + 1).astype(np.int32)
+    maxc = int(max(dist[0, tour].max(), dist[tour, 0].max(), dist[tour[:-1], tour[1:]].max()))
+    assert 3 * n * maxc < 1 << 29
+    if scale == 14:
+        assert (1 << 22) <= 3 * n * maxc < (1 << 23)
+    else:
+        assert 3 * n * maxc >= 1 << 23
+    dem = rng.integers(1, 15, size=(64 * 9 + 5, N)).astype(np.int16)
+    _check(binding, tour, dist, dem, Q, "wide costs x%d Q=%d" % (scale, Q))
+
+
 def test_routes_window_past_the_ring(binding):
     inst = W.plain_normal(51, 160, 900, 2500)  # windows of ~200 positions
-    for v in ((32, 6, 3), (64, 12, 4)):
+    for v in ((32, 8, 3, 3), (64, 16, 4, 4)):
         binding.set_route_variant(*v)
         try:
             _check(binding, *_inst_arrays(inst), inst.Q, "long windows %s" % (v,))
