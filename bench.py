@@ -204,7 +204,7 @@ def route_recovery(torch, binding, t, d, q, inst, cells, eval_costs, steps, warm
         "ms_per_call": sec * 1e3,
         "cells_per_s": cells / sec,
         "scenarios_per_s": S / sec,
-        "kernel": "routes_tile_kernel",
+        "kernel": "routes_key_kernel + routes_wide_kernel (one of them returns at once)",
         "kernel_ms": kernel_s * 1e3,
         "kernel_cells_per_s": cells / kernel_s,
         "frac_valu_peak": cells / kernel_s / 1e12 / VALU_PEAK_TOPS,
