@@ -40,6 +40,8 @@ def _load():
         lib.oracle_split_values.restype = ctypes.c_int
         lib.oracle_split_routes.argtypes = [P, i32, P, i32, P, i64, i32, P, P, P, P, ctypes.c_int]
         lib.oracle_split_routes.restype = ctypes.c_int
+        lib.oracle_split_variant.argtypes = [P, i32, P, i32, P, i64, i32, i32, i32, P, ctypes.c_int]
+        lib.oracle_split_variant.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -144,5 +146,27 @@ def split_routes(tour, dist, demands, Q, *, nthreads=1):
     return dict(costs=costs, pred=pred, cuts=cuts, nroutes=nroutes)
 
 
-__all__ = ["split_eval", "split_sample", "split_values", "split_routes", "brute", "build_oracle", "LIB",
+def split_variant(tour, dist, demands, Q, *, beta=-1, K=0, nthreads=1):
+    """Split variants for one tour over every scenario: soft capacity with
+    overload penalty beta per unit (beta < 0: hard capacity) and a fleet of
+    at most K routes (K = 0: unlimited).  Returns int64[S] (INF64 where no
+    split exists)."""
+    lib = _load()
+    tour = np.ascontiguousarray(tour, np.int32)
+    dist = np.ascontiguousarray(dist, np.int32)
+    demands = np.ascontiguousarray(demands, np.int16)
+    S = int(demands.shape[0])
+    N = int(dist.shape[0] - 1)
+    if demands.ndim != 2 or demands.shape[1] != N or dist.shape != (N + 1, N + 1):
+        raise OracleError("shape mismatch")
+    costs = np.empty(S, np.int64)
+    rc = lib.oracle_split_variant(_p(tour), int(tour.size), _p(dist), N, _p(demands), S, int(Q), int(beta),
+                                  int(K), _p(costs), int(nthreads))
+    if rc != 0:
+        raise OracleError("oracle_split_variant returned %d" % rc)
+    return costs
+
+
+__all__ = ["split_eval", "split_sample", "split_values", "split_routes", "split_variant", "brute", "build_oracle",
+           "LIB",
            "INF32", "INF64", "NO_PRED", "OracleError"]

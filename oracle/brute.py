@@ -101,3 +101,31 @@ def split_cost(tour, qvis, dist, Q, ends):
             return None
         total += route_cost(tour[a:b], dist)
     return total
+
+
+def best_split_variant(tour, qvis, dist, Q, beta=-1, K=0):
+    """Cheapest split over ALL cut sets with at most K routes (K = 0: any
+    number), each route paying beta * max(0, load - Q) (beta < 0: routes over
+    Q excluded).  None if no cut set qualifies.  Enumeration, independent of
+    any recursion."""
+    n = len(tour)
+    if n == 0:
+        return 0
+    best = None
+    for mask in range(1 << (n - 1)):
+        cuts = [k + 1 for k in range(n - 1) if mask >> k & 1]
+        if K and len(cuts) + 1 > K:
+            continue
+        bounds = [0] + cuts + [n]
+        total, ok = 0, True
+        for a, b in zip(bounds[:-1], bounds[1:]):
+            load = sum(qvis[a:b])
+            if load > Q:
+                if beta < 0:
+                    ok = False
+                    break
+                total += beta * (load - Q)
+            total += route_cost(tour[a:b], dist)
+        if ok and (best is None or total < best):
+            best = total
+    return best

@@ -438,3 +438,153 @@ int oracle_split_routes(const int32_t *tour, int32_t n, const int32_t *dist, int
     }
     return rc;
 }
+
+/*
+ * Split variants from the extensive form's objective and constraints
+ * (App. A): every route pays its overload at rate beta, i.e. the route
+ * p+1..i costs
+ *     W(p,i) + beta * max(0, load(p+1..i) - Q)        (soft capacity)
+ * instead of being excluded when its load exceeds Q, and at most K routes
+ * may be used (the fleet-size bound).  With J_k(i) the cheapest split of
+ * positions 1..i into exactly k routes,
+ *     J_0(0) = 0,  J_0(i) = +inf for i > 0,
+ *     J_k(i) = min_{p<i} J_{k-1}(p) + cost(p,i),
+ * and the scenario's cost is min_{k<=K} J_k(n).  K = 0 means an unlimited
+ * fleet: J(i) = min_{p<i} J(p) + cost(p,i) as in the plain recursion.
+ * beta < 0 keeps the hard capacity (overloaded routes excluded, as in the
+ * plain recursion), so (beta < 0, K = 0) is the plain split.  Readings: the
+ * penalty is linear in the overload of each route (one l_k per vehicle);
+ * an empty tour costs 0 for every K.
+ *
+ * costs[s] (int64) = the scenario's cost, INT64_MAX if no split exists.
+ */
+static int64_t variant_cost(const int32_t *tour, int32_t n, const int32_t *dist, int32_t N1,
+                            const int64_t *q, int64_t Q, int64_t beta, int32_t K, int64_t *Va,
+                            int64_t *Vb)
+{
+    if (n == 0)
+        return 0;
+    const int layered = K > 0;
+    const int32_t layers = layered ? K : 1;
+    int64_t *prev = Va, *cur = Vb;
+    for (int32_t i = 0; i <= n; ++i)
+        prev[i] = i == 0 ? 0 : OR_INF; /* J_0 */
+    int64_t ans = OR_INF;
+    for (int32_t k = 1; k <= layers; ++k) {
+        /* unlimited fleet: one array, each J(i) built from J(p < i) of itself */
+        int64_t *src = layered ? prev : cur;
+        cur[0] = layered ? OR_INF : 0;
+        for (int32_t i = 1; i <= n; ++i) {
+            const int32_t last = tour[i - 1];
+            const int64_t back = dist[(int64_t)last * N1 + 0];
+            int64_t best = OR_INF, load = 0, inner = 0;
+            for (int32_t p = i - 1; p >= 0; --p) {
+                const int32_t first = tour[p];
+                load += q[p + 1];
+                if (p + 1 <= i - 1)
+                    inner += dist[(int64_t)first * N1 + tour[p + 1]];
+                if (beta < 0 && load > Q)
+                    break; /* hard capacity: every smaller p overloads too */
+                int64_t w = dist[first] + inner + back;
+                if (beta >= 0 && load > Q)
+                    w += beta * (load - Q);
+                if (src[p] != OR_INF && src[p] + w < best)
+                    best = src[p] + w;
+            }
+            cur[i] = best;
+        }
+        if (cur[n] < ans)
+            ans = cur[n];
+        int64_t *t = prev;
+        prev = cur;
+        cur = t;
+    }
+    return ans;
+}
+
+typedef struct {
+    const int32_t *tour;
+    int32_t n;
+    const int32_t *dist;
+    int32_t N;
+    const int16_t *demands;
+    int64_t s_begin, s_end;
+    int64_t Q, beta;
+    int32_t K;
+    int64_t *costs;
+    int status;
+} variant_job_t;
+
+static void *run_variant_job(void *arg)
+{
+    variant_job_t *jb = (variant_job_t *)arg;
+    const int32_t n = jb->n;
+    int64_t *Va = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+    int64_t *Vb = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+    int64_t *q = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+    if (!Va || !Vb || !q) {
+        jb->status = -2;
+        free(Va);
+        free(Vb);
+        free(q);
+        return NULL;
+    }
+    for (int64_t s = jb->s_begin; s < jb->s_end; ++s) {
+        const int16_t *row = jb->demands + s * (int64_t)jb->N;
+        q[0] = 0;
+        for (int32_t k = 1; k <= n; ++k)
+            q[k] = row[jb->tour[k - 1] - 1];
+        jb->costs[s] = variant_cost(jb->tour, n, jb->dist, jb->N + 1, q, jb->Q, jb->beta, jb->K,
+                                    Va, Vb);
+    }
+    free(Va);
+    free(Vb);
+    free(q);
+    return NULL;
+}
+
+int oracle_split_variant(const int32_t *tour, int32_t n, const int32_t *dist, int32_t N,
+                         const int16_t *demands, int64_t S, int32_t Q, int32_t beta, int32_t K,
+                         int64_t *costs, int nthreads)
+{
+    int32_t lens = n;
+    if (check_args(tour, &lens, 1, dist, N, demands, S, Q) != 0 || !costs || K < 0)
+        return -1;
+    if (nthreads < 1)
+        nthreads = 1;
+    if (nthreads > 64)
+        nthreads = 64;
+    if ((int64_t)nthreads > S)
+        nthreads = (int)S;
+    variant_job_t jobs[64];
+    pthread_t th[64];
+    for (int w = 0; w < nthreads; ++w) {
+        variant_job_t *jb = &jobs[w];
+        jb->tour = tour;
+        jb->n = n;
+        jb->dist = dist;
+        jb->N = N;
+        jb->demands = demands;
+        jb->s_begin = S * w / nthreads;
+        jb->s_end = S * (w + 1) / nthreads;
+        jb->Q = Q;
+        jb->beta = beta;
+        jb->K = K;
+        jb->costs = costs;
+        jb->status = 0;
+    }
+    int created[64] = {0};
+    for (int w = 1; w < nthreads; ++w)
+        created[w] = pthread_create(&th[w], NULL, run_variant_job, &jobs[w]) == 0;
+    run_variant_job(&jobs[0]);
+    int rc = jobs[0].status;
+    for (int w = 1; w < nthreads; ++w) {
+        if (created[w])
+            pthread_join(th[w], NULL);
+        else
+            run_variant_job(&jobs[w]);
+        if (jobs[w].status && !rc)
+            rc = jobs[w].status;
+    }
+    return rc;
+}
