@@ -11,7 +11,7 @@ Also reported on the same line: scenarios/s, the main kernel's roofline
 (int32 VALU ops, one per Bellman cell, against the chip's VALU peak), the
 CPU oracle's throughput on a bounded sample of the same workload, route
 recovery of the same tour (predecessors and cut points of every scenario),
-the batched form (256 ragged tours in one captured graph vs one launch per
+the split variants (soft capacity, fleet bound), the batched form (256 ragged tours in one captured graph vs one launch per
 tour) and the served form.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -217,6 +217,37 @@ def route_recovery(torch, binding, t, d, q, inst, cells, eval_costs, steps, warm
     }
 
 
+def split_variants(torch, binding, t, d, q, inst, cells, steps, warmup):
+    """The split variants on the headline tour and scenarios: soft capacity
+    (overload penalty beta per unit, unlimited fleet) and a fleet bound K
+    (hard capacity; each of the K passes relaxes the same admissible
+    windows, so its algorithmic work is K times the plain split's cells)."""
+    dev = q.device
+    n, S = int(t.numel()), inst.S
+    out = binding.VariantOutputs(S, dev)
+    res = {}
+    for beta, K in ((10, 0), (-1, 25), (10, 25)):
+        ws = torch.empty(binding.variant_workspace_bytes(n, inst.N, S, K), dtype=torch.uint8, device=dev)
+
+        def step():
+            binding.split_variant_device(t, d, q, inst.Q, beta=beta, K=K, out=out, workspace=ws)
+
+        sec = timed_steps(torch, step, max(1, steps // 4), max(1, warmup // 2))
+        status = int(out.status.item())
+        key = "beta%d_K%d" % (beta, K)
+        entry = {"ms_per_call": sec * 1e3, "scenarios_per_s": S / sec, "status": status}
+        if beta < 0:
+            entry["cells_per_s"] = K * cells / sec
+        else:
+            # soft capacity admits every predecessor: the dense relaxation count
+            entry["dense_relaxations_per_s"] = (K or 1) * S * n * (n + 1) / 2 / sec
+        res[key] = entry
+        del ws
+    res["workload"] = "split variants of the same tour: n=%d, S=%d, Q=%d (beta: penalty per unit of " \
+                      "overload, -1 = hard capacity; K: fleet bound, 0 = unlimited)" % (n, S, inst.Q)
+    return res
+
+
 def served(torch, binding, W, num_requests, pool_size, budget_gb, seed=5):
     """Served stream: Poisson arrivals of single-tour requests (n ~ U{50..1000},
     S ~ 10^U(3,5), Q in {80,150,300}) drawn from a pool of distinct instances
@@ -289,6 +320,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-routes", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-requests", type=int, default=10_000)
     ap.add_argument("--served-pool", type=int, default=32)
@@ -398,6 +430,9 @@ def main():
         rr = route_recovery(torch, binding, t, d, q, inst, cells, out.costs[0], args.steps, args.warmup)
         rr["kernel_vs_eval_kernel"] = rr["kernel_ms"] / (kernel_s * 1e3)
         result["routes"] = rr
+    if not args.no_variants:
+        log("split variants (soft capacity, fleet bound)")
+        result["variants"] = split_variants(torch, binding, t, d, q, inst, cells, args.steps, args.warmup)
     if not args.no_batched:
         log("batched vs plain (256 ragged tours, S=10^4)")
         result["batched"] = batched_vs_plain(torch, binding, W, reps=20)

@@ -180,6 +180,49 @@ int split_routes_set_variant(int32_t ring, int32_t first, int32_t group, int32_t
 int split_routes_list_variants(int32_t *out, int32_t cap);
 
 /*
+ * Split variants (App. A, the extensive form: its objective charges every
+ * vehicle's overload l_k at rate beta, and its fleet-size constraint allows
+ * at most K vehicles).  For ONE giant tour over every scenario s, with
+ *   cost(p,i) = W(p,i) + beta * max(0, load_s(p+1..i) - Q)   (beta >= 0),
+ *   cost(p,i) = W(p,i) if load_s(p+1..i) <= Q, else excluded (beta < 0),
+ * and J_k(i) the cheapest split of positions 1..i into exactly k routes
+ * (J_0(0) = 0, J_k(i) = min_{p<i} J_{k-1}(p) + cost(p,i)), the scenario's
+ * cost is min_{k<=K} J_k(n); K = 0 means an unlimited fleet.  beta < 0 with
+ * K = 0 is the plain split of split_eval.
+ *
+ * split_variant_device -- DEVICE pointers, enqueued on `stream`, nothing
+ * allocated.
+ *   d_tour    int32 [n]      customer ids 1..N (may be NULL when n = 0)
+ *   d_dist, N, d_demands, S, Q  as in split_eval (d_demands 16-byte aligned)
+ *   beta      penalty per unit of overload, in [0, 2^24); negative = hard
+ *   K         fleet bound in [0, 65535]; 0 = unlimited
+ *   d_costs   out int32 [S]  the scenario's cost, SPLIT_INF if no split
+ *                            exists (hard capacity, or fewer than needed
+ *                            vehicles)
+ *   d_status  out int32 [1]  0, or a bit set: 1 invalid tour or costs past
+ *                            the int32 guard, 2 negative demand, 4 a
+ *                            scenario's penalty range past the int32 guard
+ *                            (3 n maxcost + beta (load + Q) >= 2^29 or
+ *                            load + Q >= 2^24); when non-zero every cost is
+ *                            SPLIT_INF
+ *   d_workspace, ws_bytes    caller-owned device scratch of at least
+ *                            split_variant_workspace_bytes(n, N, S, K) bytes,
+ *                            256-byte aligned (K > 0 adds 8 n S bytes for
+ *                            the potentials of consecutive passes)
+ * Host-checkable arguments are validated before anything is enqueued
+ * (SPLIT_EINVAL).  The library touches the buffers only until the enqueued
+ * work completes; two calls sharing a workspace must be ordered on one
+ * stream.  Windows longer than the register ring, demands above 255 and
+ * pools too large for a tile in LDS take an exact (slower) kernel; results
+ * never depend on the path.
+ */
+size_t split_variant_workspace_bytes(int32_t n, int32_t N, int64_t S, int32_t K);
+int split_variant_device(const int32_t *d_tour, int32_t n, const int32_t *d_dist, int32_t N,
+                         const int16_t *d_demands, int64_t S, int32_t Q, int32_t beta, int32_t K,
+                         int32_t *d_costs, int32_t *d_status, void *d_workspace, size_t ws_bytes,
+                         split_stream_t stream);
+
+/*
  * split_count_cells_device -- Bellman-cell counter (measurement utility).
  * For each tour writes the number of capacity-admissible relaxations
  * (s, p, i), i.e. sum over scenarios and positions i of the number of

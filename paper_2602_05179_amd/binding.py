@@ -52,6 +52,8 @@ EXPORTED = (
     "split_routes_device",
     "split_routes_set_variant",
     "split_routes_list_variants",
+    "split_variant_workspace_bytes",
+    "split_variant_device",
 )
 
 
@@ -129,6 +131,10 @@ def _load():
     lib.split_routes_set_variant.restype = ctypes.c_int
     lib.split_routes_set_variant.argtypes = [i32, i32, i32, i32]
     lib.split_routes_list_variants.restype = ctypes.c_int
+    lib.split_variant_workspace_bytes.restype = sz
+    lib.split_variant_workspace_bytes.argtypes = [i32, i32, i64, i32]
+    lib.split_variant_device.restype = ctypes.c_int
+    lib.split_variant_device.argtypes = [P, i32, P, i32, P, i64, i32, i32, i32, P, P, P, sz, P]
     lib.split_routes_list_variants.argtypes = [ctypes.POINTER(i32), i32]
     return lib
 
@@ -349,6 +355,50 @@ def split_routes_device(tour, dist, demands, Q, *, out=None, workspace=None, str
     _check(lib.split_routes_device(_dptr(tour), n, _dptr(dist), N, _dptr(demands), S, int(Q),
                                    _dptr(out.costs), _dptr(out.pred), _dptr(out.cuts), _dptr(out.nroutes),
                                    _dptr(workspace), int(workspace.numel()), _stream_handle(stream)))
+    out.workspace = workspace
+    return out
+
+
+# ---------------------------------------------------------------------------
+# split variants: soft capacity (overload penalty) and a fleet bound
+# ---------------------------------------------------------------------------
+VARIANT_BAD_TOUR, VARIANT_BAD_DEMAND, VARIANT_PENALTY_RANGE = 1, 2, 4
+
+
+def variant_workspace_bytes(n: int, N: int, S: int, K: int) -> int:
+    return int(lib.split_variant_workspace_bytes(int(n), int(N), int(S), int(K)))
+
+
+class VariantOutputs:
+    """costs int32 [S]; status int32 [1] (0 = valid)."""
+
+    def __init__(self, S: int, device):
+        torch = _torch()
+        self.S = S
+        self.costs = torch.empty(S, dtype=torch.int32, device=device)
+        self.status = torch.empty(1, dtype=torch.int32, device=device)
+
+
+def split_variant_device(tour, dist, demands, Q, *, beta=-1, K=0, out=None, workspace=None, stream=None):
+    """Enqueue the split variant of one giant tour over every scenario:
+    overload penalty beta per unit (beta < 0: hard capacity) and at most K
+    routes (K = 0: unlimited).  Returns VariantOutputs."""
+    torch = _torch()
+    n = int(tour.numel())
+    N = int(dist.shape[0] - 1)
+    S = int(demands.shape[0])
+    for name, t, dt in (("tour", tour, torch.int32), ("dist", dist, torch.int32),
+                        ("demands", demands, torch.int16)):
+        if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+            raise SplitError(SPLIT_EINVAL, "%s must be a contiguous %s CUDA tensor" % (name, dt))
+    if out is None:
+        out = VariantOutputs(S, demands.device)
+    need = variant_workspace_bytes(n, N, S, K)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=demands.device)
+    _check(lib.split_variant_device(_dptr(tour), n, _dptr(dist), N, _dptr(demands), S, int(Q), int(beta), int(K),
+                                    _dptr(out.costs), _dptr(out.status), _dptr(workspace), int(workspace.numel()),
+                                    _stream_handle(stream)))
     out.workspace = workspace
     return out
 

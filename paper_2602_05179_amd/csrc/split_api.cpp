@@ -14,6 +14,7 @@
 
 #include "split_eval.h"
 #include "split_internal.h"
+#include "split_variant.h"
 
 namespace {
 
@@ -362,6 +363,41 @@ int split_routes_device(const int32_t *d_tour, int32_t n, const int32_t *d_dist,
     HIP_TRY(splitk::launch_routes(d_tour, n, d_dist, N, d_demands, S, Q, d_costs, d_pred, d_cuts,
                                   d_nroutes, ws, static_cast<hipStream_t>(stream),
                                   splitk::choose_route_variant(Q), use_ev ? &ev : nullptr),
+            "launch");
+    return SPLIT_OK;
+}
+
+size_t split_variant_workspace_bytes(int32_t n, int32_t N, int64_t S, int32_t K)
+{
+    if (n < 0 || n > splitk::kMaxLen || S < 1 || N < 1 || K < 0)
+        return 0;
+    return splitk::variant_workspace_bytes(n, N, S, K);
+}
+
+int split_variant_device(const int32_t *d_tour, int32_t n, const int32_t *d_dist, int32_t N,
+                         const int16_t *d_demands, int64_t S, int32_t Q, int32_t beta, int32_t K,
+                         int32_t *d_costs, int32_t *d_status, void *d_workspace, size_t ws_bytes,
+                         split_stream_t stream)
+{
+    g_err[0] = 0;
+    int rc = check_scalars(1, N, S, Q, n);
+    if (rc)
+        return rc;
+    if (K < 0 || K > splitk::kMaxLen)
+        return fail(SPLIT_EINVAL, "K must be in [0, %d] (got %d)", splitk::kMaxLen, K);
+    if (beta >= (1 << 24))
+        return fail(SPLIT_EINVAL, "beta must be below 2^24 (got %d)", beta);
+    if (!d_dist || !d_demands || !d_costs || !d_status || !d_workspace || (n > 0 && !d_tour))
+        return fail(SPLIT_EINVAL, "null pointer argument");
+    if (reinterpret_cast<uintptr_t>(d_demands) % 16)
+        return fail(SPLIT_EINVAL, "demands must be 16-byte aligned");
+    if (reinterpret_cast<uintptr_t>(d_workspace) % 256)
+        return fail(SPLIT_EINVAL, "workspace must be 256-byte aligned");
+    const size_t need = splitk::variant_workspace_bytes(n, N, S, K);
+    if (ws_bytes < need)
+        return fail(SPLIT_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+    HIP_TRY(splitk::launch_variant(d_tour, n, d_dist, N, d_demands, S, Q, beta, K, d_costs,
+                                   d_status, d_workspace, static_cast<hipStream_t>(stream)),
             "launch");
     return SPLIT_OK;
 }
