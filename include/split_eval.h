@@ -223,6 +223,62 @@ int split_variant_device(const int32_t *d_tour, int32_t n, const int32_t *d_dist
                          split_stream_t stream);
 
 /*
+ * Min-plus Bellman updates (Sec. 2, min-plus matrix formulation: the
+ * stage-wise update J_{t+1} = A_t^T (x) J_t in the (min, +) semiring; App. A
+ * gives a worked 3-to-2-state example and the scenario-batched forward DP).
+ * For each of B independent problems (scenarios, or customer-scenario
+ * pairs) with m states per stage:
+ *   J_{t+1}(j) = min_i A_t(i, j) + J_t(i),   t = 0..T-1.
+ * Values are non-negative int32; INT32_MAX is +inf (a negative entry reads
+ * as +inf), and a finite sum that reaches INT32_MAX is +inf.
+ *
+ * split_minplus_forward_device -- DEVICE pointers, enqueued on `stream`.
+ *   d_A     int32, row-major (source i, target j): [T][m][m] when shared = 1
+ *           (one matrix per stage for every problem), [T][B][m][m] when
+ *           shared = 0
+ *   d_J0    int32 [B][m]  initial cost-to-go (INT32_MAX where not allowed)
+ *   d_JT    out int32 [B][m]  J_T
+ *   d_arg   out int32 [T][B][m] (may be NULL): the smallest i attaining
+ *           J_{t+1}(j), -1 where J_{t+1}(j) is +inf
+ *   1 <= m <= 4096, T >= 1, 1 <= B < 2^31.  Returns SPLIT_EINVAL on bad
+ *   sizes or null required pointers, before anything is enqueued.
+ *
+ * split_minplus_backtrack_device -- the optimal state path of every problem
+ * (App. B: backtracking the recorded minimisers):
+ *   d_path  out int32 [T+1][B]: d_path[T][b] = the smallest j minimising
+ *           J_T(b, j); d_path[t][b] = d_arg[t][b][d_path[t+1][b]]; -1
+ *           throughout when J_T(b, .) is +inf everywhere.
+ *
+ * split_ou_transitions_device -- the transition matrices of the
+ * order-up-to inventory instance (App. B: a customer is replenished up to
+ * its capacity U or not at all; the illustrative matrix form), written as
+ * d_A [T][B][U+1][U+1] for split_minplus_forward_device (shared = 0).
+ * States are end-of-day inventories 0..U.  From inventory I with day
+ * demand d the delivery is q = 0 or q = U - I, the next state
+ * max(0, I + q - d), and the day costs
+ *   transport(q) + h[next] + rho * max(0, d - I - q),
+ * transport(0) = 0, transport(q > 0) = (the cheapest of the day's R route
+ * options whose residual capacity is at least q) + u * q, impossible when
+ * none has room.  A(I, J) is the cheapest choice landing in J, INT32_MAX if
+ * none (sums are formed in 64 bits and saturate at INT32_MAX).
+ *   d_demand   int32 [T][B]        demands, >= 0
+ *   d_opt_cost int32 [T][B][R]     insertion cost of each route option, >= 0
+ *   d_opt_cap  int32 [T][B][R]     residual capacity of each route option
+ *   d_h        int32 [U+1]         end-of-day cost of each inventory level
+ *   u, rho     unit transport cost and unit shortage penalty, >= 0
+ *   0 <= U < 4096, 1 <= R <= 64.
+ */
+int split_minplus_forward_device(const int32_t *d_A, int32_t shared, int32_t T, int32_t m,
+                                 int64_t B, const int32_t *d_J0, int32_t *d_JT, int32_t *d_arg,
+                                 split_stream_t stream);
+int split_minplus_backtrack_device(const int32_t *d_JT, const int32_t *d_arg, int32_t T,
+                                   int32_t m, int64_t B, int32_t *d_path, split_stream_t stream);
+int split_ou_transitions_device(int32_t U, int32_t T, int64_t B, int32_t R,
+                                const int32_t *d_demand, const int32_t *d_opt_cost,
+                                const int32_t *d_opt_cap, const int32_t *d_h, int32_t u,
+                                int32_t rho, int32_t *d_A, split_stream_t stream);
+
+/*
  * split_count_cells_device -- Bellman-cell counter (measurement utility).
  * For each tour writes the number of capacity-admissible relaxations
  * (s, p, i), i.e. sum over scenarios and positions i of the number of

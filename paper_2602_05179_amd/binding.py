@@ -54,6 +54,9 @@ EXPORTED = (
     "split_routes_list_variants",
     "split_variant_workspace_bytes",
     "split_variant_device",
+    "split_minplus_forward_device",
+    "split_minplus_backtrack_device",
+    "split_ou_transitions_device",
 )
 
 
@@ -134,6 +137,12 @@ def _load():
     lib.split_variant_workspace_bytes.restype = sz
     lib.split_variant_workspace_bytes.argtypes = [i32, i32, i64, i32]
     lib.split_variant_device.restype = ctypes.c_int
+    lib.split_minplus_forward_device.restype = ctypes.c_int
+    lib.split_minplus_forward_device.argtypes = [P, i32, i32, i32, i64, P, P, P, P]
+    lib.split_minplus_backtrack_device.restype = ctypes.c_int
+    lib.split_minplus_backtrack_device.argtypes = [P, P, i32, i32, i64, P, P]
+    lib.split_ou_transitions_device.restype = ctypes.c_int
+    lib.split_ou_transitions_device.argtypes = [i32, i32, i64, i32, P, P, P, P, i32, i32, P, P]
     lib.split_variant_device.argtypes = [P, i32, P, i32, P, i64, i32, i32, i32, P, P, P, sz, P]
     lib.split_routes_list_variants.argtypes = [ctypes.POINTER(i32), i32]
     return lib
@@ -400,6 +409,65 @@ def split_variant_device(tour, dist, demands, Q, *, beta=-1, K=0, out=None, work
                                     _dptr(out.costs), _dptr(out.status), _dptr(workspace), int(workspace.numel()),
                                     _stream_handle(stream)))
     out.workspace = workspace
+    return out
+
+
+# ---------------------------------------------------------------------------
+# min-plus Bellman updates and the order-up-to inventory instance
+# ---------------------------------------------------------------------------
+MINPLUS_INF = np.iinfo(np.int32).max
+
+
+def _check_i32(name, t):
+    torch = _torch()
+    if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous():
+        raise SplitError(SPLIT_EINVAL, "%s must be a contiguous int32 CUDA tensor" % name)
+
+
+def minplus_forward(A, J0, *, shared, record_arg=True, stream=None):
+    """A: int32 [T, m, m] (shared) or [T, B, m, m]; J0 int32 [B, m].
+    Returns (J_T [B, m], arg [T, B, m] or None)."""
+    torch = _torch()
+    _check_i32("A", A)
+    _check_i32("J0", J0)
+    B, m = int(J0.shape[0]), int(J0.shape[1])
+    T = int(A.shape[0])
+    want = (T, m, m) if shared else (T, B, m, m)
+    if tuple(A.shape) != want:
+        raise SplitError(SPLIT_EINVAL, "A has shape %s, expected %s" % (tuple(A.shape), want))
+    JT = torch.empty((B, m), dtype=torch.int32, device=J0.device)
+    arg = torch.empty((T, B, m), dtype=torch.int32, device=J0.device) if record_arg else None
+    _check(lib.split_minplus_forward_device(_dptr(A), 1 if shared else 0, T, m, B, _dptr(J0), _dptr(JT),
+                                            _dptr(arg) if arg is not None else None, _stream_handle(stream)))
+    return JT, arg
+
+
+def minplus_backtrack(JT, arg, *, stream=None):
+    """State path int32 [T+1, B] from J_T [B, m] and arg [T, B, m]."""
+    torch = _torch()
+    _check_i32("JT", JT)
+    _check_i32("arg", arg)
+    T, B, m = (int(x) for x in arg.shape)
+    path = torch.empty((T + 1, B), dtype=torch.int32, device=JT.device)
+    _check(lib.split_minplus_backtrack_device(_dptr(JT), _dptr(arg), T, m, B, _dptr(path),
+                                              _stream_handle(stream)))
+    return path
+
+
+def ou_transitions(U, demand, opt_cost, opt_cap, h, u, rho, *, out=None, stream=None):
+    """Transition matrices int32 [T, B, U+1, U+1] of the order-up-to instance.
+    demand int32 [T, B]; opt_cost, opt_cap int32 [T, B, R]; h int32 [U+1]."""
+    torch = _torch()
+    for name, t in (("demand", demand), ("opt_cost", opt_cost), ("opt_cap", opt_cap), ("h", h)):
+        _check_i32(name, t)
+    T, B = (int(x) for x in demand.shape)
+    R = int(opt_cost.shape[2])
+    if tuple(opt_cost.shape) != (T, B, R) or tuple(opt_cap.shape) != (T, B, R) or h.numel() != U + 1:
+        raise SplitError(SPLIT_EINVAL, "shape mismatch")
+    if out is None:
+        out = torch.empty((T, B, U + 1, U + 1), dtype=torch.int32, device=demand.device)
+    _check(lib.split_ou_transitions_device(int(U), T, B, R, _dptr(demand), _dptr(opt_cost), _dptr(opt_cap),
+                                           _dptr(h), int(u), int(rho), _dptr(out), _stream_handle(stream)))
     return out
 
 

@@ -14,6 +14,7 @@
 
 #include "split_eval.h"
 #include "split_internal.h"
+#include "split_minplus.h"
 #include "split_variant.h"
 
 namespace {
@@ -398,6 +399,58 @@ int split_variant_device(const int32_t *d_tour, int32_t n, const int32_t *d_dist
         return fail(SPLIT_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
     HIP_TRY(splitk::launch_variant(d_tour, n, d_dist, N, d_demands, S, Q, beta, K, d_costs,
                                    d_status, d_workspace, static_cast<hipStream_t>(stream)),
+            "launch");
+    return SPLIT_OK;
+}
+
+int split_minplus_forward_device(const int32_t *d_A, int32_t shared, int32_t T, int32_t m,
+                                 int64_t B, const int32_t *d_J0, int32_t *d_JT, int32_t *d_arg,
+                                 split_stream_t stream)
+{
+    g_err[0] = 0;
+    if (T < 1 || m < 1 || m > splitk::kMinplusMaxStates || B < 1 || B > (int64_t)INT32_MAX)
+        return fail(SPLIT_EINVAL, "need T >= 1, 1 <= m <= %d, 1 <= B < 2^31 (got T=%d m=%d B=%lld)",
+                    splitk::kMinplusMaxStates, T, m, (long long)B);
+    if (shared != 0 && shared != 1)
+        return fail(SPLIT_EINVAL, "shared must be 0 or 1 (got %d)", shared);
+    if (!d_A || !d_J0 || !d_JT)
+        return fail(SPLIT_EINVAL, "null pointer argument");
+    HIP_TRY(splitk::launch_minplus_forward(d_A, shared, T, m, B, d_J0, d_JT, d_arg,
+                                           static_cast<hipStream_t>(stream)),
+            "launch");
+    return SPLIT_OK;
+}
+
+int split_minplus_backtrack_device(const int32_t *d_JT, const int32_t *d_arg, int32_t T,
+                                   int32_t m, int64_t B, int32_t *d_path, split_stream_t stream)
+{
+    g_err[0] = 0;
+    if (T < 1 || m < 1 || m > splitk::kMinplusMaxStates || B < 1 || B > (int64_t)INT32_MAX)
+        return fail(SPLIT_EINVAL, "need T >= 1, 1 <= m <= %d, 1 <= B < 2^31",
+                    splitk::kMinplusMaxStates);
+    if (!d_JT || !d_arg || !d_path)
+        return fail(SPLIT_EINVAL, "null pointer argument");
+    HIP_TRY(splitk::launch_minplus_backtrack(d_JT, d_arg, T, m, B, d_path,
+                                             static_cast<hipStream_t>(stream)),
+            "launch");
+    return SPLIT_OK;
+}
+
+int split_ou_transitions_device(int32_t U, int32_t T, int64_t B, int32_t R,
+                                const int32_t *d_demand, const int32_t *d_opt_cost,
+                                const int32_t *d_opt_cap, const int32_t *d_h, int32_t u,
+                                int32_t rho, int32_t *d_A, split_stream_t stream)
+{
+    g_err[0] = 0;
+    if (U < 0 || U + 1 > splitk::kMinplusMaxStates || T < 1 || B < 1 || R < 1 || R > 64)
+        return fail(SPLIT_EINVAL, "need 0 <= U < %d, T >= 1, B >= 1, 1 <= R <= 64",
+                    splitk::kMinplusMaxStates);
+    if (u < 0 || rho < 0)
+        return fail(SPLIT_EINVAL, "u and rho must be >= 0");
+    if (!d_demand || !d_opt_cost || !d_opt_cap || !d_h || !d_A)
+        return fail(SPLIT_EINVAL, "null pointer argument");
+    HIP_TRY(splitk::launch_ou_transitions(U, T, B, R, d_demand, d_opt_cost, d_opt_cap, d_h, u, rho,
+                                          d_A, static_cast<hipStream_t>(stream)),
             "launch");
     return SPLIT_OK;
 }

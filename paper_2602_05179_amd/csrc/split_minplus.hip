@@ -1,0 +1,201 @@
+// split_minplus.hip -- the generic stage-wise Bellman update in the
+// (min, +) semiring (Sec. 2, "Min-Plus Matrix Formulation"; App. A,
+// "Illustrative example for the min-plus matrix-vector Bellman update";
+// the scenario-batched forward DP of App. A), with recorded minimisers and
+// backtracking (App. B: the batched DP records its minimisers and is
+// backtracked to recover decisions), and the transition generator of the
+// order-up-to inventory instance (App. B, its illustrative matrix form).
+//
+//   J_{t+1}(j) = min_i A_t(i, j) + J_t(i),   t = 0..T-1,
+//
+// for a batch of B independent problems (scenarios, or customer-scenario
+// pairs) with m states per stage.  Values are non-negative int32; INT32_MAX
+// is +inf, and a finite sum that reaches it is +inf (the sum of two values
+// in [0, 2^31 - 1] fits 32 unsigned bits, so one unsigned add and one
+// unsigned min against INT32_MAX give the saturated sum; a negative input
+// reads as +inf).
+//
+// Layout: one wave per batch element, its J in LDS (double buffer); lane j
+// owns target state j (and j + 64, ...), reads column j of A_t row by row
+// (row i of A_t is contiguous, so each row read is coalesced across lanes)
+// and J_t(i) as an LDS broadcast.  With A per element the update streams
+// T * m * m * 4 bytes per element: HBM-bound.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "split_device.h"
+#include "split_eval.h"
+#include "split_minplus.h"
+
+namespace splitk {
+
+namespace {
+
+constexpr uint32_t kMpInf = 0x7FFFFFFFu;
+
+__device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b)
+{
+    // a, b <= kMpInf (after clamping): the 32-bit sum cannot wrap
+    return min(a + b, kMpInf);
+}
+
+// grid = B waves; LDS: 2 * m int32
+__global__ __launch_bounds__(kWave) void minplus_forward_kernel(
+    const int32_t *__restrict__ A, int32_t shared, int32_t T, int32_t m, int64_t B,
+    const int32_t *__restrict__ J0, int32_t *__restrict__ JT, int32_t *__restrict__ arg)
+{
+    extern __shared__ uint32_t jbuf[];
+    const int64_t b = blockIdx.x;
+    const int lane = threadIdx.x;
+    uint32_t *cur = jbuf, *nxt = jbuf + m;
+    for (int j = lane; j < m; j += kWave)
+        cur[j] = min((uint32_t)J0[b * m + j], kMpInf);
+    __syncthreads();
+    const int64_t mm = (int64_t)m * m;
+    for (int t = 0; t < T; ++t) {
+        const uint32_t *At = reinterpret_cast<const uint32_t *>(
+            shared ? A + (int64_t)t * mm : A + ((int64_t)t * B + b) * mm);
+        for (int j = lane; j < m; j += kWave) {
+            uint32_t best = kMpInf;
+            int bi = -1;
+            int i = 0;
+            for (; i + 4 <= m; i += 4) {
+                uint32_t a[4], c[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    a[u] = min(At[(int64_t)(i + u) * m + j], kMpInf);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    c[u] = sat_add(a[u], cur[i + u]);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (c[u] < best) { // strict: the smallest i keeps a tie
+                        best = c[u];
+                        bi = i + u;
+                    }
+            }
+            for (; i < m; ++i) {
+                const uint32_t c = sat_add(min(At[(int64_t)i * m + j], kMpInf), cur[i]);
+                if (c < best) {
+                    best = c;
+                    bi = i;
+                }
+            }
+            nxt[j] = best;
+            if (arg)
+                arg[((int64_t)t * B + b) * m + j] = best < kMpInf ? bi : -1;
+        }
+        __syncthreads();
+        uint32_t *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+    for (int j = lane; j < m; j += kWave)
+        JT[b * m + j] = (int32_t)cur[j];
+}
+
+// one thread per element: the smallest minimising final state, then back
+// through the recorded minimisers; -1 throughout when J_T is all +inf
+__global__ void minplus_backtrack_kernel(const int32_t *__restrict__ JT,
+                                         const int32_t *__restrict__ arg, int32_t T, int32_t m,
+                                         int64_t B, int32_t *__restrict__ path)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B)
+        return;
+    uint32_t best = kMpInf;
+    int s = -1;
+    for (int j = 0; j < m; ++j) {
+        const uint32_t v = (uint32_t)JT[b * m + j];
+        if (v < best) {
+            best = v;
+            s = j;
+        }
+    }
+    path[(int64_t)T * B + b] = s;
+    for (int t = T - 1; t >= 0; --t) {
+        if (s >= 0) {
+            s = arg[((int64_t)t * B + b) * m + s];
+            if (s < -1 || s >= m)
+                s = -1; // not a recorded minimiser (cannot happen for a finite J_T)
+        }
+        path[(int64_t)t * B + b] = s;
+    }
+}
+
+// one thread per entry A_t[b](I, J) of the order-up-to instance
+__global__ void ou_transitions_kernel(int32_t U, int32_t T, int64_t B, int32_t R,
+                                      const int32_t *__restrict__ demand,
+                                      const int32_t *__restrict__ opt_cost,
+                                      const int32_t *__restrict__ opt_cap,
+                                      const int32_t *__restrict__ h, int32_t u, int32_t rho,
+                                      int32_t *__restrict__ A)
+{
+    const int64_t m = (int64_t)U + 1;
+    const int64_t total = (int64_t)T * B * m * m;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int J = (int)(e % m);
+        const int I = (int)((e / m) % m);
+        const int64_t tb = e / (m * m); // t * B + b
+        const int d = demand[tb];
+        long long best = kMpInf;
+        for (int pass = 0; pass < 2; ++pass) {
+            const int q = pass == 0 ? 0 : U - I;
+            if (pass == 1 && q == 0)
+                break; // I = U: delivering up to U is no delivery
+            if (max(0, I + q - d) != J)
+                continue;
+            long long tr = 0;
+            if (q > 0) {
+                long long c = kMpInf;
+                for (int r = 0; r < R; ++r)
+                    if (opt_cap[tb * R + r] >= q)
+                        c = min(c, (long long)opt_cost[tb * R + r]);
+                if (c >= kMpInf)
+                    continue; // no route option has room for the delivery
+                tr = c + (long long)u * q;
+            }
+            const long long cost = tr + h[J] + (long long)rho * max(0, d - I - q);
+            best = min(best, cost);
+        }
+        A[e] = (int32_t)min(best, (long long)kMpInf);
+    }
+}
+
+} // namespace
+
+hipError_t launch_minplus_forward(const int32_t *A, int32_t shared, int32_t T, int32_t m,
+                                  int64_t B, const int32_t *J0, int32_t *JT, int32_t *arg,
+                                  hipStream_t stream)
+{
+    hipLaunchKernelGGL(minplus_forward_kernel, dim3((unsigned)B), dim3(kWave),
+                       (size_t)2 * m * sizeof(uint32_t), stream, A, shared, T, m, B, J0, JT, arg);
+    return hipGetLastError();
+}
+
+hipError_t launch_minplus_backtrack(const int32_t *JT, const int32_t *arg, int32_t T, int32_t m,
+                                    int64_t B, int32_t *path, hipStream_t stream)
+{
+    const unsigned blocks = (unsigned)((B + 255) / 256);
+    hipLaunchKernelGGL(minplus_backtrack_kernel, dim3(blocks), dim3(256), 0, stream, JT, arg, T, m,
+                       B, path);
+    return hipGetLastError();
+}
+
+hipError_t launch_ou_transitions(int32_t U, int32_t T, int64_t B, int32_t R,
+                                 const int32_t *demand, const int32_t *opt_cost,
+                                 const int32_t *opt_cap, const int32_t *h, int32_t u, int32_t rho,
+                                 int32_t *A, hipStream_t stream)
+{
+    const int64_t total = (int64_t)T * B * ((int64_t)U + 1) * ((int64_t)U + 1);
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536)
+        blocks = 65536;
+    hipLaunchKernelGGL(ou_transitions_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, U, T,
+                       B, R, demand, opt_cost, opt_cap, h, u, rho, A);
+    return hipGetLastError();
+}
+
+} // namespace splitk

@@ -187,3 +187,24 @@ def test_routes_device_form_rejects_bad_arguments_before_device_work():
     assert rc == binding.SPLIT_EINVAL and "null" in binding.last_error()
     rc = f(fake, 5, fake, 5, fake, 10, 3, fake, fake, fake, fake, P(300), 1 << 20, None)
     assert rc == binding.SPLIT_EINVAL and "aligned" in binding.last_error()
+
+
+def test_minplus_and_variant_entry_points_reject_bad_arguments_before_device_work():
+    P = ctypes.c_void_p
+    fake = P(256)
+    lib = binding.lib
+    for T, m, B, shared in ((0, 3, 4, 1), (2, 0, 4, 1), (2, 5000, 4, 1), (2, 3, 0, 0), (2, 3, 4, 2)):
+        assert lib.split_minplus_forward_device(fake, shared, T, m, B, fake, fake, None, None) == \
+            binding.SPLIT_EINVAL, (T, m, B, shared)
+    assert lib.split_minplus_forward_device(None, 1, 2, 3, 4, fake, fake, None, None) == binding.SPLIT_EINVAL
+    assert lib.split_minplus_backtrack_device(fake, None, 2, 3, 4, fake, None) == binding.SPLIT_EINVAL
+    for U, T, B, R, u, rho in ((-1, 1, 1, 1, 0, 0), (5000, 1, 1, 1, 0, 0), (3, 0, 1, 1, 0, 0), (3, 1, 1, 0, 0, 0),
+                               (3, 1, 1, 65, 0, 0), (3, 1, 1, 2, -1, 0), (3, 1, 1, 2, 0, -1)):
+        assert lib.split_ou_transitions_device(U, T, B, R, fake, fake, fake, fake, u, rho, fake, None) == \
+            binding.SPLIT_EINVAL, (U, T, B, R, u, rho)
+    f = lib.split_variant_device
+    assert f(fake, 5, fake, 5, fake, 10, 3, 1 << 24, 0, fake, fake, fake, 1 << 20, None) == binding.SPLIT_EINVAL
+    assert f(fake, 5, fake, 5, fake, 10, 3, 2, -1, fake, fake, fake, 1 << 20, None) == binding.SPLIT_EINVAL
+    assert f(fake, 5, fake, 5, fake, 10, 3, 2, 0, fake, None, fake, 1 << 20, None) == binding.SPLIT_EINVAL
+    assert f(fake, 5, fake, 5, fake, 10, 3, 2, 0, fake, fake, fake, 16, None) == binding.SPLIT_EINVAL
+    assert binding.variant_workspace_bytes(200, 200, 10 ** 6, 4) > binding.variant_workspace_bytes(200, 200, 10 ** 6, 0)
