@@ -11,7 +11,8 @@ Also reported on the same line: scenarios/s, the main kernel's roofline
 (int32 VALU ops, one per Bellman cell, against the chip's VALU peak), the
 CPU oracle's throughput on a bounded sample of the same workload, route
 recovery of the same tour (predecessors and cut points of every scenario),
-the split variants (soft capacity, fleet bound), the batched form (256 ragged tours in one captured graph vs one launch per
+the split variants (soft capacity, fleet bound), the order-up-to inventory
+DP on the generic min-plus update, the batched form (256 ragged tours in one captured graph vs one launch per
 tour) and the served form.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -248,6 +249,48 @@ def split_variants(torch, binding, t, d, q, inst, cells, steps, warmup):
     return res
 
 
+def inventory_minplus(torch, binding, W, steps, warmup):
+    """The order-up-to inventory DP on the generic min-plus update: transition
+    generator, forward pass with recorded minimisers, backtracking.  The
+    forward pass streams one int32 matrix per (day, problem): HBM-bound."""
+    import numpy as np
+    inst = W.inventory_ou()
+    dev = torch.device("cuda:0")
+    T, B = inst.demand.shape
+    m = inst.U + 1
+    dem, cost, cap, h = (torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+                         for a in (inst.demand, inst.opt_cost, inst.opt_cap, inst.h))
+    J0 = torch.full((B, m), int(binding.MINPLUS_INF), dtype=torch.int32, device=dev)
+    J0[torch.arange(B, device=dev), torch.from_numpy(inst.I0.astype(np.int64)).to(dev)] = 0
+    A = binding.ou_transitions(inst.U, dem, cost, cap, h, inst.u, inst.rho)
+    t_gen = timed_steps(torch, lambda: binding.ou_transitions(inst.U, dem, cost, cap, h, inst.u, inst.rho, out=A),
+                        steps, warmup)
+    res = {}
+
+    def fwd():
+        res["out"] = binding.minplus_forward(A, J0, shared=False)
+
+    t_fwd = timed_steps(torch, fwd, steps, warmup)
+    JT, arg = res["out"]
+    t_bt = timed_steps(torch, lambda: binding.minplus_backtrack(JT, arg), steps, warmup)
+    a_bytes = T * B * m * m * 4
+    fwd_bytes = a_bytes + T * B * m * 4 + 2 * B * m * 4  # A read, minimisers written, J read and written
+    return {
+        "workload": inst.name,
+        "problems": B,
+        "states": m,
+        "days": T,
+        "generator_ms": t_gen * 1e3,
+        "generator_gbs": a_bytes / t_gen / 1e9,
+        "forward_ms": t_fwd * 1e3,
+        "forward_gbs": fwd_bytes / t_fwd / 1e9,
+        "forward_hbm_frac": fwd_bytes / t_fwd / 1e9 / HBM_PEAK_GBS,
+        "forward_minplus_ops_per_s": T * B * m * m / t_fwd,
+        "backtrack_ms": t_bt * 1e3,
+        "mean_terminal_cost": float(JT.double().min(dim=1).values.mean().item()),
+    }
+
+
 def served(torch, binding, W, num_requests, pool_size, budget_gb, seed=5):
     """Served stream: Poisson arrivals of single-tour requests (n ~ U{50..1000},
     S ~ 10^U(3,5), Q in {80,150,300}) drawn from a pool of distinct instances
@@ -321,6 +364,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-routes", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-minplus", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-requests", type=int, default=10_000)
     ap.add_argument("--served-pool", type=int, default=32)
@@ -433,6 +477,9 @@ def main():
     if not args.no_variants:
         log("split variants (soft capacity, fleet bound)")
         result["variants"] = split_variants(torch, binding, t, d, q, inst, cells, args.steps, args.warmup)
+    if not args.no_minplus:
+        log("inventory DP on the min-plus update")
+        result["inventory_minplus"] = inventory_minplus(torch, binding, W, max(2, args.steps // 4), 2)
     if not args.no_batched:
         log("batched vs plain (256 ragged tours, S=10^4)")
         result["batched"] = batched_vs_plain(torch, binding, W, reps=20)

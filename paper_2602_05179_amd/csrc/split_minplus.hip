@@ -16,10 +16,12 @@
 // reads as +inf).
 //
 // Layout: one wave per batch element, its J in LDS (double buffer); lane j
-// owns target state j (and j + 64, ...), reads column j of A_t row by row
-// (row i of A_t is contiguous, so each row read is coalesced across lanes)
-// and J_t(i) as an LDS broadcast.  With A per element the update streams
-// T * m * m * 4 bytes per element: HBM-bound.
+// owns target state j (and j + 64, ...) and reads J_t(i) as an LDS
+// broadcast.  Up to 32 states each stage's matrix is staged in LDS with
+// full-wave dword loads issued one stage ahead; larger ones are read column
+// by column from global memory (row i of A_t is contiguous, so each row read is coalesced
+// across lanes).  With A per element the update streams T * m * m * 4
+// bytes per element: HBM-bound.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -95,6 +97,78 @@ __global__ __launch_bounds__(kWave) void minplus_forward_kernel(
         JT[b * m + j] = (int32_t)cur[j];
 }
 
+// Small state spaces (m <= 32): each stage's matrix (m*m <= 1024 int32,
+// contiguous) is read with all 64 lanes loading consecutive dwords into
+// registers one stage ahead, stored to LDS, and the update reads it from
+// there, so the loads of stage t+1 are in flight while stage t is relaxed.
+// grid = B waves; LDS: (2m + m*m) int32.
+constexpr int kStagedMaxStates = 32;
+constexpr int kStagedRegs = kStagedMaxStates * kStagedMaxStates / 64; // dwords per lane
+
+__global__ __launch_bounds__(kWave) void minplus_forward_staged_kernel(
+    const int32_t *__restrict__ A, int32_t shared, int32_t T, int32_t m, int64_t B,
+    const int32_t *__restrict__ J0, int32_t *__restrict__ JT, int32_t *__restrict__ arg)
+{
+    extern __shared__ uint32_t sm[];
+    const int64_t b = blockIdx.x;
+    const int lane = threadIdx.x;
+    uint32_t *cur = sm, *nxt = sm + m, *sA = sm + 2 * m;
+    const int mm = m * m;
+    auto stage_ptr = [&](int t) {
+        return reinterpret_cast<const uint32_t *>(shared ? A + (int64_t)t * mm
+                                                         : A + ((int64_t)t * B + b) * mm);
+    };
+    for (int j = lane; j < m; j += kWave)
+        cur[j] = min((uint32_t)J0[b * m + j], kMpInf);
+    uint32_t pre[kStagedRegs];
+    {
+        const uint32_t *A0 = stage_ptr(0);
+#pragma unroll
+        for (int c = 0; c < kStagedRegs; ++c) {
+            const int e = lane + kWave * c;
+            pre[c] = e < mm ? A0[e] : 0u;
+        }
+    }
+    for (int t = 0; t < T; ++t) {
+#pragma unroll
+        for (int c = 0; c < kStagedRegs; ++c) {
+            const int e = lane + kWave * c;
+            if (e < mm)
+                sA[e] = min(pre[c], kMpInf);
+        }
+        __syncthreads();
+        if (t + 1 < T) { // next stage's matrix, in flight during this stage
+            const uint32_t *An = stage_ptr(t + 1);
+#pragma unroll
+            for (int c = 0; c < kStagedRegs; ++c) {
+                const int e = lane + kWave * c;
+                pre[c] = e < mm ? An[e] : 0u;
+            }
+        }
+        if (lane < m) {
+            const int j = lane;
+            uint32_t best = kMpInf;
+            int bi = -1;
+            for (int i = 0; i < m; ++i) {
+                const uint32_t c = sat_add(sA[i * m + j], cur[i]);
+                if (c < best) { // strict: the smallest i keeps a tie
+                    best = c;
+                    bi = i;
+                }
+            }
+            nxt[j] = best;
+            if (arg)
+                arg[((int64_t)t * B + b) * m + j] = best < kMpInf ? bi : -1;
+        }
+        __syncthreads();
+        uint32_t *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+    for (int j = lane; j < m; j += kWave)
+        JT[b * m + j] = (int32_t)cur[j];
+}
+
 // one thread per element: the smallest minimising final state, then back
 // through the recorded minimisers; -1 throughout when J_T is all +inf
 __global__ void minplus_backtrack_kernel(const int32_t *__restrict__ JT,
@@ -124,43 +198,42 @@ __global__ void minplus_backtrack_kernel(const int32_t *__restrict__ JT,
     }
 }
 
-// one thread per entry A_t[b](I, J) of the order-up-to instance
-__global__ void ou_transitions_kernel(int32_t U, int32_t T, int64_t B, int32_t R,
-                                      const int32_t *__restrict__ demand,
-                                      const int32_t *__restrict__ opt_cost,
-                                      const int32_t *__restrict__ opt_cap,
-                                      const int32_t *__restrict__ h, int32_t u, int32_t rho,
-                                      int32_t *__restrict__ A)
+// one wave per (day, problem) tb = t*B + b: the cheapest route option with
+// room for each delivery size q (LDS), then the lanes write the entries
+// A(I, J) of its matrix in row-major order (coalesced)
+constexpr int kGenThreads = 64;
+
+__global__ __launch_bounds__(kGenThreads) void ou_transitions_kernel(
+    int32_t U, int64_t TB, int32_t R, const int32_t *__restrict__ demand,
+    const int32_t *__restrict__ opt_cost, const int32_t *__restrict__ opt_cap,
+    const int32_t *__restrict__ h, int32_t u, int32_t rho, int32_t *__restrict__ A)
 {
-    const int64_t m = (int64_t)U + 1;
-    const int64_t total = (int64_t)T * B * m * m;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int J = (int)(e % m);
-        const int I = (int)((e / m) % m);
-        const int64_t tb = e / (m * m); // t * B + b
-        const int d = demand[tb];
-        long long best = kMpInf;
-        for (int pass = 0; pass < 2; ++pass) {
-            const int q = pass == 0 ? 0 : U - I;
-            if (pass == 1 && q == 0)
-                break; // I = U: delivering up to U is no delivery
-            if (max(0, I + q - d) != J)
-                continue;
-            long long tr = 0;
-            if (q > 0) {
-                long long c = kMpInf;
-                for (int r = 0; r < R; ++r)
-                    if (opt_cap[tb * R + r] >= q)
-                        c = min(c, (long long)opt_cost[tb * R + r]);
-                if (c >= kMpInf)
-                    continue; // no route option has room for the delivery
-                tr = c + (long long)u * q;
-            }
-            const long long cost = tr + h[J] + (long long)rho * max(0, d - I - q);
-            best = min(best, cost);
+    extern __shared__ long long tr[]; // transport(q), q = 0..U (kMpInf: impossible)
+    const int m = U + 1;
+    for (int64_t tb = blockIdx.x; tb < TB; tb += gridDim.x) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < m; q += blockDim.x) {
+            long long c = q == 0 ? 0 : (long long)kMpInf;
+            for (int r = 0; q > 0 && r < R; ++r)
+                if (opt_cap[tb * R + r] >= q)
+                    c = min(c, (long long)opt_cost[tb * R + r]);
+            tr[q] = c >= kMpInf ? (long long)kMpInf : c + (long long)u * q;
         }
-        A[e] = (int32_t)min(best, (long long)kMpInf);
+        __syncthreads();
+        const int d = demand[tb];
+        int32_t *out = A + tb * (int64_t)m * m;
+        for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+            const int I = e / m, J = e - I * m;
+            long long best = kMpInf;
+            // no delivery
+            if (max(0, I - d) == J)
+                best = (long long)h[J] + (long long)rho * max(0, d - I);
+            // deliver up to U (a distinct choice only when I < U)
+            const int q = U - I;
+            if (q > 0 && tr[q] < kMpInf && max(0, U - d) == J)
+                best = min(best, tr[q] + h[J] + (long long)rho * max(0, d - U));
+            out[e] = (int32_t)min(best, (long long)kMpInf);
+        }
     }
 }
 
@@ -170,8 +243,14 @@ hipError_t launch_minplus_forward(const int32_t *A, int32_t shared, int32_t T, i
                                   int64_t B, const int32_t *J0, int32_t *JT, int32_t *arg,
                                   hipStream_t stream)
 {
-    hipLaunchKernelGGL(minplus_forward_kernel, dim3((unsigned)B), dim3(kWave),
-                       (size_t)2 * m * sizeof(uint32_t), stream, A, shared, T, m, B, J0, JT, arg);
+    if (m <= kStagedMaxStates)
+        hipLaunchKernelGGL(minplus_forward_staged_kernel, dim3((unsigned)B), dim3(kWave),
+                           (size_t)(2 * m + m * m) * sizeof(uint32_t), stream, A, shared, T, m, B,
+                           J0, JT, arg);
+    else
+        hipLaunchKernelGGL(minplus_forward_kernel, dim3((unsigned)B), dim3(kWave),
+                           (size_t)2 * m * sizeof(uint32_t), stream, A, shared, T, m, B, J0, JT,
+                           arg);
     return hipGetLastError();
 }
 
@@ -189,12 +268,11 @@ hipError_t launch_ou_transitions(int32_t U, int32_t T, int64_t B, int32_t R,
                                  const int32_t *opt_cap, const int32_t *h, int32_t u, int32_t rho,
                                  int32_t *A, hipStream_t stream)
 {
-    const int64_t total = (int64_t)T * B * ((int64_t)U + 1) * ((int64_t)U + 1);
-    int64_t blocks = (total + 255) / 256;
-    if (blocks > 65536)
-        blocks = 65536;
-    hipLaunchKernelGGL(ou_transitions_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, U, T,
-                       B, R, demand, opt_cost, opt_cap, h, u, rho, A);
+    const int64_t TB = (int64_t)T * B;
+    const int64_t blocks = TB < (1 << 20) ? TB : (1 << 20);
+    hipLaunchKernelGGL(ou_transitions_kernel, dim3((unsigned)blocks), dim3(kGenThreads),
+                       ((size_t)U + 1) * sizeof(long long), stream, U, TB, R, demand, opt_cost,
+                       opt_cap, h, u, rho, A);
     return hipGetLastError();
 }
 

@@ -256,3 +256,43 @@ def as_arrays(inst: Instance):
     """Contiguous arrays in the C-ABI layout."""
     return (np.ascontiguousarray(inst.tours, np.int32), np.ascontiguousarray(inst.lens, np.int32),
             np.ascontiguousarray(inst.dist, np.int32), np.ascontiguousarray(inst.demands, np.int16))
+
+
+@dataclasses.dataclass
+class InventoryInstance:
+    """Order-up-to inventory reinsertion instance: B = customers x scenarios
+    independent problems over T days with inventory states 0..U."""
+    name: str
+    U: int
+    demand: np.ndarray    # int32 [T, B]
+    opt_cost: np.ndarray  # int32 [T, B, R] insertion cost of each route option
+    opt_cap: np.ndarray   # int32 [T, B, R] residual capacity of each route option
+    h: np.ndarray         # int32 [U+1] end-of-day cost of each inventory level
+    u: int                # unit transport cost
+    rho: int              # unit shortage penalty
+    I0: np.ndarray        # int32 [B] initial inventories
+    seed: int
+
+
+def inventory_ou(seed: int = 6, customers: int = 100, scenarios: int = 1000, U: int = 20, T: int = 7,
+                 R: int = 4) -> InventoryInstance:
+    """Per customer: daily demand mean mu ~ U[1, U/3], demands Poisson(mu)
+    clipped to [0, U + 2] per day and scenario; holding cost h ~ U{1..5} per
+    unit, shortage penalty 4 h per unit (rho > 1 times holding); R route
+    options per day and scenario with insertion costs U{5..60} and residual
+    capacities U{0..U}; unit transport cost 1; initial inventory U{0..U}.
+    Problem b = c * scenarios + s."""
+    rng = np.random.default_rng(seed)
+    B = customers * scenarios
+    mu = rng.uniform(1.0, max(1.0, U / 3.0), size=customers)
+    lam = np.repeat(mu, scenarios)
+    demand = np.minimum(rng.poisson(lam[None, :], size=(T, B)), U + 2).astype(np.int32)
+    hc = rng.integers(1, 6, size=customers)
+    # one h table per instance: the mean customer's holding cost (tables are shared)
+    h = (int(np.round(hc.mean())) * np.arange(U + 1)).astype(np.int32)
+    rho = 4 * int(np.round(hc.mean()))
+    opt_cost = rng.integers(5, 61, size=(T, B, R)).astype(np.int32)
+    opt_cap = rng.integers(0, U + 1, size=(T, B, R)).astype(np.int32)
+    I0 = np.repeat(rng.integers(0, U + 1, size=customers), scenarios).astype(np.int32)
+    return InventoryInstance("inventory OU %d customers x %d scenarios U=%d T=%d R=%d" % (customers, scenarios, U, T, R),
+                             U, demand, opt_cost, opt_cap, h, 1, rho, I0, seed)
