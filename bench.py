@@ -12,7 +12,8 @@ Also reported on the same line: scenarios/s, the main kernel's roofline
 CPU oracle's throughput on a bounded sample of the same workload, route
 recovery of the same tour (predecessors and cut points of every scenario),
 the split variants (soft capacity, fleet bound), the order-up-to inventory
-DP on the generic min-plus update, the batched form (256 ragged tours in one captured graph vs one launch per
+DP on the generic min-plus update, the candidate search under a fixed time
+budget (GPU vs CPU oracle as evaluator), the batched form (256 ragged tours in one captured graph vs one launch per
 tour) and the served form.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -291,6 +292,40 @@ def inventory_minplus(torch, binding, W, steps, warmup):
     }
 
 
+def search_budget(torch, binding, W, budget_s, seed=12):
+    """First-stage candidate search under a fixed wall-clock budget (the
+    shape of the paper's fixed-time-budget comparison): the same genetic
+    algorithm and seed with the GPU evaluator and with the CPU oracle
+    (all usable host threads) as evaluator, on one instance with 10^4
+    scenarios."""
+    import numpy as np
+    import oracle
+    inst = W.plain_normal(seed, 100, 10_000, 100)
+    tours, lens, dist, dem = W.as_arrays(inst)
+    dev = torch.device("cuda:0")
+    d, q = torch.from_numpy(dist).to(dev), torch.from_numpy(dem).to(dev)
+    kw = dict(population=64, offspring=256, time_budget_s=budget_s, mutation=0.3, seed=seed)
+    gpu = binding.search(d, q, inst.Q, **kw)
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+
+    def ev(t):
+        return oracle.split_eval(t.ravel(), np.full(t.shape[0], t.shape[1], np.int32), dist, dem, inst.Q,
+                                 nthreads=cores)["sums"]
+
+    cpu = binding.search(dist, dem, inst.Q, evaluator=ev, **kw)
+    S = inst.S
+
+    def summary(r):
+        tr = r["trace"]
+        return {"candidates": r["candidates"], "generations": len(tr) - 1, "best_mean": r["best_sum"] / S,
+                "candidates_per_s": r["candidates"] / max(tr[-1, 0], 1e-9),
+                "first_mean": tr[0, 2] / S}
+
+    return {"workload": "GA over giant tours, n=100, S=10^4, Q=100, population 64, 256 candidates per "
+                        "generation, %.0f s budget each, seed %d" % (budget_s, seed),
+            "gpu": summary(gpu), "cpu_oracle": dict(summary(cpu), cores=cores)}
+
+
 def served(torch, binding, W, num_requests, pool_size, budget_gb, seed=5):
     """Served stream: Poisson arrivals of single-tour requests (n ~ U{50..1000},
     S ~ 10^U(3,5), Q in {80,150,300}) drawn from a pool of distinct instances
@@ -365,6 +400,8 @@ def main():
     ap.add_argument("--no-routes", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-minplus", action="store_true")
+    ap.add_argument("--search-budget", type=float, default=5.0,
+                    help="seconds per evaluator for the candidate-search comparison (0: skip)")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-requests", type=int, default=10_000)
     ap.add_argument("--served-pool", type=int, default=32)
@@ -480,6 +517,9 @@ def main():
     if not args.no_minplus:
         log("inventory DP on the min-plus update")
         result["inventory_minplus"] = inventory_minplus(torch, binding, W, max(2, args.steps // 4), 2)
+    if args.search_budget > 0:
+        log("candidate search, %.0f s budget per evaluator" % args.search_budget)
+        result["search"] = search_budget(torch, binding, W, args.search_budget)
     if not args.no_batched:
         log("batched vs plain (256 ragged tours, S=10^4)")
         result["batched"] = batched_vs_plain(torch, binding, W, reps=20)

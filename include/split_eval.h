@@ -279,6 +279,56 @@ int split_ou_transitions_device(int32_t U, int32_t T, int64_t B, int32_t R,
                                 int32_t rho, int32_t *d_A, split_stream_t stream);
 
 /*
+ * First-stage candidate search: a genetic algorithm over giant tours whose
+ * candidates are all evaluated on every scenario by the batched split (the
+ * paper's candidate-based scheme, Sec. 4 "decision quality under fixed
+ * time budgets"; the appendix tables of candidates explored vs objective).
+ * (mu + lambda) generations: binary-tournament parents on the exact
+ * scenario sum, order crossover, a random segment reversal with probability
+ * `mutation`, the `offspring` children of a generation evaluated in one
+ * batched call, and the best `population` of parents and children kept
+ * (stable: on equal sums parents first).  Deterministic for a seed
+ * (splitmix64 stream); with the same seed two evaluators that return the
+ * same sums give the same search.
+ */
+typedef struct {
+    int32_t population;   /* tours kept per generation (mu), >= 2 */
+    int32_t offspring;    /* candidates evaluated per generation (lambda), >= 1 */
+    int32_t generations;  /* generation limit; <= 0: none */
+    double time_budget_s; /* wall-clock limit in seconds; <= 0: none (one limit is required) */
+    double mutation;      /* probability of a segment reversal per child, in [0, 1] */
+    uint64_t seed;        /* random stream */
+} split_search_params;
+
+/* Caller-supplied evaluator: exact scenario sums of `count` host tours of n
+ * customers each (tours[k*n .. k*n+n-1]); INT64_MAX for an infeasible tour;
+ * returns 0 on success. */
+typedef int (*split_search_eval_fn)(void *ctx, const int32_t *tours, int32_t count, int32_t n,
+                                    int64_t *sums);
+
+/*
+ * split_search_run -- runs the search over permutations of customers 1..N.
+ *   d_dist, d_demands, S, Q  DEVICE inputs as in split_eval_device (used by
+ *            the built-in evaluator: one captured evaluation plan per batch
+ *            size, on `stream`, buffers allocated and freed by the call)
+ *   init_tour   host int32 [N], a permutation seeding the population (may be NULL)
+ *   evaluator, evaluator_ctx  optional host evaluator replacing the GPU one
+ *   best_tour   out host int32 [N]; best_sum  out: its scenario sum
+ *   candidates  out: tours evaluated (population + generations * offspring)
+ *   trace       out host double [trace_cap][3] (may be NULL if trace_cap = 0):
+ *               per generation (0 = initial population) the elapsed seconds,
+ *               the candidates evaluated so far and the best sum
+ *   trace_len   out: generations recorded (may exceed trace_cap)
+ * SPLIT_EINVAL for bad parameters or an init_tour that is not a permutation;
+ * errors of the evaluator are returned as they come.  Synchronous.
+ */
+int split_search_run(const int32_t *d_dist, int32_t N, const int16_t *d_demands, int64_t S,
+                     int32_t Q, const int32_t *init_tour, const split_search_params *params,
+                     split_search_eval_fn evaluator, void *evaluator_ctx, int32_t *best_tour,
+                     int64_t *best_sum, int64_t *candidates, double *trace, int32_t trace_cap,
+                     int32_t *trace_len, split_stream_t stream);
+
+/*
  * split_count_cells_device -- Bellman-cell counter (measurement utility).
  * For each tour writes the number of capacity-admissible relaxations
  * (s, p, i), i.e. sum over scenarios and positions i of the number of

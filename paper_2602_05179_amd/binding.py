@@ -57,7 +57,17 @@ EXPORTED = (
     "split_minplus_forward_device",
     "split_minplus_backtrack_device",
     "split_ou_transitions_device",
+    "split_search_run",
 )
+
+
+class SearchParams(ctypes.Structure):
+    _fields_ = [("population", ctypes.c_int32), ("offspring", ctypes.c_int32), ("generations", ctypes.c_int32),
+                ("time_budget_s", ctypes.c_double), ("mutation", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+SEARCH_EVAL_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                                  ctypes.c_int32, ctypes.POINTER(ctypes.c_int64))
 
 
 class SplitError(RuntimeError):
@@ -137,6 +147,9 @@ def _load():
     lib.split_variant_workspace_bytes.restype = sz
     lib.split_variant_workspace_bytes.argtypes = [i32, i32, i64, i32]
     lib.split_variant_device.restype = ctypes.c_int
+    lib.split_search_run.restype = ctypes.c_int
+    lib.split_search_run.argtypes = [P, i32, P, i64, i32, P, ctypes.POINTER(SearchParams), P, P, P,
+                                     ctypes.POINTER(i64), ctypes.POINTER(i64), P, i32, ctypes.POINTER(i32), P]
     lib.split_minplus_forward_device.restype = ctypes.c_int
     lib.split_minplus_forward_device.argtypes = [P, i32, i32, i32, i64, P, P, P, P]
     lib.split_minplus_backtrack_device.restype = ctypes.c_int
@@ -469,6 +482,47 @@ def ou_transitions(U, demand, opt_cost, opt_cap, h, u, rho, *, out=None, stream=
     _check(lib.split_ou_transitions_device(int(U), T, B, R, _dptr(demand), _dptr(opt_cost), _dptr(opt_cap),
                                            _dptr(h), int(u), int(rho), _dptr(out), _stream_handle(stream)))
     return out
+
+
+# ---------------------------------------------------------------------------
+# first-stage candidate search (genetic algorithm over giant tours)
+# ---------------------------------------------------------------------------
+def search(dist, demands, Q, *, population=64, offspring=256, generations=0, time_budget_s=0.0, mutation=0.3,
+           seed=1, init_tour=None, evaluator=None, trace_cap=100000, stream=None):
+    """Run the search over permutations of 1..N.  dist and demands are
+    device tensors (int32 [N+1, N+1], int16 [S, N]) for the GPU evaluator;
+    with `evaluator` (a Python callable(tours int32 [count, n] numpy) ->
+    int64 [count] sums replacing it) only their shapes are used.  Returns dict(best_tour, best_sum,
+    candidates, trace float64 [generations+1, 3] = (seconds, candidates, best sum))."""
+    N = int(dist.shape[0] - 1)
+    S = int(demands.shape[0])
+    params = SearchParams(int(population), int(offspring), int(generations), float(time_budget_s),
+                          float(mutation), int(seed))
+    best = np.empty(N, np.int32)
+    best_sum, cand, tlen = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+    trace = np.zeros((max(int(trace_cap), 1), 3), np.float64)
+    init = None
+    if init_tour is not None:
+        init = np.ascontiguousarray(init_tour, np.int32)
+    cb = None
+    if evaluator is not None:
+        def _cb(ctx, tours_p, count, n, sums_p):
+            try:
+                tours = np.ctypeslib.as_array(tours_p, shape=(count * n,)).reshape(count, n).copy()
+                out = np.asarray(evaluator(tours), dtype=np.int64)
+                np.ctypeslib.as_array(sums_p, shape=(count,))[:] = out
+                return 0
+            except Exception:  # reported to the caller as an evaluator error
+                return 1
+        cb = SEARCH_EVAL_FN(_cb)
+    on_gpu = evaluator is None
+    _check(lib.split_search_run(_dptr(dist) if on_gpu else None, N, _dptr(demands) if on_gpu else None, S, int(Q),
+                                _np_ptr(init) if init is not None else None, ctypes.byref(params),
+                                ctypes.cast(cb, ctypes.c_void_p) if cb is not None else None, None,
+                                _np_ptr(best), ctypes.byref(best_sum), ctypes.byref(cand), _np_ptr(trace),
+                                int(trace_cap), ctypes.byref(tlen), _stream_handle(stream) if on_gpu else None))
+    n_tr = min(int(tlen.value), int(trace_cap))
+    return dict(best_tour=best, best_sum=int(best_sum.value), candidates=int(cand.value), trace=trace[:n_tr].copy())
 
 
 def tune_device(tours, lens, dist, demands, Q, *, max_len=None, reps=5, stream=None) -> float:

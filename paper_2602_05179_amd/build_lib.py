@@ -12,7 +12,8 @@ LIB = os.path.join(PKG, "libsplit_eval.so")
 SOURCES = [os.path.join(CSRC, "split_kernels.hip"), os.path.join(CSRC, "split_api.cpp"),
            os.path.join(CSRC, "split_server.cpp"), os.path.join(CSRC, "split_tune.cpp"),
            os.path.join(CSRC, "split_probe.hip"), os.path.join(CSRC, "split_routes.hip"),
-           os.path.join(CSRC, "split_variant.hip"), os.path.join(CSRC, "split_minplus.hip")]
+           os.path.join(CSRC, "split_variant.hip"), os.path.join(CSRC, "split_minplus.hip"),
+           os.path.join(CSRC, "split_search.cpp")]
 HEADERS = [os.path.join(INCLUDE, "split_eval.h"), os.path.join(CSRC, "split_internal.h"),
            os.path.join(CSRC, "split_device.h"), os.path.join(CSRC, "window_min_asm.inc"),
            os.path.join(CSRC, "window_argmin_asm.inc"), os.path.join(CSRC, "split_variant.h"),
