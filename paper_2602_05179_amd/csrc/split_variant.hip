@@ -103,9 +103,11 @@ template <int R, bool SOFT, bool LAYERED, int U> struct VarState {
         const int2 t3 = tab_at(tab, j + 3);
         int pf2 = kInf;
         if constexpr (LAYERED) {
-            if (has_src && j + 2 <= n - 1)
-                pf2 = *r.srcp;
-            r.srcp += S;
+            if (has_src) { // uniform: the first pass has no previous potentials
+                if (j + 2 <= n - 1)
+                    pf2 = *r.srcp;
+                r.srcp += S;
+            }
         }
         const int L = r.L;
         if (j == n)
