@@ -17,7 +17,8 @@ SOURCES = [os.path.join(CSRC, "split_kernels.hip"), os.path.join(CSRC, "split_ap
 HEADERS = [os.path.join(INCLUDE, "split_eval.h"), os.path.join(CSRC, "split_internal.h"),
            os.path.join(CSRC, "split_device.h"), os.path.join(CSRC, "window_min_asm.inc"),
            os.path.join(CSRC, "window_argmin_asm.inc"), os.path.join(CSRC, "split_variant.h"),
-           os.path.join(CSRC, "split_minplus.h")]
+           os.path.join(CSRC, "split_minplus.h"),
+           os.path.join(CSRC, "window_min_multi_asm.inc")]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are disabled for every GPU object this library

@@ -48,6 +48,7 @@ constexpr int kFeasible = 1 << 29;
 constexpr int ST_PENALTY_RANGE = 4;
 
 #include "window_min_asm.inc"
+#include "window_min_multi_asm.inc"
 
 // hard capacity: the evaluator's window variant for each ring length
 template <int R> struct HardWindow;
@@ -225,6 +226,239 @@ __device__ __forceinline__ int var_pass(const uint8_t *row, CInt *tab, const Tou
     ovf = r.ovf != 0;
     Ltot = r.lastL;
     return r.mres;
+}
+
+__device__ __forceinline__ bool penalty_fits(const TourRec &rec, int beta, int Q, int Ltot);
+
+// ---------------------------------------------------------------------------
+// fleet bound: NL passes per sweep over the tour.  Every pass
+// relaxes the same admissible window (it depends on loads only), so one
+// masked scan (window_min_multi_asm.inc) serves NL potential rings: ring 0
+// holds the previous sweep's last pass (streamed from the workspace), ring
+// g the potentials that ring g-1 produces in this sweep, and only the last
+// ring's potentials are written out for the next sweep.
+// ---------------------------------------------------------------------------
+template <int NL> struct VarMultiRegs {
+    int L, qa;
+    int2 t0, t1, t2;
+    int pf0, pf1;
+    int mres[NL];
+    int mret[NL]; // soft: min over retired cells of f_p - beta (L_p + Q), per ring
+    int lastL;
+    int ovf;
+    uint64_t cp1, cp2;
+    const int *srcp;
+    int *dstp;
+};
+
+template <int R, int NL, bool SOFT, int U> struct VarMultiState {
+    __device__ __forceinline__ static bool run(int (&f)[NL][R], int (&lq)[R], VarMultiRegs<NL> &r,
+                                               const uint8_t *row, CInt *tab, int j0, int n,
+                                               int Q, int beta, bool has_src, int64_t S)
+    {
+        const int j = j0 + U;
+        if (U == 0 && j == 0)
+            return true;
+        if (j > n)
+            return false;
+        const int cj = r.t0.y;
+        const int Ln = r.L + r.qa;
+        r.qa = row[r.t2.x];
+        const int2 t3 = tab_at(tab, j + 3);
+        int pf2 = kInf;
+        if (has_src) {
+            if (j + 2 <= n - 1)
+                pf2 = *r.srcp;
+            r.srcp += S;
+        }
+        const int L = r.L;
+        if (j == n)
+            r.lastL = L;
+        int m[NL];
+        if constexpr (SOFT) {
+            // the penalty of a cell is the same for every pass: once per cell
+#pragma unroll
+            for (int g = 0; g < NL; ++g)
+                m[g] = r.mret[g] + (int)__umul24((unsigned)beta, (unsigned)L);
+#pragma unroll
+            for (int d = 1; d <= R; ++d) {
+                const int pen = (int)__umul24((unsigned)beta,
+                                              (unsigned)max(L - lq[(U - d) & (R - 1)], 0));
+#pragma unroll
+                for (int g = 0; g < NL; ++g)
+                    m[g] = min(m[g], f[g][(U - d) & (R - 1)] + pen);
+            }
+            if (j > R && L <= lq[U])
+                r.ovf = 1;
+            if (j >= R) { // slot U holds p = j - R >= 0, leaving the ring
+                const int bq = (int)__umul24((unsigned)beta, (unsigned)lq[U]);
+#pragma unroll
+                for (int g = 0; g < NL; ++g)
+                    r.mret[g] = min(r.mret[g], f[g][U] - bq);
+            }
+        } else {
+            using HW = HardWindow<R>;
+            uint64_t cn1, cn2;
+            WindowMinMulti<R, HW::F, HW::G, HW::E, NL>::template run<U>(f, lq, L, Ln, j, r.cp1,
+                                                                        r.cp2, cn1, cn2, r.ovf, m);
+            r.cp1 = cn1;
+            r.cp2 = cn2;
+        }
+#pragma unroll
+        for (int g = 0; g < NL; ++g) {
+            m[g] = min(m[g], kInf);
+            r.mres[g] = m[g];
+        }
+        if (j <= n - 1)
+            *r.dstp = m[NL - 1] + cj;
+        r.dstp += S;
+#pragma unroll
+        for (int g = NL - 1; g >= 1; --g)
+            f[g][U] = m[g - 1] + cj;
+        f[0][U] = r.pf0;
+        r.pf0 = r.pf1;
+        r.pf1 = pf2;
+        lq[U] = L + Q;
+        r.L = Ln;
+        r.t0 = r.t1;
+        r.t1 = r.t2;
+        r.t2 = t3;
+        return true;
+    }
+};
+
+template <int R, int NL, bool SOFT, int... Us>
+__device__ __forceinline__ bool var_multi_block(int (&f)[NL][R], int (&lq)[R],
+                                                VarMultiRegs<NL> &r, const uint8_t *row,
+                                                CInt *tab, int j0, int n, int Q, int beta,
+                                                bool has_src, int64_t S,
+                                                std::integer_sequence<int, Us...>)
+{
+    return (VarMultiState<R, NL, SOFT, Us>::run(f, lq, r, row, tab, j0, n, Q, beta, has_src, S) &&
+            ...);
+}
+
+// One sweep: passes k0 .. k0+NL-1.  src: pass k0-1's potentials (nullptr
+// when k0 = 1); dst: pass k0+NL-1's.  m_n of every pass in mres.
+template <int R, int NL, bool SOFT>
+__device__ __forceinline__ void var_sweep(const uint8_t *row, CInt *tab, const TourRec &rec, int Q,
+                                          int beta, int k0, const int *src, int *dst, int64_t S,
+                                          bool &ovf, int &Ltot, int (&mres)[NL])
+{
+    // slots before the tour start: +inf potentials; soft capacity gives them
+    // a threshold no load reaches, hard capacity one every load exceeds
+    int f[NL][R], lq[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        lq[i] = SOFT ? kInf : kNeg;
+#pragma unroll
+        for (int g = 0; g < NL; ++g)
+            f[g][i] = kInf;
+    }
+    // p = 0 of pass k0+g-1: V_0(0) = 0 for the pass before the first, +inf after
+    f[0][0] = k0 == 1 ? rec.f0 : kInf;
+    lq[0] = Q;
+    VarMultiRegs<NL> r;
+#pragma unroll
+    for (int g = 0; g < NL; ++g) {
+        r.mres[g] = kInf;
+        r.mret[g] = kInf;
+    }
+    r.lastL = 0;
+    r.ovf = 0;
+    r.cp1 = ~0ull;
+    r.cp2 = ~0ull;
+    r.t0 = tab_at(tab, 1);
+    r.t1 = tab_at(tab, 2);
+    r.t2 = tab_at(tab, 3);
+    r.L = row[r.t0.x];
+    r.qa = row[r.t1.x];
+    const int n = rec.n;
+    r.pf0 = kInf;
+    r.pf1 = kInf;
+    r.srcp = nullptr;
+    const bool has_src = src != nullptr;
+    if (has_src) {
+        if (n >= 2)
+            r.pf0 = src[S];
+        if (n >= 3)
+            r.pf1 = src[2 * S];
+        r.srcp = src + 3 * S;
+    }
+    r.dstp = dst + S;
+    for (int j0 = 0; j0 <= n; j0 += R) {
+        if (!var_multi_block<R, NL, SOFT>(f, lq, r, row, tab, j0, n, Q, beta, has_src, S,
+                                          std::make_integer_sequence<int, R>{}))
+            break;
+    }
+    ovf = r.ovf != 0;
+    Ltot = r.lastL;
+#pragma unroll
+    for (int g = 0; g < NL; ++g)
+        mres[g] = r.mres[g];
+}
+
+// grid = tiles, one wave each; LDS as variant_tile_kernel.  Fleet bound
+// K > 0, hard or soft capacity.
+template <int R, int NL, bool SOFT>
+__global__ __launch_bounds__(kWave) void variant_multi_kernel(VarArgs a, Workspace ws,
+                                                              int32_t lds_bytes)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    const TourRec rec = ws.rec[0];
+    if (rec.status != ST_OK)
+        return;
+    const int64_t k = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t s0 = k * kWave;
+    const int rows = (int)min<int64_t>(kWave, a.S - s0);
+    if (rec.n == 0) {
+        if (lane < rows)
+            a.costs[s0 + lane] = 0;
+        return;
+    }
+    bool ok = false;
+    if (lds_bytes) {
+        int &s_bad = *reinterpret_cast<int *>(lds + (((size_t)kWave * a.N + 15) & ~(size_t)15));
+        ok = stage_tile_u8(a.demands + s0 * a.N, lds, (int64_t)rows * a.N, lane, kWave, s_bad);
+    }
+    bool redo = true;
+    if (ok) {
+        CInt *tab = (CInt *)ws.tab;
+        bool ovf = false, range_bad = false;
+        int best = kInf;
+        if (lane < rows) {
+            const uint8_t *row = lds + (int64_t)lane * a.N;
+            const int64_t s = s0 + lane;
+            const int passes = a.K < rec.n ? a.K : rec.n;
+            const int *src = nullptr;
+            int *dst = a.lay0 + s;
+            int Ltot = 0;
+            for (int k0 = 1; k0 <= passes; k0 += NL) {
+                bool o = false;
+                int mres[NL];
+                var_sweep<R, NL, SOFT>(row, tab, rec, a.Q, a.beta, k0, src, dst, a.S, o, Ltot,
+                                       mres);
+                ovf = ovf || o;
+#pragma unroll
+                for (int g = 0; g < NL; ++g)
+                    if (k0 + g <= passes)
+                        best = min(best, mres[g]);
+                src = dst;
+                dst = (dst == a.lay0 + s) ? a.lay1 + s : a.lay0 + s;
+            }
+            range_bad = !penalty_fits(rec, a.beta, a.Q, Ltot);
+        }
+        if (ballot(range_bad) != 0 && lane == 0)
+            atomicOr(&ws.rec[0].status, ST_PENALTY_RANGE);
+        redo = ballot(ovf) != 0;
+        if (!redo && lane < rows)
+            a.costs[s0 + lane] = best < kFeasible ? best + rec.bn : SPLIT_INF;
+    }
+    if (redo && lane == 0) {
+        const int slot = atomicAdd(ws.list_count, 1);
+        ws.list[slot] = (int)k;
+    }
 }
 
 // the scenario's penalty range fits the int32 and 24-bit arithmetic
@@ -422,15 +656,48 @@ hipError_t launch_variant_tiles(const VarArgs &a, const Workspace &ws, hipStream
     return hipGetLastError();
 }
 
+template <int R, int NL, bool SOFT>
+hipError_t launch_variant_multi(const VarArgs &a, const Workspace &ws, hipStream_t stream)
+{
+    static int lim = -1;
+    hipError_t e = allow_lds_once(
+        reinterpret_cast<const void *>(&variant_multi_kernel<R, NL, SOFT>), &lim);
+    if (e != hipSuccess)
+        return e;
+    const size_t lds = (((size_t)kTile * (size_t)a.N + 15) & ~(size_t)15) + 16;
+    const int32_t lds_bytes = lds <= (size_t)lim ? (int32_t)lds : 0;
+    hipLaunchKernelGGL((variant_multi_kernel<R, NL, SOFT>), dim3((unsigned)num_tiles(a.S)),
+                       dim3(kWave), (size_t)lds_bytes, stream, a, ws, lds_bytes);
+    return hipGetLastError();
+}
+
+// passes per sweep of the fleet-bounded kernels: as many rings as keep the
+// occupancy the LDS tile allows (3 waves per SIMD at N = 200); the soft
+// ring of 64 keeps one pass per sweep
+template <int R, bool SOFT> struct SweepRings;
+template <> struct SweepRings<32, false> {
+    static constexpr int NL = 3;
+};
+template <> struct SweepRings<64, false> {
+    static constexpr int NL = 2;
+};
+template <> struct SweepRings<32, true> {
+    static constexpr int NL = 2;
+};
+
 template <int R>
 hipError_t launch_variant_ring(const VarArgs &a, const Workspace &ws, hipStream_t stream)
 {
     const bool soft = a.beta >= 0, layered = a.K > 0;
-    if (soft)
-        return layered ? launch_variant_tiles<R, true, true>(a, ws, stream)
-                       : launch_variant_tiles<R, true, false>(a, ws, stream);
-    return layered ? launch_variant_tiles<R, false, true>(a, ws, stream)
-                   : launch_variant_tiles<R, false, false>(a, ws, stream);
+    if (!layered)
+        return soft ? launch_variant_tiles<R, true, false>(a, ws, stream)
+                    : launch_variant_tiles<R, false, false>(a, ws, stream);
+    if (!soft)
+        return launch_variant_multi<R, SweepRings<R, false>::NL, false>(a, ws, stream);
+    if constexpr (R == 32)
+        return launch_variant_multi<32, SweepRings<32, true>::NL, true>(a, ws, stream);
+    else
+        return launch_variant_tiles<R, true, true>(a, ws, stream);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
