@@ -362,7 +362,9 @@ int split_routes_device(const int32_t *d_tour, int32_t n, const int32_t *d_dist,
     bool use_ev = false;
     HIP_TRY(profile_events(&ev, &use_ev), "profile events");
     HIP_TRY(splitk::launch_routes(d_tour, n, d_dist, N, d_demands, S, Q, d_costs, d_pred, d_cuts,
-                                  d_nroutes, ws, static_cast<hipStream_t>(stream),
+                                  d_nroutes, ws,
+                                  splitk::routes_position_table(d_workspace, n, N, S),
+                                  static_cast<hipStream_t>(stream),
                                   splitk::choose_route_variant(Q), use_ev ? &ev : nullptr),
             "launch");
     return SPLIT_OK;

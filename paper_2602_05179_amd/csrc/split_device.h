@@ -90,4 +90,73 @@ __device__ __forceinline__ bool stage_tile_u8(const int16_t *__restrict__ src, u
     return s_bad == 0;
 }
 
+// ---------------------------------------------------------------------------
+// gathered staging: the demands of one tour's positions, in tour order,
+// lds[r * pitch + k] = demands[r * N + cust_k] as a byte for k < n, zero for
+// n <= k < pitch (cust_k = tab[k + 1].x, the per-tour table's customer
+// index).  Lanes take consecutive positions of one scenario row at a time,
+// so each load instruction reads a few lines of that row.  Returns false
+// (uniformly) when some value is outside [0, 255].
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool stage_tile_gather_u8(const int16_t *__restrict__ src, int N,
+                                                     int rows, const int2 *__restrict__ tab,
+                                                     int n, int pitch, uint8_t *lds, int tid,
+                                                     int nthreads, int &s_bad)
+{
+    if (tid == 0)
+        s_bad = 0;
+    __syncthreads();
+    uint32_t bad = 0;
+    for (int k0 = 0; k0 < pitch; k0 += nthreads) {
+        const int k = k0 + tid;
+        const int cust = k < n ? tab[k + 1].x : -1;
+        int r = 0;
+        for (; r + 8 <= rows; r += 8) {
+            int v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                v[u] = cust >= 0 ? src[(int64_t)(r + u) * N + cust] : 0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                bad |= (v[u] < 0 || v[u] > 255) ? 1u : 0u;
+                if (k < pitch)
+                    lds[(r + u) * pitch + k] = (uint8_t)v[u];
+            }
+        }
+        for (; r < rows; ++r) {
+            const int v = cust >= 0 ? src[(int64_t)r * N + cust] : 0;
+            bad |= (v < 0 || v > 255) ? 1u : 0u;
+            if (k < pitch)
+                lds[r * pitch + k] = (uint8_t)v;
+        }
+    }
+    if (ballot(bad != 0) != 0 && (tid & (kWave - 1)) == 0)
+        atomicOr(&s_bad, 1);
+    __syncthreads();
+    return s_bad == 0;
+}
+
+namespace {
+
+// The per-tour table re-indexed for a gathered tile: entry j = {j - 1, c_j}
+// for j = 1..n (the demand of position j is byte j - 1 of the lane's row),
+// and {n, 0} for entry 0 and the padding entries (byte n of a row is zero).
+__global__ void position_table_kernel(const int2 *__restrict__ tab, int n, int2 *__restrict__ out)
+{
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n + kTabPad;
+         j += gridDim.x * blockDim.x)
+        out[j] = (j >= 1 && j <= n) ? make_int2(j - 1, tab[j].y) : make_int2(n, 0);
+}
+
+} // namespace
+
+// Whether a one-tour kernel stages the tour's demands gathered (64 x (n+1)
+// bytes) instead of whole rows (64 x N bytes): when whole rows do not fit
+// the LDS limit, or the tour covers at most half of the pool.
+inline bool gather_tile(int32_t n, int32_t N, int lds_limit)
+{
+    const size_t rows_bytes = (((size_t)kWave * (size_t)N + 15) & ~(size_t)15) + 16;
+    return rows_bytes > (size_t)lds_limit || 2 * ((int64_t)n + 1) <= (int64_t)N;
+}
+
 } // namespace splitk

@@ -108,10 +108,12 @@ int compiled_route_variants(RouteVariant *out, int cap);
 RouteVariant choose_route_variant(int32_t Q); // override, else the default for Q
 void set_route_override(const RouteVariant &v); // ring 0 = automatic
 size_t routes_workspace_bytes(int32_t n, int32_t N, int64_t S);
+// where a route-recovery workspace keeps the position table of a gathered tile
+int2 *routes_position_table(void *workspace, int32_t n, int32_t N, int64_t S);
 hipError_t launch_routes(const int32_t *tour, int32_t n, const int32_t *dist, int32_t N,
                          const int16_t *demands, int64_t S, int32_t Q, int32_t *costs,
                          uint16_t *pred, uint16_t *cuts, int32_t *nroutes, const Workspace &ws,
-                         hipStream_t stream, const RouteVariant &v,
+                         int2 *tabp, hipStream_t stream, const RouteVariant &v,
                          const LaunchEvents *ev = nullptr);
 
 // Shape bucket used by the tuning table.

@@ -326,7 +326,8 @@ __device__ __forceinline__ void routes_tile(const int16_t *__restrict__ demands,
                                             int64_t S, int32_t Q, int32_t *__restrict__ costs,
                                             uint16_t *pred, uint16_t *cuts,
                                             int32_t *__restrict__ nroutes, const Workspace &ws,
-                                            int32_t lds_bytes, int key_bits)
+                                            int32_t lds_bytes, int32_t pitch, const int2 *tabp,
+                                            int key_bits)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     const TourRec rec = ws.rec[0];
@@ -345,18 +346,23 @@ __device__ __forceinline__ void routes_tile(const int16_t *__restrict__ demands,
         }
         return;
     }
+    // whole scenario rows (pitch 0: row stride N, indexed by customer) or the
+    // tour's demands gathered in tour order (row stride pitch, by position)
+    const int stride = pitch ? pitch : N;
     bool ok = false;
     if (lds_bytes) {
-        int &s_bad = *reinterpret_cast<int *>(lds + (((size_t)kWave * N + 15) & ~(size_t)15));
-        ok = stage_tile_u8(demands + s0 * N, lds, (int64_t)rows * N, lane, kWave, s_bad);
+        int &s_bad = *reinterpret_cast<int *>(lds + (((size_t)kWave * stride + 15) & ~(size_t)15));
+        ok = pitch ? stage_tile_gather_u8(demands + s0 * N, N, rows, ws.tab, rec.n, pitch, lds, lane,
+                                          kWave, s_bad)
+                   : stage_tile_u8(demands + s0 * N, lds, (int64_t)rows * N, lane, kWave, s_bad);
     }
     bool redo = true;
     if (ok) {
-        CInt *tab = (CInt *)ws.tab;
+        CInt *tab = (CInt *)(pitch ? tabp : ws.tab);
         bool ovf = false;
         int v = kInf;
         if (lane < rows) {
-            const uint8_t *row = lds + (int64_t)lane * N;
+            const uint8_t *row = lds + (int64_t)lane * stride;
             if constexpr (KEYS) {
                 v = rk_lane<R, F, G, E>(row, tab, rec, Q, pred + s0, S, lane, ovf);
             } else {
@@ -392,10 +398,10 @@ template <int R, int F, int G, int E>
 __global__ __launch_bounds__(kWave) void routes_key_kernel(
     const int16_t *__restrict__ demands, int32_t N, int64_t S, int32_t Q,
     int32_t *__restrict__ costs, uint16_t *pred, uint16_t *cuts, int32_t *__restrict__ nroutes,
-    Workspace ws, int32_t lds_bytes)
+    Workspace ws, int32_t lds_bytes, int32_t pitch, const int2 *tabp)
 {
     routes_tile<true, R, F, G, E>(demands, N, S, Q, costs, pred, cuts, nroutes, ws, lds_bytes,
-                                  key_shift<R>());
+                                  pitch, tabp, key_shift<R>());
 }
 
 // Same grid and LDS; serves the tours that keys of key_bits cannot hold.
@@ -403,10 +409,10 @@ template <int R, int F, int E>
 __global__ __launch_bounds__(kWave) void routes_wide_kernel(
     const int16_t *__restrict__ demands, int32_t N, int64_t S, int32_t Q,
     int32_t *__restrict__ costs, uint16_t *pred, uint16_t *cuts, int32_t *__restrict__ nroutes,
-    Workspace ws, int32_t lds_bytes, int32_t key_bits)
+    Workspace ws, int32_t lds_bytes, int32_t pitch, const int2 *tabp, int32_t key_bits)
 {
     routes_tile<false, R, F, 0, E>(demands, N, S, Q, costs, pred, cuts, nroutes, ws, lds_bytes,
-                                   key_bits);
+                                   pitch, tabp, key_bits);
 }
 
 // grid = kFallbackBlocks waves; exact recursion for listed tiles with
@@ -528,13 +534,10 @@ hipError_t allow_lds(const void *kernel, int *limit)
 template <int R, int F, int G, int E>
 hipError_t launch_route_tiles(int32_t n, const int16_t *demands, int32_t N, int64_t S,
                               int32_t Q, int32_t *costs, uint16_t *pred, uint16_t *cuts,
-                              int32_t *nroutes, const Workspace &ws, hipStream_t stream)
+                              int32_t *nroutes, const Workspace &ws, int2 *tabp,
+                              hipStream_t stream)
 {
     constexpr int WF = WideOf<R>::F, WE = WideOf<R>::E;
-    // demand tile + flag word, and at least room for the backtracking bitmask
-    const size_t tile = (((size_t)kTile * (size_t)N + 15) & ~(size_t)15) + 16;
-    const size_t bits = (size_t)((n + 31) / 32) * 4 * kTile;
-    const size_t lds = tile > bits ? tile : bits;
     static int lim_key = -1, lim_wide = -1;
     hipError_t e = hipSuccess;
     if (lim_key < 0)
@@ -543,16 +546,31 @@ hipError_t launch_route_tiles(int32_t n, const int16_t *demands, int32_t N, int6
         e = allow_lds(reinterpret_cast<const void *>(&routes_wide_kernel<R, WF, WE>), &lim_wide);
     if (e != hipSuccess)
         return e;
-    const int32_t lds_bytes = lds <= (size_t)lim_key && lds <= (size_t)lim_wide ? (int32_t)lds : 0;
+    const int lim = lim_key < lim_wide ? lim_key : lim_wide;
+    // demand tile (whole rows, or the tour gathered) + flag word, and at
+    // least room for the backtracking bitmask
+    const int32_t pitch = gather_tile(n, N, lim) ? n + 1 : 0;
+    const size_t stride = pitch ? (size_t)pitch : (size_t)N;
+    const size_t tile = (((size_t)kTile * stride + 15) & ~(size_t)15) + 16;
+    const size_t bits = (size_t)((n + 31) / 32) * 4 * kTile;
+    const size_t lds = tile > bits ? tile : bits;
+    const int32_t lds_bytes = lds <= (size_t)lim ? (int32_t)lds : 0;
+    if (pitch && lds_bytes) {
+        hipLaunchKernelGGL(position_table_kernel, dim3(1), dim3(256), 0, stream, ws.tab, n, tabp);
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
     const dim3 grid((unsigned)num_tiles(S));
     hipLaunchKernelGGL((routes_key_kernel<R, F, G, E>), grid, dim3(kWave), (size_t)lds_bytes,
-                       stream, demands, N, S, Q, costs, pred, cuts, nroutes, ws, lds_bytes);
+                       stream, demands, N, S, Q, costs, pred, cuts, nroutes, ws, lds_bytes, pitch,
+                       tabp);
     e = hipGetLastError();
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL((routes_wide_kernel<R, WF, WE>), grid, dim3(kWave), (size_t)lds_bytes,
-                       stream, demands, N, S, Q, costs, pred, cuts, nroutes, ws, lds_bytes,
-                       (int32_t)key_shift<R>());
+                       stream, demands, N, S, Q, costs, pred, cuts, nroutes, ws, lds_bytes, pitch,
+                       tabp, (int32_t)key_shift<R>());
     return hipGetLastError();
 }
 
@@ -585,15 +603,27 @@ RouteVariant choose_route_variant(int32_t Q)
     return g_route_override.ring ? g_route_override : default_route_variant(Q);
 }
 
+static size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
+
 size_t routes_workspace_bytes(int32_t n, int32_t N, int64_t S)
 {
-    return workspace_bytes(1, n, N, S, false);
+    // the evaluator's one-tour workspace, then the position table of a
+    // gathered tile
+    return round256(workspace_bytes(1, n, N, S, false)) +
+           round256(((size_t)n + kTabPad) * sizeof(int2));
+}
+
+int2 *routes_position_table(void *workspace, int32_t n, int32_t N, int64_t S)
+{
+    return reinterpret_cast<int2 *>(static_cast<char *>(workspace) +
+                                    round256(workspace_bytes(1, n, N, S, false)));
 }
 
 hipError_t launch_routes(const int32_t *tour, int32_t n, const int32_t *dist, int32_t N,
                          const int16_t *demands, int64_t S, int32_t Q, int32_t *costs,
                          uint16_t *pred, uint16_t *cuts, int32_t *nroutes, const Workspace &ws,
-                         hipStream_t stream, const RouteVariant &v, const LaunchEvents *ev)
+                         int2 *tabp, hipStream_t stream, const RouteVariant &v,
+                         const LaunchEvents *ev)
 {
     if (!route_variant_supported(v))
         return hipErrorInvalidValue;
@@ -608,7 +638,7 @@ hipError_t launch_routes(const int32_t *tour, int32_t n, const int32_t *dist, in
 #define SPLIT_RV_LAUNCH(R_, F_, G_, E_)                                                          \
     if (v.ring == R_ && v.first == F_ && v.group == G_ && v.every == E_)                         \
         e = launch_route_tiles<R_, F_, G_, E_>(n, demands, N, S, Q, costs, pred, cuts, nroutes,  \
-                                               ws, stream);
+                                               ws, tabp, stream);
     SPLIT_ROUTE_KEY_VARIANTS(SPLIT_RV_LAUNCH)
 #undef SPLIT_RV_LAUNCH
     if (e != hipSuccess)

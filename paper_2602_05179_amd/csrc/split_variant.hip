@@ -69,7 +69,24 @@ struct VarArgs {
     int32_t *costs;
     int *lay0, *lay1; // [n][S] potentials of consecutive passes (K > 0)
     int *vs;          // fallback scratch [blocks][2][n+1][64]
+    int32_t pitch;    // 0: whole scenario rows in LDS; else the tour gathered, row stride pitch
+    const int2 *tabp; // per-tour table indexed by position (gathered tile)
 };
+
+// Stages the tile (whole rows or the tour gathered) and returns the table
+// and row stride the recursion reads it with.
+__device__ __forceinline__ bool stage_variant_tile(const VarArgs &a, const Workspace &ws, int n,
+                                                   int64_t s0, int rows, uint8_t *lds, int lane,
+                                                   CInt *&tab, int &stride)
+{
+    stride = a.pitch ? a.pitch : a.N;
+    tab = (CInt *)(a.pitch ? a.tabp : ws.tab);
+    int &s_bad = *reinterpret_cast<int *>(lds + (((size_t)kWave * stride + 15) & ~(size_t)15));
+    return a.pitch ? stage_tile_gather_u8(a.demands + s0 * a.N, a.N, rows, ws.tab, n, a.pitch, lds,
+                                          lane, kWave, s_bad)
+                   : stage_tile_u8(a.demands + s0 * a.N, lds, (int64_t)rows * a.N, lane, kWave,
+                                   s_bad);
+}
 
 struct VarRegs {
     int L;           // load of positions 1..j
@@ -418,17 +435,16 @@ __global__ __launch_bounds__(kWave) void variant_multi_kernel(VarArgs a, Workspa
         return;
     }
     bool ok = false;
-    if (lds_bytes) {
-        int &s_bad = *reinterpret_cast<int *>(lds + (((size_t)kWave * a.N + 15) & ~(size_t)15));
-        ok = stage_tile_u8(a.demands + s0 * a.N, lds, (int64_t)rows * a.N, lane, kWave, s_bad);
-    }
+    CInt *tab = nullptr;
+    int stride = a.N;
+    if (lds_bytes)
+        ok = stage_variant_tile(a, ws, rec.n, s0, rows, lds, lane, tab, stride);
     bool redo = true;
     if (ok) {
-        CInt *tab = (CInt *)ws.tab;
         bool ovf = false, range_bad = false;
         int best = kInf;
         if (lane < rows) {
-            const uint8_t *row = lds + (int64_t)lane * a.N;
+            const uint8_t *row = lds + (int64_t)lane * stride;
             const int64_t s = s0 + lane;
             const int passes = a.K < rec.n ? a.K : rec.n;
             const int *src = nullptr;
@@ -491,17 +507,16 @@ __global__ __launch_bounds__(kWave) void variant_tile_kernel(VarArgs a, Workspac
         return;
     }
     bool ok = false;
-    if (lds_bytes) {
-        int &s_bad = *reinterpret_cast<int *>(lds + (((size_t)kWave * a.N + 15) & ~(size_t)15));
-        ok = stage_tile_u8(a.demands + s0 * a.N, lds, (int64_t)rows * a.N, lane, kWave, s_bad);
-    }
+    CInt *tab = nullptr;
+    int stride = a.N;
+    if (lds_bytes)
+        ok = stage_variant_tile(a, ws, rec.n, s0, rows, lds, lane, tab, stride);
     bool redo = true;
     if (ok) {
-        CInt *tab = (CInt *)ws.tab;
         bool ovf = false, range_bad = false;
         int best = kInf;
         if (lane < rows) {
-            const uint8_t *row = lds + (int64_t)lane * a.N;
+            const uint8_t *row = lds + (int64_t)lane * stride;
             const int64_t s = s0 + lane;
             int Ltot = 0;
             if constexpr (!LAYERED) {
@@ -641,6 +656,15 @@ hipError_t allow_lds_once(const void *kernel, int *limit)
     return e;
 }
 
+// LDS of a tile (its row stride set by a.pitch) with the flag word; 0 when
+// it does not fit (every tile then takes the exact fallback)
+int32_t variant_lds_bytes(const VarArgs &a, int lim)
+{
+    const size_t stride = a.pitch ? (size_t)a.pitch : (size_t)a.N;
+    const size_t lds = (((size_t)kTile * stride + 15) & ~(size_t)15) + 16;
+    return lds <= (size_t)lim ? (int32_t)lds : 0;
+}
+
 template <int R, bool SOFT, bool LAYERED>
 hipError_t launch_variant_tiles(const VarArgs &a, const Workspace &ws, hipStream_t stream)
 {
@@ -649,8 +673,7 @@ hipError_t launch_variant_tiles(const VarArgs &a, const Workspace &ws, hipStream
         reinterpret_cast<const void *>(&variant_tile_kernel<R, SOFT, LAYERED>), &lim);
     if (e != hipSuccess)
         return e;
-    const size_t lds = (((size_t)kTile * (size_t)a.N + 15) & ~(size_t)15) + 16;
-    const int32_t lds_bytes = lds <= (size_t)lim ? (int32_t)lds : 0;
+    const int32_t lds_bytes = variant_lds_bytes(a, lim);
     hipLaunchKernelGGL((variant_tile_kernel<R, SOFT, LAYERED>), dim3((unsigned)num_tiles(a.S)),
                        dim3(kWave), (size_t)lds_bytes, stream, a, ws, lds_bytes);
     return hipGetLastError();
@@ -664,8 +687,7 @@ hipError_t launch_variant_multi(const VarArgs &a, const Workspace &ws, hipStream
         reinterpret_cast<const void *>(&variant_multi_kernel<R, NL, SOFT>), &lim);
     if (e != hipSuccess)
         return e;
-    const size_t lds = (((size_t)kTile * (size_t)a.N + 15) & ~(size_t)15) + 16;
-    const int32_t lds_bytes = lds <= (size_t)lim ? (int32_t)lds : 0;
+    const int32_t lds_bytes = variant_lds_bytes(a, lim);
     hipLaunchKernelGGL((variant_multi_kernel<R, NL, SOFT>), dim3((unsigned)num_tiles(a.S)),
                        dim3(kWave), (size_t)lds_bytes, stream, a, ws, lds_bytes);
     return hipGetLastError();
@@ -710,6 +732,7 @@ size_t variant_workspace_bytes(int32_t n, int32_t N, int64_t S, int32_t K)
     if (K > 0)
         b += 2 * align256((size_t)n * (size_t)S * sizeof(int));
     b += align256((size_t)kFallbackBlocks * 2 * ((size_t)n + 1) * kWave * sizeof(int));
+    b += align256(((size_t)n + kTabPad) * sizeof(int2));
     return b;
 }
 
@@ -738,9 +761,28 @@ hipError_t launch_variant(const int32_t *tour, int32_t n, const int32_t *dist, i
         p += align256((size_t)n * (size_t)S * sizeof(int));
     }
     a.vs = reinterpret_cast<int *>(p);
+    p += align256((size_t)kFallbackBlocks * 2 * ((size_t)n + 1) * kWave * sizeof(int));
+    int2 *tabp = reinterpret_cast<int2 *>(p);
     hipError_t e = launch_prep(tour, nullptr, 1, n, dist, N, ws, stream);
     if (e != hipSuccess)
         return e;
+    // a gathered tile when whole rows do not fit or the tour covers at most
+    // half of the pool (the LDS limit of the device, as the kernels see it)
+    int dev = 0, lim = 0;
+    e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess)
+        return e;
+    lim = lim < kLdsLimit ? lim : kLdsLimit;
+    a.pitch = gather_tile(n, N, lim) ? n + 1 : 0;
+    a.tabp = tabp;
+    if (a.pitch) {
+        hipLaunchKernelGGL(position_table_kernel, dim3(1), dim3(256), 0, stream, ws.tab, n, tabp);
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
     e = variant_ring(Q) == 64 ? launch_variant_ring<64>(a, ws, stream)
                               : launch_variant_ring<32>(a, ws, stream);
     if (e != hipSuccess)
