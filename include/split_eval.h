@@ -152,7 +152,11 @@ int split_eval_device(const int32_t *d_tours, const int32_t *d_lens, int32_t num
  * ordered on one stream.  Tiles whose 64 x N demand bytes do not fit in
  * LDS, whose demands exceed 255, or whose windows exceed the register
  * ring are recomputed by an exact (slower) kernel; results never depend
- * on the path taken.
+ * on the path taken.  Long tours on large pools (more than 16 KB of demand
+ * bytes per 64-scenario tile) take a path that first writes the tour's
+ * demands in tour order into the workspace, one byte per position, and
+ * streams them from there (the workspace then includes S x (n rounded up
+ * to 32, plus 32) bytes for that copy).
  */
 #define SPLIT_NO_PRED 0xFFFF
 
@@ -178,6 +182,17 @@ int split_routes_device(const int32_t *d_tour, int32_t n, const int32_t *d_dist,
  */
 int split_routes_set_variant(int32_t ring, int32_t first, int32_t group, int32_t every);
 int split_routes_list_variants(int32_t *out, int32_t cap);
+
+/*
+ * split_routes_set_path -- how later route-recovery calls in the process
+ * read the demands: 0 automatic (by the demand bytes per tile), 1 the tile
+ * staged in LDS, 2 the tour-ordered copy in the workspace (taken only where
+ * its permute tile, 64 x N demand bytes, fits in LDS; else path 1).
+ * split_routes_workspace_bytes reflects the setting: query it after
+ * setting the path.  SPLIT_EINVAL outside [0, 2].  Results never depend on
+ * the path.  Not thread-safe against concurrent calls.
+ */
+int split_routes_set_path(int32_t path);
 
 /*
  * Split variants (App. A, the extensive form: its objective charges every

@@ -52,6 +52,7 @@ EXPORTED = (
     "split_routes_device",
     "split_routes_set_variant",
     "split_routes_list_variants",
+    "split_routes_set_path",
     "split_variant_workspace_bytes",
     "split_variant_device",
     "split_minplus_forward_device",
@@ -144,6 +145,8 @@ def _load():
     lib.split_routes_set_variant.restype = ctypes.c_int
     lib.split_routes_set_variant.argtypes = [i32, i32, i32, i32]
     lib.split_routes_list_variants.restype = ctypes.c_int
+    lib.split_routes_set_path.restype = ctypes.c_int
+    lib.split_routes_set_path.argtypes = [i32]
     lib.split_variant_workspace_bytes.restype = sz
     lib.split_variant_workspace_bytes.argtypes = [i32, i32, i64, i32]
     lib.split_variant_device.restype = ctypes.c_int
@@ -329,6 +332,15 @@ ROUTE_VARIANTS = list_route_variants()
 def set_route_variant(ring: int, first: int = 8, group: int = 3, every: int = 3):
     """Force the route-recovery window variant; ring=0 restores the automatic choice."""
     _check(lib.split_routes_set_variant(int(ring), int(first), int(group), int(every)))
+
+
+ROUTE_PATH_AUTO, ROUTE_PATH_LDS, ROUTE_PATH_ORDERED = 0, 1, 2
+
+
+def set_route_path(path: int):
+    """How route recovery reads the demands: 0 automatic, 1 the tile staged
+    in LDS, 2 the tour-ordered copy in the workspace."""
+    _check(lib.split_routes_set_path(int(path)))
 
 
 def routes_workspace_bytes(n: int, N: int, S: int) -> int:

@@ -322,6 +322,15 @@ int split_routes_set_variant(int32_t ring, int32_t first, int32_t group, int32_t
     return SPLIT_OK;
 }
 
+int split_routes_set_path(int32_t path)
+{
+    g_err[0] = 0;
+    if (path < 0 || path > 2)
+        return fail(SPLIT_EINVAL, "route path must be 0, 1 or 2 (got %d)", path);
+    splitk::set_route_path(path);
+    return SPLIT_OK;
+}
+
 int split_routes_list_variants(int32_t *out, int32_t cap)
 {
     g_err[0] = 0;
@@ -357,7 +366,8 @@ int split_routes_device(const int32_t *d_tour, int32_t n, const int32_t *d_dist,
     const size_t need = splitk::routes_workspace_bytes(n, N, S);
     if (ws_bytes < need)
         return fail(SPLIT_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
-    const splitk::Workspace ws = splitk::carve_workspace(d_workspace, 1, n, N, S, false);
+    const splitk::Workspace ws =
+        splitk::carve_workspace(d_workspace, 1, n, N, S, splitk::routes_ordered(n, N));
     splitk::LaunchEvents ev;
     bool use_ev = false;
     HIP_TRY(profile_events(&ev, &use_ev), "profile events");

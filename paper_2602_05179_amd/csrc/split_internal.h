@@ -63,6 +63,11 @@ Workspace carve_workspace(void *base, int32_t T, int32_t max_len, int32_t N, int
 int waves_per_group(int32_t T, int32_t N);
 bool ordered_path_possible(int32_t N, int32_t max_len);
 bool use_ordered_path(int32_t T, int32_t N, int32_t max_len);
+int32_t ordered_pitch(int32_t max_len); // row stride of the tour-ordered copy
+
+// Writes the tour-ordered copy of every tile (ws.perm, ws.tile_bad).
+hipError_t launch_permute(const int16_t *demands, int32_t N, int64_t S, int32_t T,
+                          int32_t max_len, const Workspace &ws, hipStream_t stream);
 
 // Per-tour tables, validation and accumulator reset for T tours (lens ==
 // nullptr: one tour of length max_len).
@@ -107,6 +112,10 @@ bool route_variant_supported(const RouteVariant &v);
 int compiled_route_variants(RouteVariant *out, int cap);
 RouteVariant choose_route_variant(int32_t Q); // override, else the default for Q
 void set_route_override(const RouteVariant &v); // ring 0 = automatic
+// whether a call streams the tour-ordered copy (path override, else by
+// the demand bytes per wave of the LDS tile); the workspace holds the copy then
+bool routes_ordered(int32_t n, int32_t N);
+void set_route_path(int path); // 0 automatic, 1 LDS tile, 2 tour-ordered copy
 size_t routes_workspace_bytes(int32_t n, int32_t N, int64_t S);
 // where a route-recovery workspace keeps the position table of a gathered tile
 int2 *routes_position_table(void *workspace, int32_t n, int32_t N, int64_t S);

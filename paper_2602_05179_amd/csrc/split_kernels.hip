@@ -933,6 +933,24 @@ bool schedule_supported(const Schedule &s)
     return false;
 }
 
+hipError_t launch_permute(const int16_t *demands, int32_t N, int64_t S, int32_t T,
+                          int32_t max_len, const Workspace &ws, hipStream_t stream)
+{
+    static bool perm_attr = false;
+    if (!perm_attr) {
+        const hipError_t e =
+            hipFuncSetAttribute(reinterpret_cast<const void *>(&permute_tile_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kLdsLimit);
+        if (e != hipSuccess)
+            return e;
+        perm_attr = true;
+    }
+    hipLaunchKernelGGL(permute_tile_kernel, dim3((unsigned)num_tiles(S)), dim3(kPermThreads),
+                       permute_lds_bytes(N, max_len), stream, demands, N, S, T,
+                       ordered_pitch(max_len), ws);
+    return hipGetLastError();
+}
+
 template <int R, int F, int G, int E>
 static hipError_t launch_tiles(const int16_t *demands, int32_t N, int64_t S, int32_t Q, int32_t T,
                                int32_t *costs, const Workspace &ws, hipStream_t stream, int W)
@@ -981,21 +999,10 @@ hipError_t launch_eval(const int32_t *tours, const int32_t *lens, int32_t T, int
             return e;
     }
     if (ws.perm) {
-        const size_t plds = permute_lds_bytes(N, max_len);
-        static bool perm_attr = false;
-        if (!perm_attr) {
-            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&permute_tile_kernel),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, kLdsLimit);
-            if (e != hipSuccess)
-                return e;
-            perm_attr = true;
-        }
-        const int32_t pitch = ordered_pitch(max_len);
-        hipLaunchKernelGGL(permute_tile_kernel, dim3((unsigned)num_tiles(S)), dim3(kPermThreads),
-                           plds, stream, demands, N, S, T, pitch, ws);
-        e = hipGetLastError();
+        e = launch_permute(demands, N, S, T, max_len, ws, stream);
         if (e != hipSuccess)
             return e;
+        const int32_t pitch = ordered_pitch(max_len);
         const int64_t units = (int64_t)T * num_tiles(S);
 #define SPLIT_LAUNCH_O(R_, F_, G_, E_)                                                           \
     if (sched.ring == R_ && sched.first == F_ && sched.group == G_ && sched.every == E_)          \

@@ -69,6 +69,65 @@ __device__ __forceinline__ bool keys_fit(const TourRec &rec, int B)
     return (long long)3 * rec.n * rec.maxc < (1LL << (29 - B));
 }
 
+// Demand bytes of one lane's scenario, read in tour order by the recursion:
+// position j's demand at position j - 2 (two ahead), after `init` has read
+// positions 1 and 2.  ahead<U>(t) is called at position j = j0 + U of a
+// block (j0 a multiple of 32), with t the table entry of position j + 2.
+
+// a row in LDS, indexed through the table (the customer index for whole
+// rows, position - 1 for a gathered tile)
+struct LdsRow {
+    const uint8_t *row;
+    __device__ __forceinline__ void init(int2 t0, int2 t1, int &q1, int &q2) const
+    {
+        q1 = row[t0.x];
+        q2 = row[t1.x];
+    }
+    template <int U> __device__ __forceinline__ int ahead(int2 t) const { return row[t.x]; }
+};
+
+// the lane's row of the tour-ordered copy in global memory (byte j - 1 =
+// position j, zero-padded to a multiple of 32 bytes plus 32), held 32 bytes
+// at a time in registers with the next 32 in flight
+struct StreamRow {
+    const u32x4 *row;
+    int segs; // 32-byte segments in the row (at least 2)
+    int nseg; // segment held in nxt
+    u32x4 cur[2], nxt[2];
+
+    template <int B> __device__ __forceinline__ static int byte_of(const u32x4 (&seg)[2])
+    {
+        const u32x4 &v = seg[B >> 4];
+        constexpr int w = (B >> 2) & 3;
+        const uint32_t x = w == 0 ? v.x : w == 1 ? v.y : w == 2 ? v.z : v.w;
+        return (int)((x >> (8 * (B & 3))) & 0xFFu);
+    }
+    __device__ __forceinline__ void init(int2, int2, int &q1, int &q2)
+    {
+        cur[0] = __builtin_nontemporal_load(row);
+        cur[1] = __builtin_nontemporal_load(row + 1);
+        nxt[0] = __builtin_nontemporal_load(row + 2);
+        nxt[1] = __builtin_nontemporal_load(row + 3);
+        nseg = 1;
+        q1 = byte_of<0>(cur);
+        q2 = byte_of<1>(cur);
+    }
+    template <int U> __device__ __forceinline__ int ahead(int2)
+    {
+        constexpr int B = (U + 1) & 31; // byte j + 1 of the row
+        const int v = byte_of<B>(cur);
+        if (B == 31) { // next 32 positions: rotate and fetch the segment after
+            cur[0] = nxt[0];
+            cur[1] = nxt[1];
+            if (++nseg < segs) {
+                nxt[0] = __builtin_nontemporal_load(row + 2 * nseg);
+                nxt[1] = __builtin_nontemporal_load(row + 2 * nseg + 1);
+            }
+        }
+        return v;
+    }
+};
+
 // Backtracking of one scenario from position n.  pcol / ccol point at the
 // scenario's column of pred / cuts (stride S).  Returns the number of
 // routes, or -1 if the chain does not descend (never for a finite V(n)).
@@ -104,9 +163,10 @@ struct RtRegs {
 };
 
 template <int R, int F, int E, int U> struct RtState {
-    __device__ __forceinline__ static bool run(int (&f)[R], int (&lq)[R], RtRegs &r,
-                                               const uint8_t *row, CInt *tab, int j0, int n,
-                                               int Q, int64_t S, int lane)
+    template <class Src>
+    __device__ __forceinline__ static bool run(int (&f)[R], int (&lq)[R], RtRegs &r, Src &src,
+                                               CInt *tab, int j0, int n, int Q, int64_t S,
+                                               int lane)
     {
         const int j = j0 + U;
         if (U == 0 && j == 0)
@@ -115,7 +175,7 @@ template <int R, int F, int E, int U> struct RtState {
             return false;
         const int cj = r.t0.y;
         const int Ln = r.L + r.qa;
-        r.qa = row[r.t2.x];
+        r.qa = src.template ahead<U>(r.t2);
         const int2 t3 = tab_at(tab, j + 3);
         uint64_t cn1;
         int a;
@@ -135,18 +195,18 @@ template <int R, int F, int E, int U> struct RtState {
     }
 };
 
-template <int R, int F, int E, int... Us>
-__device__ __forceinline__ bool rt_block(int (&f)[R], int (&lq)[R], RtRegs &r, const uint8_t *row,
+template <int R, int F, int E, class Src, int... Us>
+__device__ __forceinline__ bool rt_block(int (&f)[R], int (&lq)[R], RtRegs &r, Src &src,
                                          CInt *tab, int j0, int n, int Q, int64_t S, int lane,
                                          std::integer_sequence<int, Us...>)
 {
-    return (RtState<R, F, E, Us>::run(f, lq, r, row, tab, j0, n, Q, S, lane) && ...);
+    return (RtState<R, F, E, Us>::run(f, lq, r, src, tab, j0, n, Q, S, lane) && ...);
 }
 
 // Writes pred(1..n) of the lane's scenario; returns m_n, sets ovf when a
 // window left the ring.  prow0 = pred + s0 (the tile's first column).
-template <int R, int F, int E>
-__device__ __forceinline__ int rt_lane(const uint8_t *row, CInt *tab, int n, int f0, int Q,
+template <int R, int F, int E, class Src>
+__device__ __forceinline__ int rt_lane(Src &src, CInt *tab, int n, int f0, int Q,
                                        uint16_t *prow0, int64_t S, int lane, bool &ovf)
 {
     int f[R], lq[R];
@@ -164,11 +224,10 @@ __device__ __forceinline__ int rt_lane(const uint8_t *row, CInt *tab, int n, int
     r.t0 = tab_at(tab, 1);
     r.t1 = tab_at(tab, 2);
     r.t2 = tab_at(tab, 3);
-    r.L = row[r.t0.x];
-    r.qa = row[r.t1.x];
+    src.init(r.t0, r.t1, r.L, r.qa);
     r.prow = prow0;
     for (int j0 = 0; j0 <= n; j0 += R) {
-        if (!rt_block<R, F, E>(f, lq, r, row, tab, j0, n, Q, S, lane,
+        if (!rt_block<R, F, E>(f, lq, r, src, tab, j0, n, Q, S, lane,
                                std::make_integer_sequence<int, R>{}))
             break;
     }
@@ -192,9 +251,10 @@ struct RkRegs {
 };
 
 template <int R, int F, int G, int E, int U> struct RkState {
-    __device__ __forceinline__ static bool run(int (&K)[R], int (&lq)[R], RkRegs &r,
-                                               const uint8_t *row, CInt *tab, int j0, int n,
-                                               int Q, int64_t S, int lane)
+    template <class Src>
+    __device__ __forceinline__ static bool run(int (&K)[R], int (&lq)[R], RkRegs &r, Src &src,
+                                               CInt *tab, int j0, int n, int Q, int64_t S,
+                                               int lane)
     {
         constexpr int B = key_shift<R>();
         constexpr int M = (1 << B) - 1;
@@ -211,7 +271,7 @@ template <int R, int F, int G, int E, int U> struct RkState {
         }
         const int cj = r.t0.y;
         const int Ln = r.L + r.qa;
-        r.qa = row[r.t2.x];
+        r.qa = src.template ahead<U>(r.t2);
         const int2 t3 = tab_at(tab, j + 3);
         uint64_t cn1, cn2;
         const int km = WindowMin<R, F, G, E>::template run<U>(K, lq, r.L, Ln, j, r.cp1, r.cp2,
@@ -232,18 +292,18 @@ template <int R, int F, int G, int E, int U> struct RkState {
     }
 };
 
-template <int R, int F, int G, int E, int... Us>
-__device__ __forceinline__ bool rk_block(int (&K)[R], int (&lq)[R], RkRegs &r, const uint8_t *row,
+template <int R, int F, int G, int E, class Src, int... Us>
+__device__ __forceinline__ bool rk_block(int (&K)[R], int (&lq)[R], RkRegs &r, Src &src,
                                          CInt *tab, int j0, int n, int Q, int64_t S, int lane,
                                          std::integer_sequence<int, Us...>)
 {
-    return (RkState<R, F, G, E, Us>::run(K, lq, r, row, tab, j0, n, Q, S, lane) && ...);
+    return (RkState<R, F, G, E, Us>::run(K, lq, r, src, tab, j0, n, Q, S, lane) && ...);
 }
 
 // Writes pred(1..n) of the lane's scenario; returns V(n) (kInf if +inf),
 // sets ovf when a window left the ring.
-template <int R, int F, int G, int E>
-__device__ __forceinline__ int rk_lane(const uint8_t *row, CInt *tab, const TourRec &rec, int Q,
+template <int R, int F, int G, int E, class Src>
+__device__ __forceinline__ int rk_lane(Src &src, CInt *tab, const TourRec &rec, int Q,
                                        uint16_t *prow0, int64_t S, int lane, bool &ovf)
 {
     constexpr int B = key_shift<R>();
@@ -264,12 +324,11 @@ __device__ __forceinline__ int rk_lane(const uint8_t *row, CInt *tab, const Tour
     r.t0 = tab_at(tab, 1);
     r.t1 = tab_at(tab, 2);
     r.t2 = tab_at(tab, 3);
-    r.L = row[r.t0.x];
-    r.qa = row[r.t1.x];
+    src.init(r.t0, r.t1, r.L, r.qa);
     r.prow = prow0;
     const int n = rec.n;
     for (int j0 = 0; j0 <= n; j0 += R) {
-        if (!rk_block<R, F, G, E>(K, lq, r, row, tab, j0, n, Q, S, lane,
+        if (!rk_block<R, F, G, E>(K, lq, r, src, tab, j0, n, Q, S, lane,
                                   std::make_integer_sequence<int, R>{}))
             break;
     }
@@ -316,12 +375,27 @@ __device__ __forceinline__ int backtrack_tile(const uint16_t *pcol, uint16_t *cc
     return r;
 }
 
-// Tile body shared by the key and the wide kernel: stage the tile, run the
-// lane recursion, backtrack, or list the tile for the exact fallback.
+// V(n) of the lane's scenario (kInf if +inf) with pred(1..n) written, by
+// packed keys (KEYS) or the per-cell argmin
+template <bool KEYS, int R, int F, int G, int E, class Src>
+__device__ __forceinline__ int route_lane(Src &src, CInt *tab, const TourRec &rec, int Q,
+                                          uint16_t *prow0, int64_t S, int lane, bool &ovf)
+{
+    if constexpr (KEYS) {
+        return rk_lane<R, F, G, E>(src, tab, rec, Q, prow0, S, lane, ovf);
+    } else {
+        const int m = rt_lane<R, F, E>(src, tab, rec.n, rec.f0, Q, prow0, S, lane, ovf);
+        return m < kFeasible ? m + rec.bn : kInf;
+    }
+}
+
+// Tile body shared by the key and the wide kernel: stage the tile (or, ORD,
+// read the tour-ordered copy the permute kernel wrote), run the lane
+// recursion, backtrack, or list the tile for the exact fallback.
 // KEYS: packed keys with ring R and window variant (F, G, E); otherwise the
 // per-cell argmin with ring R and (F, E), serving the tours whose costs are
 // too wide for keys of key_bits.
-template <bool KEYS, int R, int F, int G, int E>
+template <bool KEYS, bool ORD, int R, int F, int G, int E>
 __device__ __forceinline__ void routes_tile(const int16_t *__restrict__ demands, int32_t N,
                                             int64_t S, int32_t Q, int32_t *__restrict__ costs,
                                             uint16_t *pred, uint16_t *cuts,
@@ -346,28 +420,40 @@ __device__ __forceinline__ void routes_tile(const int16_t *__restrict__ demands,
         }
         return;
     }
-    // whole scenario rows (pitch 0: row stride N, indexed by customer) or the
-    // tour's demands gathered in tour order (row stride pitch, by position)
-    const int stride = pitch ? pitch : N;
     bool ok = false;
-    if (lds_bytes) {
-        int &s_bad = *reinterpret_cast<int *>(lds + (((size_t)kWave * stride + 15) & ~(size_t)15));
-        ok = pitch ? stage_tile_gather_u8(demands + s0 * N, N, rows, ws.tab, rec.n, pitch, lds, lane,
-                                          kWave, s_bad)
-                   : stage_tile_u8(demands + s0 * N, lds, (int64_t)rows * N, lane, kWave, s_bad);
+    CInt *tab;
+    if constexpr (ORD) {
+        // the permute kernel flagged tiles with a demand outside [0, 255]
+        ok = ws.tile_bad[k] == 0;
+        tab = (CInt *)ws.tab;
+    } else {
+        // whole scenario rows (pitch 0: row stride N, indexed by customer) or
+        // the tour's demands gathered in tour order (row stride pitch, by
+        // position)
+        const int stride = pitch ? pitch : N;
+        if (lds_bytes) {
+            int &s_bad =
+                *reinterpret_cast<int *>(lds + (((size_t)kWave * stride + 15) & ~(size_t)15));
+            ok = pitch ? stage_tile_gather_u8(demands + s0 * N, N, rows, ws.tab, rec.n, pitch, lds,
+                                              lane, kWave, s_bad)
+                       : stage_tile_u8(demands + s0 * N, lds, (int64_t)rows * N, lane, kWave,
+                                       s_bad);
+        }
+        tab = (CInt *)(pitch ? tabp : ws.tab);
     }
     bool redo = true;
     if (ok) {
-        CInt *tab = (CInt *)(pitch ? tabp : ws.tab);
         bool ovf = false;
         int v = kInf;
         if (lane < rows) {
-            const uint8_t *row = lds + (int64_t)lane * stride;
-            if constexpr (KEYS) {
-                v = rk_lane<R, F, G, E>(row, tab, rec, Q, pred + s0, S, lane, ovf);
+            if constexpr (ORD) {
+                StreamRow src;
+                src.row = reinterpret_cast<const u32x4 *>(ws.perm + (s0 + lane) * (int64_t)pitch);
+                src.segs = pitch / 32;
+                v = route_lane<KEYS, R, F, G, E>(src, tab, rec, Q, pred + s0, S, lane, ovf);
             } else {
-                const int m = rt_lane<R, F, E>(row, tab, rec.n, rec.f0, Q, pred + s0, S, lane, ovf);
-                v = m < kFeasible ? m + rec.bn : kInf;
+                LdsRow src{lds + (int64_t)lane * (pitch ? pitch : N)};
+                v = route_lane<KEYS, R, F, G, E>(src, tab, rec, Q, pred + s0, S, lane, ovf);
             }
         }
         redo = ballot(ovf) != 0;
@@ -392,27 +478,28 @@ __device__ __forceinline__ void routes_tile(const int16_t *__restrict__ demands,
     }
 }
 
-// grid = tiles, one wave each; LDS: 64 x N demand bytes + flag word.
-// Serves tours whose potentials fit packed keys of this ring.
-template <int R, int F, int G, int E>
+// grid = tiles, one wave each; LDS: the demand tile + flag word (or, ORD,
+// only the backtracking bitmask; pitch is then the ordered copy's row
+// stride).  Serves tours whose potentials fit packed keys of this ring.
+template <int R, int F, int G, int E, bool ORD>
 __global__ __launch_bounds__(kWave) void routes_key_kernel(
     const int16_t *__restrict__ demands, int32_t N, int64_t S, int32_t Q,
     int32_t *__restrict__ costs, uint16_t *pred, uint16_t *cuts, int32_t *__restrict__ nroutes,
     Workspace ws, int32_t lds_bytes, int32_t pitch, const int2 *tabp)
 {
-    routes_tile<true, R, F, G, E>(demands, N, S, Q, costs, pred, cuts, nroutes, ws, lds_bytes,
-                                  pitch, tabp, key_shift<R>());
+    routes_tile<true, ORD, R, F, G, E>(demands, N, S, Q, costs, pred, cuts, nroutes, ws,
+                                       lds_bytes, pitch, tabp, key_shift<R>());
 }
 
 // Same grid and LDS; serves the tours that keys of key_bits cannot hold.
-template <int R, int F, int E>
+template <int R, int F, int E, bool ORD>
 __global__ __launch_bounds__(kWave) void routes_wide_kernel(
     const int16_t *__restrict__ demands, int32_t N, int64_t S, int32_t Q,
     int32_t *__restrict__ costs, uint16_t *pred, uint16_t *cuts, int32_t *__restrict__ nroutes,
     Workspace ws, int32_t lds_bytes, int32_t pitch, const int2 *tabp, int32_t key_bits)
 {
-    routes_tile<false, R, F, 0, E>(demands, N, S, Q, costs, pred, cuts, nroutes, ws, lds_bytes,
-                                   pitch, tabp, key_bits);
+    routes_tile<false, ORD, R, F, 0, E>(demands, N, S, Q, costs, pred, cuts, nroutes, ws,
+                                        lds_bytes, pitch, tabp, key_bits);
 }
 
 // grid = kFallbackBlocks waves; exact recursion for listed tiles with
@@ -529,30 +616,72 @@ hipError_t allow_lds(const void *kernel, int *limit)
     return e;
 }
 
-// Launches the key kernel and the wide kernel of ring R; the one that does
-// not serve the tour returns at once.
+template <int R, int F, int G, int E, bool ORD> struct RouteKernels {
+    static constexpr int WF = WideOf<R>::F, WE = WideOf<R>::E;
+    // the LDS limit both kernels were allowed (-1 before the first call)
+    static hipError_t limit(int *lim)
+    {
+        static int lim_key = -1, lim_wide = -1;
+        hipError_t e = hipSuccess;
+        if (lim_key < 0)
+            e = allow_lds(reinterpret_cast<const void *>(&routes_key_kernel<R, F, G, E, ORD>),
+                          &lim_key);
+        if (e == hipSuccess && lim_wide < 0)
+            e = allow_lds(reinterpret_cast<const void *>(&routes_wide_kernel<R, WF, WE, ORD>),
+                          &lim_wide);
+        *lim = lim_key < lim_wide ? lim_key : lim_wide;
+        return e;
+    }
+    static hipError_t launch(const int16_t *demands, int32_t N, int64_t S, int32_t Q,
+                             int32_t *costs, uint16_t *pred, uint16_t *cuts, int32_t *nroutes,
+                             const Workspace &ws, int32_t lds_bytes, int32_t pitch,
+                             const int2 *tabp, hipStream_t stream)
+    {
+        const dim3 grid((unsigned)num_tiles(S));
+        hipLaunchKernelGGL((routes_key_kernel<R, F, G, E, ORD>), grid, dim3(kWave),
+                           (size_t)lds_bytes, stream, demands, N, S, Q, costs, pred, cuts,
+                           nroutes, ws, lds_bytes, pitch, tabp);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL((routes_wide_kernel<R, WF, WE, ORD>), grid, dim3(kWave),
+                           (size_t)lds_bytes, stream, demands, N, S, Q, costs, pred, cuts,
+                           nroutes, ws, lds_bytes, pitch, tabp, (int32_t)key_shift<R>());
+        return hipGetLastError();
+    }
+};
+
+// Launches the key kernel and the wide kernel of ring R (the one that does
+// not serve the tour returns at once): on the demand tile in LDS, or, when
+// the workspace holds the tour-ordered copy, after the permute kernel wrote
+// it.
 template <int R, int F, int G, int E>
 hipError_t launch_route_tiles(int32_t n, const int16_t *demands, int32_t N, int64_t S,
                               int32_t Q, int32_t *costs, uint16_t *pred, uint16_t *cuts,
                               int32_t *nroutes, const Workspace &ws, int2 *tabp,
                               hipStream_t stream)
 {
-    constexpr int WF = WideOf<R>::F, WE = WideOf<R>::E;
-    static int lim_key = -1, lim_wide = -1;
-    hipError_t e = hipSuccess;
-    if (lim_key < 0)
-        e = allow_lds(reinterpret_cast<const void *>(&routes_key_kernel<R, F, G, E>), &lim_key);
-    if (e == hipSuccess && lim_wide < 0)
-        e = allow_lds(reinterpret_cast<const void *>(&routes_wide_kernel<R, WF, WE>), &lim_wide);
+    const size_t bits = (size_t)((n + 31) / 32) * 4 * kTile; // backtracking bitmask
+    int lim = 0;
+    if (ws.perm) {
+        hipError_t e = RouteKernels<R, F, G, E, true>::limit(&lim);
+        if (e == hipSuccess)
+            e = launch_permute(demands, N, S, 1, n, ws, stream);
+        if (e != hipSuccess)
+            return e;
+        const int32_t lds_bytes = bits <= (size_t)lim ? (int32_t)bits : 0;
+        return RouteKernels<R, F, G, E, true>::launch(demands, N, S, Q, costs, pred, cuts, nroutes,
+                                                      ws, lds_bytes, ordered_pitch(n), tabp,
+                                                      stream);
+    }
+    hipError_t e = RouteKernels<R, F, G, E, false>::limit(&lim);
     if (e != hipSuccess)
         return e;
-    const int lim = lim_key < lim_wide ? lim_key : lim_wide;
     // demand tile (whole rows, or the tour gathered) + flag word, and at
     // least room for the backtracking bitmask
     const int32_t pitch = gather_tile(n, N, lim) ? n + 1 : 0;
     const size_t stride = pitch ? (size_t)pitch : (size_t)N;
     const size_t tile = (((size_t)kTile * stride + 15) & ~(size_t)15) + 16;
-    const size_t bits = (size_t)((n + 31) / 32) * 4 * kTile;
     const size_t lds = tile > bits ? tile : bits;
     const int32_t lds_bytes = lds <= (size_t)lim ? (int32_t)lds : 0;
     if (pitch && lds_bytes) {
@@ -561,17 +690,8 @@ hipError_t launch_route_tiles(int32_t n, const int16_t *demands, int32_t N, int6
         if (e != hipSuccess)
             return e;
     }
-    const dim3 grid((unsigned)num_tiles(S));
-    hipLaunchKernelGGL((routes_key_kernel<R, F, G, E>), grid, dim3(kWave), (size_t)lds_bytes,
-                       stream, demands, N, S, Q, costs, pred, cuts, nroutes, ws, lds_bytes, pitch,
-                       tabp);
-    e = hipGetLastError();
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL((routes_wide_kernel<R, WF, WE>), grid, dim3(kWave), (size_t)lds_bytes,
-                       stream, demands, N, S, Q, costs, pred, cuts, nroutes, ws, lds_bytes, pitch,
-                       tabp, (int32_t)key_shift<R>());
-    return hipGetLastError();
+    return RouteKernels<R, F, G, E, false>::launch(demands, N, S, Q, costs, pred, cuts, nroutes,
+                                                   ws, lds_bytes, pitch, tabp, stream);
 }
 
 } // namespace
@@ -605,18 +725,39 @@ RouteVariant choose_route_variant(int32_t Q)
 
 static size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+static int g_route_path = 0; // 0 automatic, 1 demand tile in LDS, 2 tour-ordered copy
+
+void set_route_path(int path) { g_route_path = path; }
+
+// Whole-row tiles above this many bytes per wave stream the tour-ordered
+// copy instead (measured at n = N: 300 is faster in LDS, 500 streamed).
+constexpr int64_t kRouteTileMax = 24 * 1024;
+
+bool routes_ordered(int32_t n, int32_t N)
+{
+    if (n == 0 || !ordered_path_possible(N, n))
+        return false;
+    if (g_route_path)
+        return g_route_path == 2;
+    // a tour over at most half of the pool would be gathered into LDS with
+    // scattered 2-byte loads; the permute kernel's coalesced row reads and
+    // the streamed copy measured faster there (n = 200, N = 1000)
+    const bool gathered = 2 * ((int64_t)n + 1) <= N;
+    return gathered || (int64_t)kTile * N > kRouteTileMax;
+}
+
 size_t routes_workspace_bytes(int32_t n, int32_t N, int64_t S)
 {
-    // the evaluator's one-tour workspace, then the position table of a
-    // gathered tile
-    return round256(workspace_bytes(1, n, N, S, false)) +
+    // the evaluator's one-tour workspace (with the tour-ordered copy when
+    // that path is taken), then the position table of a gathered tile
+    return round256(workspace_bytes(1, n, N, S, routes_ordered(n, N))) +
            round256(((size_t)n + kTabPad) * sizeof(int2));
 }
 
 int2 *routes_position_table(void *workspace, int32_t n, int32_t N, int64_t S)
 {
     return reinterpret_cast<int2 *>(static_cast<char *>(workspace) +
-                                    round256(workspace_bytes(1, n, N, S, false)));
+                                    round256(workspace_bytes(1, n, N, S, routes_ordered(n, N))));
 }
 
 hipError_t launch_routes(const int32_t *tour, int32_t n, const int32_t *dist, int32_t N,

@@ -172,6 +172,31 @@ def test_routes_workspace_size():
     assert binding.routes_workspace_bytes(70000, 5, 10) == 0
 
 
+def test_route_path_setting_and_workspace():
+    """The ordered path adds the tour-ordered copy (S rows of n rounded up
+    to 32 plus 32 bytes) to the workspace; the LDS path does not; an
+    impossible ordered path (64 x N bytes past the LDS) falls back."""
+    n, N, S = 1000, 1000, 200_000
+    pitch = (n + 31) // 32 * 32 + 32
+    try:
+        binding.set_route_path(binding.ROUTE_PATH_LDS)
+        lds = binding.routes_workspace_bytes(n, N, S)
+        binding.set_route_path(binding.ROUTE_PATH_ORDERED)
+        ordered = binding.routes_workspace_bytes(n, N, S)
+        assert ordered - lds >= S * pitch
+        assert binding.routes_workspace_bytes(80, 3000, S) < S * 80  # no copy possible
+        binding.set_route_path(binding.ROUTE_PATH_AUTO)
+        assert binding.routes_workspace_bytes(n, N, S) == ordered   # long tour, large pool
+        assert binding.routes_workspace_bytes(200, 200, S) < S * 200  # 12.8 KB tiles stay in LDS
+        assert binding.routes_workspace_bytes(300, 300, S) < S * 300  # 19.2 KB too
+        assert binding.routes_workspace_bytes(200, 1000, S) >= S * 224  # part of a pool: streamed
+        for bad in (-1, 3):
+            with pytest.raises(binding.SplitError):
+                binding.set_route_path(bad)
+    finally:
+        binding.set_route_path(0)
+
+
 def test_routes_device_form_rejects_bad_arguments_before_device_work():
     P = ctypes.c_void_p
     fake = P(256)

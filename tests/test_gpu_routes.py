@@ -202,6 +202,88 @@ def test_routes_long_tour(binding):
 
 
 # ----------------------------------------------------------------------------
+# both demand paths forced: the tile in LDS (1) and the tour-ordered copy
+# streamed from the workspace (2)
+# ----------------------------------------------------------------------------
+def _case_ragged():
+    inst = W.plain_normal(61, 150, 64 * 13 + 29, 120)
+    return _inst_arrays(inst) + (inst.Q,)
+
+
+def _case_wide(scale, Q):
+    rng = np.random.default_rng(62 + scale)
+    N = n = 100
+    dist = W.dist_round(_coords(rng, N) * scale)
+    tour = (rng.permutation(N) + 1).astype(np.int32)
+    return tour, dist, rng.integers(1, 15, size=(64 * 5 + 5, N)).astype(np.int16), Q
+
+
+def _case_mixed():
+    rng = np.random.default_rng(63)
+    N, n = 130, 97  # a tour over part of the pool
+    dist = W.dist_round(_coords(rng, N))
+    tour = (rng.permutation(N)[:n] + 1).astype(np.int32)
+    dem = rng.integers(1, 12, size=(64 * 8 + 3, N)).astype(np.int16)
+    dem[64 * 2:64 * 3] = 1          # windows past ring 32
+    dem[64 * 5 + 1, tour[40] - 1] = 300  # a demand past a byte
+    dem[64 * 6:64 * 7:5, tour[7] - 1] = 70  # position 8 alone exceeds Q
+    return tour, dist, dem, 60
+
+
+def _case_long():
+    inst = W.plain_normal(64, 1000, 64 * 4 + 7, 150)
+    return _inst_arrays(inst) + (inst.Q,)
+
+
+def _case_short():
+    rng = np.random.default_rng(65)
+    N = 9
+    dist = W.dist_round(_coords(rng, N))
+    return np.array([4], np.int32), dist, rng.integers(0, 3, size=(130, N)).astype(np.int16), 2
+
+
+PATH_CASES = {
+    "ragged": _case_ragged,
+    "wide_x100": lambda: _case_wide(100, 100),
+    "wide_x14": lambda: _case_wide(14, 300),
+    "mixed_fallback": _case_mixed,
+    "long_n1000": _case_long,
+    "n1": _case_short,
+}
+
+
+@pytest.mark.parametrize("case", sorted(PATH_CASES))
+@pytest.mark.parametrize("path", [1, 2])
+def test_routes_forced_path(binding, path, case):
+    tour, dist, dem, Q = PATH_CASES[case]()
+    binding.set_route_path(path)
+    try:
+        for v in ((32, 8, 0, 4), (64, 16, 4, 4)):
+            binding.set_route_variant(*v)
+            _check(binding, tour, dist, dem, Q, "path %d %s %s" % (path, case, v))
+    finally:
+        binding.set_route_variant(0)
+        binding.set_route_path(0)
+
+
+def test_routes_ordered_path_invalid_inputs(binding):
+    rng = np.random.default_rng(66)
+    N = n = 300
+    dist = W.dist_round(_coords(rng, N))
+    tour = (rng.permutation(N) + 1).astype(np.int32)
+    dem = rng.integers(1, 10, size=(200, N)).astype(np.int16)
+    dem[150, tour[7] - 1] = -3
+    binding.set_route_path(2)
+    try:
+        got = _gpu_routes(binding, tour, dist, dem, 30)
+        assert (got["costs"] == oracle.INF32).all() and (got["nroutes"] == -1).all()
+        dem[150, tour[7] - 1] = 3
+        _check(binding, tour, dist, dem, 30, "ordered path, valid after invalid")
+    finally:
+        binding.set_route_path(0)
+
+
+# ----------------------------------------------------------------------------
 # degenerate cases
 # ----------------------------------------------------------------------------
 def test_routes_infeasible_scenarios(binding):
