@@ -227,15 +227,27 @@ int split_routes_set_path(int32_t path);
  * Host-checkable arguments are validated before anything is enqueued
  * (SPLIT_EINVAL).  The library touches the buffers only until the enqueued
  * work completes; two calls sharing a workspace must be ordered on one
- * stream.  Windows longer than the register ring, demands above 255 and
- * pools too large for a tile in LDS take an exact (slower) kernel; results
- * never depend on the path.
+ * stream.  Windows longer than the register ring and demands above 255
+ * take an exact (slower) kernel.  The demands are read from a tile staged
+ * in LDS, or, for long tours on large pools and tours over at most half of
+ * the pool, from a tour-ordered copy (one byte per position) written into
+ * the workspace, which then includes S x (n rounded up to 32, plus 32)
+ * bytes for it; results never depend on the path.
  */
 size_t split_variant_workspace_bytes(int32_t n, int32_t N, int64_t S, int32_t K);
 int split_variant_device(const int32_t *d_tour, int32_t n, const int32_t *d_dist, int32_t N,
                          const int16_t *d_demands, int64_t S, int32_t Q, int32_t beta, int32_t K,
                          int32_t *d_costs, int32_t *d_status, void *d_workspace, size_t ws_bytes,
                          split_stream_t stream);
+
+/*
+ * split_variant_set_path -- how later split-variant calls in the process
+ * read the demands, with split_routes_set_path's meaning (0 automatic,
+ * 1 the tile in LDS, 2 the tour-ordered copy where its permute tile fits).
+ * split_variant_workspace_bytes reflects the setting.  SPLIT_EINVAL outside
+ * [0, 2].  Not thread-safe against concurrent calls.
+ */
+int split_variant_set_path(int32_t path);
 
 /*
  * Min-plus Bellman updates (Sec. 2, min-plus matrix formulation: the

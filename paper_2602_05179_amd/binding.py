@@ -54,6 +54,7 @@ EXPORTED = (
     "split_routes_list_variants",
     "split_routes_set_path",
     "split_variant_workspace_bytes",
+    "split_variant_set_path",
     "split_variant_device",
     "split_minplus_forward_device",
     "split_minplus_backtrack_device",
@@ -147,6 +148,8 @@ def _load():
     lib.split_routes_list_variants.restype = ctypes.c_int
     lib.split_routes_set_path.restype = ctypes.c_int
     lib.split_routes_set_path.argtypes = [i32]
+    lib.split_variant_set_path.restype = ctypes.c_int
+    lib.split_variant_set_path.argtypes = [i32]
     lib.split_variant_workspace_bytes.restype = sz
     lib.split_variant_workspace_bytes.argtypes = [i32, i32, i64, i32]
     lib.split_variant_device.restype = ctypes.c_int
@@ -397,6 +400,12 @@ def split_routes_device(tour, dist, demands, Q, *, out=None, workspace=None, str
 # split variants: soft capacity (overload penalty) and a fleet bound
 # ---------------------------------------------------------------------------
 VARIANT_BAD_TOUR, VARIANT_BAD_DEMAND, VARIANT_PENALTY_RANGE = 1, 2, 4
+
+
+def set_variant_path(path: int):
+    """How the split variants read the demands: 0 automatic, 1 the tile
+    staged in LDS, 2 the tour-ordered copy in the workspace."""
+    _check(lib.split_variant_set_path(int(path)))
 
 
 def variant_workspace_bytes(n: int, N: int, S: int, K: int) -> int:

@@ -3,6 +3,7 @@ from __future__ import annotations
 
 import os
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -37,12 +38,40 @@ def hipcc() -> str:
     return "hipcc"
 
 
+def _jobs() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n, len(SOURCES)))
+
+
 def build_library(out: str = LIB, extra=()) -> str:
-    """Compile the kernels and the C ABI into one shared object."""
-    tmp = out + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, *extra, "-o", tmp, *SOURCES]
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, out)
+    """Compile the kernels and the C ABI into one shared object (one hipcc
+    process per source, in parallel, then one link)."""
+    objdir = os.path.join(os.path.dirname(out), "_build")
+    os.makedirs(objdir, exist_ok=True)
+    compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+
+    def compile_one(src):
+        obj = os.path.join(objdir, os.path.basename(src) + ".%d.o" % os.getpid())
+        cmd = [hipcc(), *compile_flags, "-I", INCLUDE, "-I", CSRC, *extra, "-c", "-o", obj, src]
+        return obj, subprocess.run(cmd).returncode
+
+    with ThreadPoolExecutor(max_workers=_jobs()) as pool:
+        results = list(pool.map(compile_one, SOURCES))
+    objs = [o for o, _ in results]
+    try:
+        failed = [os.path.basename(s) for s, (_, rc) in zip(SOURCES, results) if rc != 0]
+        if failed:
+            raise subprocess.CalledProcessError(1, "hipcc -c " + " ".join(failed))
+        tmp = out + ".tmp%d" % os.getpid()
+        subprocess.run([hipcc(), *HIPCC_FLAGS, *extra, "-o", tmp, *objs], check=True)
+        os.replace(tmp, out)
+    finally:
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
     return out
 
 

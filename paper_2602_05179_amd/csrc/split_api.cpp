@@ -380,6 +380,15 @@ int split_routes_device(const int32_t *d_tour, int32_t n, const int32_t *d_dist,
     return SPLIT_OK;
 }
 
+int split_variant_set_path(int32_t path)
+{
+    g_err[0] = 0;
+    if (path < 0 || path > 2)
+        return fail(SPLIT_EINVAL, "variant path must be 0, 1 or 2 (got %d)", path);
+    splitk::set_variant_path(path);
+    return SPLIT_OK;
+}
+
 size_t split_variant_workspace_bytes(int32_t n, int32_t N, int64_t S, int32_t K)
 {
     if (n < 0 || n > splitk::kMaxLen || S < 1 || N < 1 || K < 0)

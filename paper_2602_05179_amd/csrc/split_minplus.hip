@@ -198,9 +198,14 @@ __global__ void minplus_backtrack_kernel(const int32_t *__restrict__ JT,
     }
 }
 
-// one wave per (day, problem) tb = t*B + b: the cheapest route option with
-// room for each delivery size q (LDS), then the lanes write the entries
-// A(I, J) of its matrix in row-major order (coalesced)
+// One wave per (day, problem) pair tb = t*B + b (striding past 2^20): the
+// cheapest route option with room for each delivery size q (LDS), then the
+// lanes write the entries A(I, J) of its matrix in row-major order
+// (coalesced).  Entry e = lane + 64k has the same (I, J) in every matrix, so
+// each lane steps its (I, J) by 64 entries without a division; h sits in LDS.
+// Measured alternatives: persistent waves over many pairs (each wave then
+// serialises its load latencies) and per-lane option scans without LDS
+// (dependent loads per entry) were both slower.
 constexpr int kGenThreads = 64;
 
 __global__ __launch_bounds__(kGenThreads) void ou_transitions_kernel(
@@ -208,8 +213,14 @@ __global__ __launch_bounds__(kGenThreads) void ou_transitions_kernel(
     const int32_t *__restrict__ opt_cost, const int32_t *__restrict__ opt_cap,
     const int32_t *__restrict__ h, int32_t u, int32_t rho, int32_t *__restrict__ A)
 {
-    extern __shared__ long long tr[]; // transport(q), q = 0..U (kMpInf: impossible)
+    extern __shared__ long long tr[]; // transport(q), q = 0..U (kMpInf: impossible); then h
     const int m = U + 1;
+    int32_t *hs = reinterpret_cast<int32_t *>(tr + m);
+    for (int J = threadIdx.x; J < m; J += blockDim.x)
+        hs[J] = h[J];
+    const int mm = m * m;
+    const int I0 = (int)threadIdx.x / m, J0 = (int)threadIdx.x - I0 * m;
+    const int dI = kGenThreads / m, dJ = kGenThreads - dI * m;
     for (int64_t tb = blockIdx.x; tb < TB; tb += gridDim.x) {
         __syncthreads();
         for (int q = threadIdx.x; q < m; q += blockDim.x) {
@@ -221,18 +232,26 @@ __global__ __launch_bounds__(kGenThreads) void ou_transitions_kernel(
         }
         __syncthreads();
         const int d = demand[tb];
-        int32_t *out = A + tb * (int64_t)m * m;
-        for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-            const int I = e / m, J = e - I * m;
+        const long long deliver_left = (long long)rho * max(0, d - U); // shortage after delivering
+        const int Jd = max(0, U - d);                                   // level after delivering
+        int32_t *out = A + tb * (int64_t)mm;
+        int I = I0, J = J0;
+        for (int e = threadIdx.x; e < mm; e += kGenThreads) {
             long long best = kMpInf;
             // no delivery
             if (max(0, I - d) == J)
-                best = (long long)h[J] + (long long)rho * max(0, d - I);
+                best = (long long)hs[J] + (long long)rho * max(0, d - I);
             // deliver up to U (a distinct choice only when I < U)
             const int q = U - I;
-            if (q > 0 && tr[q] < kMpInf && max(0, U - d) == J)
-                best = min(best, tr[q] + h[J] + (long long)rho * max(0, d - U));
+            if (q > 0 && J == Jd && tr[q] < kMpInf)
+                best = min(best, tr[q] + hs[J] + deliver_left);
             out[e] = (int32_t)min(best, (long long)kMpInf);
+            I += dI;
+            J += dJ;
+            if (J >= m) {
+                J -= m;
+                ++I;
+            }
         }
     }
 }
@@ -269,10 +288,12 @@ hipError_t launch_ou_transitions(int32_t U, int32_t T, int64_t B, int32_t R,
                                  int32_t *A, hipStream_t stream)
 {
     const int64_t TB = (int64_t)T * B;
+    // one wave per pair (a persistent grid serialises each wave's global
+    // load latencies over its pairs: measured slower)
     const int64_t blocks = TB < (1 << 20) ? TB : (1 << 20);
     hipLaunchKernelGGL(ou_transitions_kernel, dim3((unsigned)blocks), dim3(kGenThreads),
-                       ((size_t)U + 1) * sizeof(long long), stream, U, TB, R, demand, opt_cost,
-                       opt_cap, h, u, rho, A);
+                       ((size_t)U + 1) * (sizeof(long long) + sizeof(int32_t)), stream, U, TB, R,
+                       demand, opt_cost, opt_cap, h, u, rho, A);
     return hipGetLastError();
 }
 

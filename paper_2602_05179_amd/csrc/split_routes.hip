@@ -69,65 +69,6 @@ __device__ __forceinline__ bool keys_fit(const TourRec &rec, int B)
     return (long long)3 * rec.n * rec.maxc < (1LL << (29 - B));
 }
 
-// Demand bytes of one lane's scenario, read in tour order by the recursion:
-// position j's demand at position j - 2 (two ahead), after `init` has read
-// positions 1 and 2.  ahead<U>(t) is called at position j = j0 + U of a
-// block (j0 a multiple of 32), with t the table entry of position j + 2.
-
-// a row in LDS, indexed through the table (the customer index for whole
-// rows, position - 1 for a gathered tile)
-struct LdsRow {
-    const uint8_t *row;
-    __device__ __forceinline__ void init(int2 t0, int2 t1, int &q1, int &q2) const
-    {
-        q1 = row[t0.x];
-        q2 = row[t1.x];
-    }
-    template <int U> __device__ __forceinline__ int ahead(int2 t) const { return row[t.x]; }
-};
-
-// the lane's row of the tour-ordered copy in global memory (byte j - 1 =
-// position j, zero-padded to a multiple of 32 bytes plus 32), held 32 bytes
-// at a time in registers with the next 32 in flight
-struct StreamRow {
-    const u32x4 *row;
-    int segs; // 32-byte segments in the row (at least 2)
-    int nseg; // segment held in nxt
-    u32x4 cur[2], nxt[2];
-
-    template <int B> __device__ __forceinline__ static int byte_of(const u32x4 (&seg)[2])
-    {
-        const u32x4 &v = seg[B >> 4];
-        constexpr int w = (B >> 2) & 3;
-        const uint32_t x = w == 0 ? v.x : w == 1 ? v.y : w == 2 ? v.z : v.w;
-        return (int)((x >> (8 * (B & 3))) & 0xFFu);
-    }
-    __device__ __forceinline__ void init(int2, int2, int &q1, int &q2)
-    {
-        cur[0] = __builtin_nontemporal_load(row);
-        cur[1] = __builtin_nontemporal_load(row + 1);
-        nxt[0] = __builtin_nontemporal_load(row + 2);
-        nxt[1] = __builtin_nontemporal_load(row + 3);
-        nseg = 1;
-        q1 = byte_of<0>(cur);
-        q2 = byte_of<1>(cur);
-    }
-    template <int U> __device__ __forceinline__ int ahead(int2)
-    {
-        constexpr int B = (U + 1) & 31; // byte j + 1 of the row
-        const int v = byte_of<B>(cur);
-        if (B == 31) { // next 32 positions: rotate and fetch the segment after
-            cur[0] = nxt[0];
-            cur[1] = nxt[1];
-            if (++nseg < segs) {
-                nxt[0] = __builtin_nontemporal_load(row + 2 * nseg);
-                nxt[1] = __builtin_nontemporal_load(row + 2 * nseg + 1);
-            }
-        }
-        return v;
-    }
-};
-
 // Backtracking of one scenario from position n.  pcol / ccol point at the
 // scenario's column of pred / cuts (stride S).  Returns the number of
 // routes, or -1 if the chain does not descend (never for a finite V(n)).

@@ -8,10 +8,17 @@
 
 namespace splitk {
 
-// Workspace of a variant call: the evaluator's one-tour workspace, two
+// Workspace of a variant call: the evaluator's one-tour workspace (with the
+// tour-ordered copy when that path is taken), two
 // position-major potential buffers [n][S] when K > 0, and the exact
 // fallback's two value arrays per block.
 size_t variant_workspace_bytes(int32_t n, int32_t N, int64_t S, int32_t K);
+
+// Whether a call streams the tour-ordered copy of the demands (path
+// override, else by the demand bytes per wave of the LDS tile); the
+// workspace holds the copy then.
+bool variants_ordered(int32_t n, int32_t N, int32_t K);
+void set_variant_path(int path); // 0 automatic, 1 LDS tile, 2 tour-ordered copy
 
 // Register ring length used for this capacity (32, or 64 above Q = 200).
 int variant_ring(int32_t Q);

@@ -71,6 +71,7 @@ struct VarArgs {
     int *vs;          // fallback scratch [blocks][2][n+1][64]
     int32_t pitch;    // 0: whole scenario rows in LDS; else the tour gathered, row stride pitch
     const int2 *tabp; // per-tour table indexed by position (gathered tile)
+    int32_t opitch;   // row stride of the tour-ordered copy (ordered kernels)
 };
 
 // Stages the tile (whole rows or the tour gathered) and returns the table
@@ -106,9 +107,10 @@ struct VarRegs {
 // potentials and this pass's are written out; otherwise the ring holds the
 // pass's own potentials (unlimited fleet).
 template <int R, bool SOFT, bool LAYERED, int U> struct VarState {
-    __device__ __forceinline__ static bool run(int (&f)[R], int (&lq)[R], VarRegs &r,
-                                               const uint8_t *row, CInt *tab, int j0, int n,
-                                               int Q, int beta, bool has_src, int64_t S)
+    template <class Src>
+    __device__ __forceinline__ static bool run(int (&f)[R], int (&lq)[R], VarRegs &r, Src &src,
+                                               CInt *tab, int j0, int n, int Q, int beta,
+                                               bool has_src, int64_t S)
     {
         const int j = j0 + U;
         if (U == 0 && j == 0)
@@ -117,7 +119,7 @@ template <int R, bool SOFT, bool LAYERED, int U> struct VarState {
             return false;
         const int cj = r.t0.y;
         const int Ln = r.L + r.qa;
-        r.qa = row[r.t2.x];
+        r.qa = src.template ahead<U>(r.t2);
         const int2 t3 = tab_at(tab, j + 3);
         int pf2 = kInf;
         if constexpr (LAYERED) {
@@ -178,23 +180,22 @@ template <int R, bool SOFT, bool LAYERED, int U> struct VarState {
     }
 };
 
-template <int R, bool SOFT, bool LAYERED, int... Us>
-__device__ __forceinline__ bool var_block(int (&f)[R], int (&lq)[R], VarRegs &r,
-                                          const uint8_t *row, CInt *tab, int j0, int n, int Q,
-                                          int beta, bool has_src, int64_t S,
-                                          std::integer_sequence<int, Us...>)
+template <int R, bool SOFT, bool LAYERED, class Src, int... Us>
+__device__ __forceinline__ bool var_block(int (&f)[R], int (&lq)[R], VarRegs &r, Src &src,
+                                          CInt *tab, int j0, int n, int Q, int beta, bool has_src,
+                                          int64_t S, std::integer_sequence<int, Us...>)
 {
-    return (VarState<R, SOFT, LAYERED, Us>::run(f, lq, r, row, tab, j0, n, Q, beta, has_src, S) &&
+    return (VarState<R, SOFT, LAYERED, Us>::run(f, lq, r, src, tab, j0, n, Q, beta, has_src, S) &&
             ...);
 }
 
-// One pass over the tour.  src: previous pass's potentials of this lane's
-// column (nullptr for the first pass of a layered run); dst: this pass's.
-// Returns m_n.
-template <int R, bool SOFT, bool LAYERED>
-__device__ __forceinline__ int var_pass(const uint8_t *row, CInt *tab, const TourRec &rec, int Q,
-                                        int beta, int first_f, const int *src, int *dst,
-                                        int64_t S, bool &ovf, int &Ltot)
+// One pass over the tour, reading the demands from a fresh copy of dsrc.
+// src: previous pass's potentials of this lane's column (nullptr for the
+// first pass of a layered run); dst: this pass's.  Returns m_n.
+template <int R, bool SOFT, bool LAYERED, class Src>
+__device__ __forceinline__ int var_pass(Src dsrc, CInt *tab, const TourRec &rec, int Q, int beta,
+                                        int first_f, const int *src, int *dst, int64_t S,
+                                        bool &ovf, int &Ltot)
 {
     // slots before the tour start: potential +inf; soft capacity gives them
     // a threshold no load reaches (cost +inf without a mask), hard capacity
@@ -217,8 +218,7 @@ __device__ __forceinline__ int var_pass(const uint8_t *row, CInt *tab, const Tou
     r.t0 = tab_at(tab, 1);
     r.t1 = tab_at(tab, 2);
     r.t2 = tab_at(tab, 3);
-    r.L = row[r.t0.x];
-    r.qa = row[r.t1.x];
+    dsrc.init(r.t0, r.t1, r.L, r.qa);
     const int n = rec.n;
     r.pf0 = kInf;
     r.pf1 = kInf;
@@ -236,7 +236,7 @@ __device__ __forceinline__ int var_pass(const uint8_t *row, CInt *tab, const Tou
         r.dstp = dst + S; // row j at position j = 1
     }
     for (int j0 = 0; j0 <= n; j0 += R) {
-        if (!var_block<R, SOFT, LAYERED>(f, lq, r, row, tab, j0, n, Q, beta, has_src, S,
+        if (!var_block<R, SOFT, LAYERED>(f, lq, r, dsrc, tab, j0, n, Q, beta, has_src, S,
                                          std::make_integer_sequence<int, R>{}))
             break;
     }
@@ -269,9 +269,10 @@ template <int NL> struct VarMultiRegs {
 };
 
 template <int R, int NL, bool SOFT, int U> struct VarMultiState {
+    template <class Src>
     __device__ __forceinline__ static bool run(int (&f)[NL][R], int (&lq)[R], VarMultiRegs<NL> &r,
-                                               const uint8_t *row, CInt *tab, int j0, int n,
-                                               int Q, int beta, bool has_src, int64_t S)
+                                               Src &src, CInt *tab, int j0, int n, int Q, int beta,
+                                               bool has_src, int64_t S)
     {
         const int j = j0 + U;
         if (U == 0 && j == 0)
@@ -280,7 +281,7 @@ template <int R, int NL, bool SOFT, int U> struct VarMultiState {
             return false;
         const int cj = r.t0.y;
         const int Ln = r.L + r.qa;
-        r.qa = row[r.t2.x];
+        r.qa = src.template ahead<U>(r.t2);
         const int2 t3 = tab_at(tab, j + 3);
         int pf2 = kInf;
         if (has_src) {
@@ -344,23 +345,22 @@ template <int R, int NL, bool SOFT, int U> struct VarMultiState {
     }
 };
 
-template <int R, int NL, bool SOFT, int... Us>
+template <int R, int NL, bool SOFT, class Src, int... Us>
 __device__ __forceinline__ bool var_multi_block(int (&f)[NL][R], int (&lq)[R],
-                                                VarMultiRegs<NL> &r, const uint8_t *row,
-                                                CInt *tab, int j0, int n, int Q, int beta,
-                                                bool has_src, int64_t S,
+                                                VarMultiRegs<NL> &r, Src &src, CInt *tab, int j0,
+                                                int n, int Q, int beta, bool has_src, int64_t S,
                                                 std::integer_sequence<int, Us...>)
 {
-    return (VarMultiState<R, NL, SOFT, Us>::run(f, lq, r, row, tab, j0, n, Q, beta, has_src, S) &&
+    return (VarMultiState<R, NL, SOFT, Us>::run(f, lq, r, src, tab, j0, n, Q, beta, has_src, S) &&
             ...);
 }
 
 // One sweep: passes k0 .. k0+NL-1.  src: pass k0-1's potentials (nullptr
 // when k0 = 1); dst: pass k0+NL-1's.  m_n of every pass in mres.
-template <int R, int NL, bool SOFT>
-__device__ __forceinline__ void var_sweep(const uint8_t *row, CInt *tab, const TourRec &rec, int Q,
-                                          int beta, int k0, const int *src, int *dst, int64_t S,
-                                          bool &ovf, int &Ltot, int (&mres)[NL])
+template <int R, int NL, bool SOFT, class Src>
+__device__ __forceinline__ void var_sweep(Src dsrc, CInt *tab, const TourRec &rec, int Q, int beta,
+                                          int k0, const int *src, int *dst, int64_t S, bool &ovf,
+                                          int &Ltot, int (&mres)[NL])
 {
     // slots before the tour start: +inf potentials; soft capacity gives them
     // a threshold no load reaches, hard capacity one every load exceeds
@@ -388,8 +388,7 @@ __device__ __forceinline__ void var_sweep(const uint8_t *row, CInt *tab, const T
     r.t0 = tab_at(tab, 1);
     r.t1 = tab_at(tab, 2);
     r.t2 = tab_at(tab, 3);
-    r.L = row[r.t0.x];
-    r.qa = row[r.t1.x];
+    dsrc.init(r.t0, r.t1, r.L, r.qa);
     const int n = rec.n;
     r.pf0 = kInf;
     r.pf1 = kInf;
@@ -404,7 +403,7 @@ __device__ __forceinline__ void var_sweep(const uint8_t *row, CInt *tab, const T
     }
     r.dstp = dst + S;
     for (int j0 = 0; j0 <= n; j0 += R) {
-        if (!var_multi_block<R, NL, SOFT>(f, lq, r, row, tab, j0, n, Q, beta, has_src, S,
+        if (!var_multi_block<R, NL, SOFT>(f, lq, r, dsrc, tab, j0, n, Q, beta, has_src, S,
                                           std::make_integer_sequence<int, R>{}))
             break;
     }
@@ -417,7 +416,55 @@ __device__ __forceinline__ void var_sweep(const uint8_t *row, CInt *tab, const T
 
 // grid = tiles, one wave each; LDS as variant_tile_kernel.  Fleet bound
 // K > 0, hard or soft capacity.
-template <int R, int NL, bool SOFT>
+// The fleet-bounded passes of one lane, in sweeps of NL: the minimum over
+// passes of m_n (kInf if none is finite); sets ovf, Ltot.
+template <int R, int NL, bool SOFT, class Src>
+__device__ __forceinline__ int multi_lane(const Src &dsrc, CInt *tab, const TourRec &rec,
+                                          const VarArgs &a, int64_t s, bool &ovf, int &Ltot)
+{
+    const int passes = a.K < rec.n ? a.K : rec.n;
+    const int *src = nullptr;
+    int *dst = a.lay0 + s;
+    int best = kInf;
+    for (int k0 = 1; k0 <= passes; k0 += NL) {
+        bool o = false;
+        int mres[NL];
+        var_sweep<R, NL, SOFT>(dsrc, tab, rec, a.Q, a.beta, k0, src, dst, a.S, o, Ltot, mres);
+        ovf = ovf || o;
+#pragma unroll
+        for (int g = 0; g < NL; ++g)
+            if (k0 + g <= passes)
+                best = min(best, mres[g]);
+        src = dst;
+        dst = (dst == a.lay0 + s) ? a.lay1 + s : a.lay0 + s;
+    }
+    return best;
+}
+
+// The tile's demands: staged in LDS (whole rows or the tour gathered), or,
+// ORD, the tour-ordered copy the permute kernel wrote (tiles it flagged
+// take the exact fallback).  Returns false when the tile must be redone.
+template <bool ORD>
+__device__ __forceinline__ bool variant_tile_source(const VarArgs &a, const Workspace &ws,
+                                                    const TourRec &rec, int64_t k, int64_t s0,
+                                                    int rows, uint8_t *lds, int lane,
+                                                    int32_t lds_bytes, CInt *&tab, int &stride)
+{
+    if constexpr (ORD) {
+        tab = (CInt *)ws.tab;
+        stride = a.opitch;
+        return ws.tile_bad[k] == 0;
+    } else {
+        tab = nullptr;
+        stride = a.N;
+        return lds_bytes ? stage_variant_tile(a, ws, rec.n, s0, rows, lds, lane, tab, stride)
+                         : false;
+    }
+}
+
+// grid = tiles, one wave each; LDS as variant_tile_kernel (none when ORD).
+// Fleet bound K > 0, hard or soft capacity.
+template <int R, int NL, bool SOFT, bool ORD>
 __global__ __launch_bounds__(kWave) void variant_multi_kernel(VarArgs a, Workspace ws,
                                                               int32_t lds_bytes)
 {
@@ -434,34 +481,25 @@ __global__ __launch_bounds__(kWave) void variant_multi_kernel(VarArgs a, Workspa
             a.costs[s0 + lane] = 0;
         return;
     }
-    bool ok = false;
-    CInt *tab = nullptr;
-    int stride = a.N;
-    if (lds_bytes)
-        ok = stage_variant_tile(a, ws, rec.n, s0, rows, lds, lane, tab, stride);
+    CInt *tab;
+    int stride;
+    const bool ok =
+        variant_tile_source<ORD>(a, ws, rec, k, s0, rows, lds, lane, lds_bytes, tab, stride);
     bool redo = true;
     if (ok) {
         bool ovf = false, range_bad = false;
         int best = kInf;
         if (lane < rows) {
-            const uint8_t *row = lds + (int64_t)lane * stride;
             const int64_t s = s0 + lane;
-            const int passes = a.K < rec.n ? a.K : rec.n;
-            const int *src = nullptr;
-            int *dst = a.lay0 + s;
             int Ltot = 0;
-            for (int k0 = 1; k0 <= passes; k0 += NL) {
-                bool o = false;
-                int mres[NL];
-                var_sweep<R, NL, SOFT>(row, tab, rec, a.Q, a.beta, k0, src, dst, a.S, o, Ltot,
-                                       mres);
-                ovf = ovf || o;
-#pragma unroll
-                for (int g = 0; g < NL; ++g)
-                    if (k0 + g <= passes)
-                        best = min(best, mres[g]);
-                src = dst;
-                dst = (dst == a.lay0 + s) ? a.lay1 + s : a.lay0 + s;
+            if constexpr (ORD) {
+                StreamRow src;
+                src.row = reinterpret_cast<const u32x4 *>(ws.perm + s * (int64_t)stride);
+                src.segs = stride / 32;
+                best = multi_lane<R, NL, SOFT>(src, tab, rec, a, s, ovf, Ltot);
+            } else {
+                const LdsRow src{lds + (int64_t)lane * stride};
+                best = multi_lane<R, NL, SOFT>(src, tab, rec, a, s, ovf, Ltot);
             }
             range_bad = !penalty_fits(rec, a.beta, a.Q, Ltot);
         }
@@ -487,9 +525,37 @@ __device__ __forceinline__ bool penalty_fits(const TourRec &rec, int beta, int Q
            (long long)3 * rec.n * rec.maxc + (long long)beta * lq < (1LL << 29);
 }
 
-// grid = tiles, one wave each; LDS: 64 x N demand bytes + flag word.
-// LAYERED: K passes (fleet bound); otherwise one pass (unlimited fleet).
-template <int R, bool SOFT, bool LAYERED>
+// The passes of one lane: one (unlimited fleet) or K (LAYERED); the
+// minimum over passes of m_n; sets ovf, Ltot.
+template <int R, bool SOFT, bool LAYERED, class Src>
+__device__ __forceinline__ int tile_lane(const Src &dsrc, CInt *tab, const TourRec &rec,
+                                         const VarArgs &a, int64_t s, bool &ovf, int &Ltot)
+{
+    if constexpr (!LAYERED) {
+        return var_pass<R, SOFT, false>(dsrc, tab, rec, a.Q, a.beta, rec.f0, nullptr, nullptr,
+                                        a.S, ovf, Ltot);
+    } else {
+        const int *src = nullptr;
+        int *dst = a.lay0 + s;
+        const int passes = a.K < rec.n ? a.K : rec.n;
+        int best = kInf;
+        for (int kk = 1; kk <= passes; ++kk) {
+            bool o = false;
+            const int m = var_pass<R, SOFT, true>(dsrc, tab, rec, a.Q, a.beta,
+                                                  kk == 1 ? rec.f0 : kInf, src, dst, a.S, o, Ltot);
+            ovf = ovf || o;
+            best = min(best, m);
+            src = dst;
+            dst = (dst == a.lay0 + s) ? a.lay1 + s : a.lay0 + s;
+        }
+        return best;
+    }
+}
+
+// grid = tiles, one wave each; LDS: the demand tile + flag word (none when
+// ORD).  LAYERED: K passes (fleet bound); otherwise one pass (unlimited
+// fleet).
+template <int R, bool SOFT, bool LAYERED, bool ORD>
 __global__ __launch_bounds__(kWave) void variant_tile_kernel(VarArgs a, Workspace ws,
                                                              int32_t lds_bytes)
 {
@@ -506,36 +572,25 @@ __global__ __launch_bounds__(kWave) void variant_tile_kernel(VarArgs a, Workspac
             a.costs[s0 + lane] = 0;
         return;
     }
-    bool ok = false;
-    CInt *tab = nullptr;
-    int stride = a.N;
-    if (lds_bytes)
-        ok = stage_variant_tile(a, ws, rec.n, s0, rows, lds, lane, tab, stride);
+    CInt *tab;
+    int stride;
+    const bool ok =
+        variant_tile_source<ORD>(a, ws, rec, k, s0, rows, lds, lane, lds_bytes, tab, stride);
     bool redo = true;
     if (ok) {
         bool ovf = false, range_bad = false;
         int best = kInf;
         if (lane < rows) {
-            const uint8_t *row = lds + (int64_t)lane * stride;
             const int64_t s = s0 + lane;
             int Ltot = 0;
-            if constexpr (!LAYERED) {
-                best = var_pass<R, SOFT, false>(row, tab, rec, a.Q, a.beta, rec.f0, nullptr,
-                                                nullptr, a.S, ovf, Ltot);
+            if constexpr (ORD) {
+                StreamRow src;
+                src.row = reinterpret_cast<const u32x4 *>(ws.perm + s * (int64_t)stride);
+                src.segs = stride / 32;
+                best = tile_lane<R, SOFT, LAYERED>(src, tab, rec, a, s, ovf, Ltot);
             } else {
-                const int *src = nullptr;
-                int *dst = a.lay0 + s;
-                const int passes = a.K < rec.n ? a.K : rec.n;
-                for (int kk = 1; kk <= passes; ++kk) {
-                    bool o = false;
-                    const int m = var_pass<R, SOFT, true>(row, tab, rec, a.Q, a.beta,
-                                                          kk == 1 ? rec.f0 : kInf, src, dst, a.S,
-                                                          o, Ltot);
-                    ovf = ovf || o;
-                    best = min(best, m);
-                    src = dst;
-                    dst = (dst == a.lay0 + s) ? a.lay1 + s : a.lay0 + s;
-                }
+                const LdsRow src{lds + (int64_t)lane * stride};
+                best = tile_lane<R, SOFT, LAYERED>(src, tab, rec, a, s, ovf, Ltot);
             }
             range_bad = !penalty_fits(rec, a.beta, a.Q, Ltot);
         }
@@ -665,16 +720,44 @@ int32_t variant_lds_bytes(const VarArgs &a, int lim)
     return lds <= (size_t)lim ? (int32_t)lds : 0;
 }
 
+template <int R, bool SOFT, bool LAYERED, bool ORD>
+hipError_t launch_variant_tiles_as(const VarArgs &a, const Workspace &ws, hipStream_t stream)
+{
+    int32_t lds_bytes = 0;
+    if constexpr (!ORD) {
+        static int lim = -1;
+        hipError_t e = allow_lds_once(
+            reinterpret_cast<const void *>(&variant_tile_kernel<R, SOFT, LAYERED, false>), &lim);
+        if (e != hipSuccess)
+            return e;
+        lds_bytes = variant_lds_bytes(a, lim);
+    }
+    hipLaunchKernelGGL((variant_tile_kernel<R, SOFT, LAYERED, ORD>),
+                       dim3((unsigned)num_tiles(a.S)), dim3(kWave), (size_t)lds_bytes, stream, a,
+                       ws, lds_bytes);
+    return hipGetLastError();
+}
+
 template <int R, bool SOFT, bool LAYERED>
 hipError_t launch_variant_tiles(const VarArgs &a, const Workspace &ws, hipStream_t stream)
 {
-    static int lim = -1;
-    hipError_t e = allow_lds_once(
-        reinterpret_cast<const void *>(&variant_tile_kernel<R, SOFT, LAYERED>), &lim);
-    if (e != hipSuccess)
-        return e;
-    const int32_t lds_bytes = variant_lds_bytes(a, lim);
-    hipLaunchKernelGGL((variant_tile_kernel<R, SOFT, LAYERED>), dim3((unsigned)num_tiles(a.S)),
+    return ws.perm ? launch_variant_tiles_as<R, SOFT, LAYERED, true>(a, ws, stream)
+                   : launch_variant_tiles_as<R, SOFT, LAYERED, false>(a, ws, stream);
+}
+
+template <int R, int NL, bool SOFT, bool ORD>
+hipError_t launch_variant_multi_as(const VarArgs &a, const Workspace &ws, hipStream_t stream)
+{
+    int32_t lds_bytes = 0;
+    if constexpr (!ORD) {
+        static int lim = -1;
+        hipError_t e = allow_lds_once(
+            reinterpret_cast<const void *>(&variant_multi_kernel<R, NL, SOFT, false>), &lim);
+        if (e != hipSuccess)
+            return e;
+        lds_bytes = variant_lds_bytes(a, lim);
+    }
+    hipLaunchKernelGGL((variant_multi_kernel<R, NL, SOFT, ORD>), dim3((unsigned)num_tiles(a.S)),
                        dim3(kWave), (size_t)lds_bytes, stream, a, ws, lds_bytes);
     return hipGetLastError();
 }
@@ -682,15 +765,8 @@ hipError_t launch_variant_tiles(const VarArgs &a, const Workspace &ws, hipStream
 template <int R, int NL, bool SOFT>
 hipError_t launch_variant_multi(const VarArgs &a, const Workspace &ws, hipStream_t stream)
 {
-    static int lim = -1;
-    hipError_t e = allow_lds_once(
-        reinterpret_cast<const void *>(&variant_multi_kernel<R, NL, SOFT>), &lim);
-    if (e != hipSuccess)
-        return e;
-    const int32_t lds_bytes = variant_lds_bytes(a, lim);
-    hipLaunchKernelGGL((variant_multi_kernel<R, NL, SOFT>), dim3((unsigned)num_tiles(a.S)),
-                       dim3(kWave), (size_t)lds_bytes, stream, a, ws, lds_bytes);
-    return hipGetLastError();
+    return ws.perm ? launch_variant_multi_as<R, NL, SOFT, true>(a, ws, stream)
+                   : launch_variant_multi_as<R, NL, SOFT, false>(a, ws, stream);
 }
 
 // passes per sweep of the fleet-bounded kernels: as many rings as keep the
@@ -726,9 +802,32 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 } // namespace
 
+static int g_variant_path = 0; // 0 automatic, 1 demand tile in LDS, 2 tour-ordered copy
+
+void set_variant_path(int path) { g_variant_path = path; }
+
+// LDS tiles above this many bytes per wave stream the tour-ordered copy
+// instead (measured: n = N = 200 faster in LDS, 500 and 1000 streamed).
+constexpr int64_t kVariantTileMax = 24 * 1024;
+
+bool variants_ordered(int32_t n, int32_t N, int32_t K)
+{
+    if (n == 0 || !ordered_path_possible(N, n))
+        return false;
+    if (g_variant_path)
+        return g_variant_path == 2;
+    // a tour over at most half of the pool is gathered into LDS; one pass
+    // (K = 0) measured faster streamed, but K passes re-read the copy from
+    // HBM each sweep and measured faster from the gathered tile (n = 200,
+    // N = 1000)
+    const bool gathered = 2 * ((int64_t)n + 1) <= N;
+    const int64_t tile = (int64_t)kTile * (gathered ? (int64_t)n + 1 : (int64_t)N);
+    return tile > kVariantTileMax || (gathered && K == 0);
+}
+
 size_t variant_workspace_bytes(int32_t n, int32_t N, int64_t S, int32_t K)
 {
-    size_t b = align256(workspace_bytes(1, n, N, S, false));
+    size_t b = align256(workspace_bytes(1, n, N, S, variants_ordered(n, N, K)));
     if (K > 0)
         b += 2 * align256((size_t)n * (size_t)S * sizeof(int));
     b += align256((size_t)kFallbackBlocks * 2 * ((size_t)n + 1) * kWave * sizeof(int));
@@ -743,8 +842,9 @@ hipError_t launch_variant(const int32_t *tour, int32_t n, const int32_t *dist, i
                           int32_t *costs, int32_t *status, void *workspace, hipStream_t stream)
 {
     char *p = static_cast<char *>(workspace);
-    const Workspace ws = carve_workspace(p, 1, n, N, S, false);
-    p += align256(workspace_bytes(1, n, N, S, false));
+    const bool ordered = variants_ordered(n, N, K);
+    const Workspace ws = carve_workspace(p, 1, n, N, S, ordered);
+    p += align256(workspace_bytes(1, n, N, S, ordered));
     VarArgs a;
     a.demands = demands;
     a.N = N;
@@ -775,8 +875,14 @@ hipError_t launch_variant(const int32_t *tour, int32_t n, const int32_t *dist, i
     if (e != hipSuccess)
         return e;
     lim = lim < kLdsLimit ? lim : kLdsLimit;
-    a.pitch = gather_tile(n, N, lim) ? n + 1 : 0;
+    a.pitch = !ordered && gather_tile(n, N, lim) ? n + 1 : 0;
     a.tabp = tabp;
+    a.opitch = ordered ? ordered_pitch(n) : 0;
+    if (ordered) {
+        e = launch_permute(demands, N, S, 1, n, ws, stream);
+        if (e != hipSuccess)
+            return e;
+    }
     if (a.pitch) {
         hipLaunchKernelGGL(position_table_kernel, dim3(1), dim3(256), 0, stream, ws.tab, n, tabp);
         e = hipGetLastError();

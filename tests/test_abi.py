@@ -197,6 +197,24 @@ def test_route_path_setting_and_workspace():
         binding.set_route_path(0)
 
 
+def test_variant_path_setting_and_workspace():
+    n, N, S = 1000, 1000, 100_000
+    pitch = (n + 31) // 32 * 32 + 32
+    try:
+        binding.set_variant_path(1)
+        lds = binding.variant_workspace_bytes(n, N, S, 5)
+        binding.set_variant_path(2)
+        assert binding.variant_workspace_bytes(n, N, S, 5) - lds >= S * pitch
+        binding.set_variant_path(0)
+        assert binding.variant_workspace_bytes(n, N, S, 5) - lds >= S * pitch
+        assert binding.variant_workspace_bytes(200, 200, S, 0) < S * 200
+        for bad in (-1, 3):
+            with pytest.raises(binding.SplitError):
+                binding.set_variant_path(bad)
+    finally:
+        binding.set_variant_path(0)
+
+
 def test_routes_device_form_rejects_bad_arguments_before_device_work():
     P = ctypes.c_void_p
     fake = P(256)

@@ -152,6 +152,70 @@ def test_variant_pool_too_large_for_lds(binding):
 
 
 # ----------------------------------------------------------------------------
+# both demand paths forced: the tile in LDS (1) and the tour-ordered copy
+# streamed from the workspace (2)
+# ----------------------------------------------------------------------------
+def _path_mixed():
+    rng = np.random.default_rng(80)
+    N, n = 110, 83  # a tour over part of the pool
+    dist = W.dist_round(W.coords(rng, N))
+    tour = (rng.permutation(N)[:n] + 1).astype(np.int32)
+    dem = rng.integers(1, 12, size=(64 * 7 + 11, N)).astype(np.int16)
+    dem[64 * 2:64 * 3] = 1                       # a tile with long hard windows
+    dem[64 * 4 + 3, tour[30] - 1] = 280          # a demand past a byte
+    return tour, dist, dem
+
+
+@pytest.mark.parametrize("beta,K", [(-1, 0), (-1, 4), (-1, 9), (3, 0), (3, 5)])
+@pytest.mark.parametrize("Q", [60, 250])
+@pytest.mark.parametrize("path", [1, 2])
+def test_variant_forced_path(binding, path, Q, beta, K):
+    inst = W.plain_normal(81 + Q, 120, 64 * 6 + 21, Q)
+    tour, dist, dem = _one(inst)
+    binding.set_variant_path(path)
+    try:
+        _check(binding, tour, dist, dem, Q, beta, K, "path %d" % path)
+        if Q == 60:
+            tour, dist, dem = _path_mixed()
+            _check(binding, tour, dist, dem, 45, beta, K, "path %d mixed" % path)
+    finally:
+        binding.set_variant_path(0)
+
+
+@pytest.mark.parametrize("path", [1, 2])
+def test_variant_forced_path_long_tour_and_n1(binding, path):
+    inst = W.plain_normal(83, 600, 64 * 2 + 5, 150)
+    tour, dist, dem = _one(inst)
+    rng = np.random.default_rng(84)
+    d9 = W.dist_round(W.coords(rng, 9))
+    q9 = rng.integers(0, 6, size=(130, 9)).astype(np.int16)
+    binding.set_variant_path(path)
+    try:
+        for beta, K in ((-1, 0), (4, 0), (-1, 30), (4, 7)):
+            _check(binding, tour, dist, dem, 150, beta, K, "path %d n=600" % path)
+            _check(binding, np.array([4], np.int32), d9, q9, 3, beta, K, "path %d n=1" % path)
+    finally:
+        binding.set_variant_path(0)
+
+
+def test_variant_ordered_path_invalid_demand(binding):
+    rng = np.random.default_rng(85)
+    N = n = 300
+    dist = W.dist_round(W.coords(rng, N))
+    tour = (rng.permutation(N) + 1).astype(np.int32)
+    dem = rng.integers(1, 10, size=(200, N)).astype(np.int16)
+    dem[120, tour[5] - 1] = -2
+    binding.set_variant_path(2)
+    try:
+        got, status = _gpu(binding, tour, dist, dem, 30, 4, 3)
+        assert status & binding.VARIANT_BAD_DEMAND and (got == INF32).all()
+        dem[120, tour[5] - 1] = 2
+        _check(binding, tour, dist, dem, 30, 4, 3, "ordered, valid after invalid")
+    finally:
+        binding.set_variant_path(0)
+
+
+# ----------------------------------------------------------------------------
 # degenerate cases and validation
 # ----------------------------------------------------------------------------
 def test_variant_empty_and_single(binding):
