@@ -381,8 +381,8 @@ def served(torch, binding, W, num_requests, pool_size, budget_gb, seed=5):
     out = {"workload": "%d requests from %d resident instances: n~U{50..1000}, S~10^U(3,5), "
                        "Q in {80,150,300}, Normal(mu,0.3mu) demands" % (num_requests, len(pool)),
            "budget_gb": budget_gb, "streams": 4, "saturated": sat}
-    for frac in (0.5, 0.8):
-        out["load_%.1f" % frac] = run(frac * sat["req_per_s"])
+    for frac in (0.5, 0.8, 0.95):
+        out["load_%g" % frac] = run(frac * sat["req_per_s"])
     out["peak_bytes"] = srv.stats()["peak_bytes"]
     srv.close()
     return out
