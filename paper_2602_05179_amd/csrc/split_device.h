@@ -152,6 +152,8 @@ struct LdsRow {
         q2 = row[t1.x];
     }
     template <int U> __device__ __forceinline__ int ahead(int2 t) const { return row[t.x]; }
+    // demand of position j (random access, outside the recursion)
+    __device__ __forceinline__ int at(CInt *tab, int j) const { return row[tab_at(tab, j).x]; }
 };
 
 // the lane's row of the tour-ordered copy in global memory (byte j - 1 =
@@ -193,6 +195,11 @@ struct StreamRow {
             }
         }
         return v;
+    }
+    // demand of position j (random access, outside the recursion)
+    __device__ __forceinline__ int at(CInt *, int j) const
+    {
+        return reinterpret_cast<const uint8_t *>(row)[j - 1];
     }
 };
 

@@ -130,7 +130,7 @@ template <int R, int F, int E, int U> struct RtState {
         r.t0 = r.t1;
         r.t1 = r.t2;
         r.t2 = t3;
-        r.prow[lane] = m < kFeasible ? (uint16_t)(j - a) : kNoPred;
+        r.prow[lane] = (uint16_t)(j - a); // +inf positions are marked after the pass
         r.prow += S;
         return true;
     }
@@ -227,7 +227,7 @@ template <int R, int F, int G, int E, int U> struct RkState {
         r.t0 = r.t1;
         r.t1 = r.t2;
         r.t2 = t3;
-        r.prow[lane] = km < kFeasible ? (uint16_t)(r.base + (km & M)) : kNoPred;
+        r.prow[lane] = (uint16_t)(r.base + (km & M)); // +inf positions: marked after the pass
         r.prow += S;
         return true;
     }
@@ -317,17 +317,30 @@ __device__ __forceinline__ int backtrack_tile(const uint16_t *pcol, uint16_t *cc
 }
 
 // V(n) of the lane's scenario (kInf if +inf) with pred(1..n) written, by
-// packed keys (KEYS) or the per-cell argmin
+// packed keys (KEYS) or the per-cell argmin.  The recursion stores every
+// position's predecessor without testing it; V(j) is +inf exactly from the
+// first position whose demand alone exceeds Q (its window is empty, and
+// every later window lies past it), so a scenario with V(n) = +inf gets
+// SPLIT_NO_PRED from that position on here, off the per-position path.
 template <bool KEYS, int R, int F, int G, int E, class Src>
 __device__ __forceinline__ int route_lane(Src &src, CInt *tab, const TourRec &rec, int Q,
                                           uint16_t *prow0, int64_t S, int lane, bool &ovf)
 {
+    int v;
     if constexpr (KEYS) {
-        return rk_lane<R, F, G, E>(src, tab, rec, Q, prow0, S, lane, ovf);
+        v = rk_lane<R, F, G, E>(src, tab, rec, Q, prow0, S, lane, ovf);
     } else {
         const int m = rt_lane<R, F, E>(src, tab, rec.n, rec.f0, Q, prow0, S, lane, ovf);
-        return m < kFeasible ? m + rec.bn : kInf;
+        v = m < kFeasible ? m + rec.bn : kInf;
     }
+    if (v >= kInf) {
+        int j = 1;
+        while (j <= rec.n && src.at(tab, j) <= Q)
+            ++j;
+        for (; j <= rec.n; ++j)
+            prow0[(int64_t)(j - 1) * S + lane] = kNoPred;
+    }
+    return v;
 }
 
 // Tile body shared by the key and the wide kernel: stage the tile (or, ORD,
