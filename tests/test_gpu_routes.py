@@ -266,6 +266,15 @@ def test_routes_forced_path(binding, path, case):
         binding.set_route_path(0)
 
 
+def test_routes_ordered_path_many_tiles(binding):
+    """n = N = 1000 takes the tour-ordered path by itself: 500 tiles plus a
+    ragged one, every scenario's costs, predecessors and cuts checked."""
+    inst = W.plain_normal(67, 1000, 64 * 500 + 17, 150)
+    tour, dist, dem = _inst_arrays(inst)
+    assert binding.routes_workspace_bytes(1000, 1000, dem.shape[0]) >= dem.shape[0] * 1056
+    _check(binding, tour, dist, dem, inst.Q, "ordered path n=1000 S=32017")
+
+
 def test_routes_ordered_path_invalid_inputs(binding):
     rng = np.random.default_rng(66)
     N = n = 300

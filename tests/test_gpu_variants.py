@@ -198,6 +198,15 @@ def test_variant_forced_path_long_tour_and_n1(binding, path):
         binding.set_variant_path(0)
 
 
+@pytest.mark.parametrize("beta,K", [(-1, 0), (6, 0), (-1, 25), (6, 12)])
+def test_variant_ordered_path_many_tiles(binding, beta, K):
+    """n = N = 1000 takes the tour-ordered path by itself (120 tiles plus a
+    ragged one), every scenario against the oracle."""
+    inst = W.plain_normal(86, 1000, 64 * 120 + 9, 150)
+    tour, dist, dem = _one(inst)
+    _check(binding, tour, dist, dem, inst.Q, beta, K, "ordered path n=1000")
+
+
 def test_variant_ordered_path_invalid_demand(binding):
     rng = np.random.default_rng(85)
     N = n = 300
