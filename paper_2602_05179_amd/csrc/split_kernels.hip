@@ -259,7 +259,9 @@ struct DpRegs {
     int ovf;      // 1 when a window reached past the ring
 };
 
-template <int R, int F, int G, int E, int U> struct DpState {
+// CHK: the block may run past position n (the tour's last block); a full
+// block skips the per-position bound test
+template <int R, int F, int G, int E, int U, bool CHK> struct DpState {
     __device__ __forceinline__ static bool run(int (&f)[R], int (&lq)[R], DpRegs &r,
                                                const uint8_t *row, CInt *tab, int j0, int n,
                                                int Q)
@@ -267,7 +269,7 @@ template <int R, int F, int G, int E, int U> struct DpState {
         const int j = j0 + U;
         if (U == 0 && j == 0)
             return true;
-        if (j > n)
+        if (CHK && j > n)
             return false;
         const int cj = r.t0.y;
         const int Ln = r.L + r.qa;
@@ -289,12 +291,12 @@ template <int R, int F, int G, int E, int U> struct DpState {
     }
 };
 
-template <int R, int F, int G, int E, int... Us>
+template <int R, int F, int G, int E, bool CHK, int... Us>
 __device__ __forceinline__ bool dp_block(int (&f)[R], int (&lq)[R], DpRegs &r, const uint8_t *row,
                                          CInt *tab, int j0, int n, int Q,
                                          std::integer_sequence<int, Us...>)
 {
-    return (DpState<R, F, G, E, Us>::run(f, lq, r, row, tab, j0, n, Q) && ...);
+    return (DpState<R, F, G, E, Us, CHK>::run(f, lq, r, row, tab, j0, n, Q) && ...);
 }
 
 // Returns m_n of the lane's scenario; sets ovf when a window left the ring.
@@ -320,11 +322,13 @@ __device__ __forceinline__ int dp_lane(const uint8_t *row, CInt *tab, int n, int
     r.t2 = tab_at(tab, 3);
     r.L = row[r.t0.x];
     r.qa = row[r.t1.x];
-    for (int j0 = 0; j0 <= n; j0 += R) {
-        if (!dp_block<R, F, G, E>(f, lq, r, row, tab, j0, n, Q,
-                                  std::make_integer_sequence<int, R>{}))
-            break;
-    }
+    int j0 = 0;
+    for (; j0 + R - 1 <= n; j0 += R) // blocks whose positions all exist
+        dp_block<R, F, G, E, false>(f, lq, r, row, tab, j0, n, Q,
+                                    std::make_integer_sequence<int, R>{});
+    if (j0 <= n) // the last, partial block
+        dp_block<R, F, G, E, true>(f, lq, r, row, tab, j0, n, Q,
+                                   std::make_integer_sequence<int, R>{});
     ovf = r.ovf != 0;
     return r.mres;
 }
@@ -487,7 +491,7 @@ __device__ __forceinline__ int byte_at(const u32x4 (&seg)[2], int b)
 }
 
 // position j = j0 + 1 + U of a block of R positions (j0 a multiple of R)
-template <int R, int F, int G, int E, int U> struct DpStateO {
+template <int R, int F, int G, int E, int U, bool CHK> struct DpStateO {
     __device__ __forceinline__ static bool run(int (&f)[R], int (&lq)[R], DpRegsO &r,
                                                const u32x4 *row, int64_t segs, CInt *tab,
                                                int j0, int n, int Q)
@@ -495,7 +499,7 @@ template <int R, int F, int G, int E, int U> struct DpStateO {
         constexpr int SL = (U + 1) & (R - 1);
         constexpr int B = U & 31; // byte of position j in the current segment
         const int j = j0 + 1 + U;
-        if (j > n)
+        if (CHK && j > n)
             return false;
         const int qn = B == 31 ? byte_at(r.nxt, 0) : byte_at(r.cur, B + 1);
         const int cj = r.t0.y;
@@ -524,12 +528,12 @@ template <int R, int F, int G, int E, int U> struct DpStateO {
     }
 };
 
-template <int R, int F, int G, int E, int... Us>
+template <int R, int F, int G, int E, bool CHK, int... Us>
 __device__ __forceinline__ bool dp_block_o(int (&f)[R], int (&lq)[R], DpRegsO &r, const u32x4 *row,
                                            int64_t segs, CInt *tab, int j0, int n, int Q,
                                            std::integer_sequence<int, Us...>)
 {
-    return (DpStateO<R, F, G, E, Us>::run(f, lq, r, row, segs, tab, j0, n, Q) && ...);
+    return (DpStateO<R, F, G, E, Us, CHK>::run(f, lq, r, row, segs, tab, j0, n, Q) && ...);
 }
 
 template <int R, int F, int G, int E>
@@ -563,11 +567,13 @@ __device__ __forceinline__ int dp_lane_ordered(const uint8_t *rowb, int pitch, C
         r.nxt[1] = r.cur[1];
     }
     r.L = byte_at(r.cur, 0);
-    for (int j0 = 0; j0 < n; j0 += R) {
-        if (!dp_block_o<R, F, G, E>(f, lq, r, row, segs, tab, j0, n, Q,
-                                    std::make_integer_sequence<int, R>{}))
-            break;
-    }
+    int j0 = 0;
+    for (; j0 + R <= n; j0 += R) // blocks whose positions all exist
+        dp_block_o<R, F, G, E, false>(f, lq, r, row, segs, tab, j0, n, Q,
+                                      std::make_integer_sequence<int, R>{});
+    if (j0 < n) // the last, partial block
+        dp_block_o<R, F, G, E, true>(f, lq, r, row, segs, tab, j0, n, Q,
+                                     std::make_integer_sequence<int, R>{});
     ovf = r.ovf != 0;
     return r.mres;
 }

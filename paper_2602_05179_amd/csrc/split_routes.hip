@@ -103,7 +103,7 @@ struct RtRegs {
     uint16_t *prow; // pred row of position j (wave-uniform), advanced by S
 };
 
-template <int R, int F, int E, int U> struct RtState {
+template <int R, int F, int E, int U, bool CHK> struct RtState {
     template <class Src>
     __device__ __forceinline__ static bool run(int (&f)[R], int (&lq)[R], RtRegs &r, Src &src,
                                                CInt *tab, int j0, int n, int Q, int64_t S,
@@ -112,7 +112,7 @@ template <int R, int F, int E, int U> struct RtState {
         const int j = j0 + U;
         if (U == 0 && j == 0)
             return true;
-        if (j > n)
+        if (CHK && j > n)
             return false;
         const int cj = r.t0.y;
         const int Ln = r.L + r.qa;
@@ -136,12 +136,12 @@ template <int R, int F, int E, int U> struct RtState {
     }
 };
 
-template <int R, int F, int E, class Src, int... Us>
+template <int R, int F, int E, bool CHK, class Src, int... Us>
 __device__ __forceinline__ bool rt_block(int (&f)[R], int (&lq)[R], RtRegs &r, Src &src,
                                          CInt *tab, int j0, int n, int Q, int64_t S, int lane,
                                          std::integer_sequence<int, Us...>)
 {
-    return (RtState<R, F, E, Us>::run(f, lq, r, src, tab, j0, n, Q, S, lane) && ...);
+    return (RtState<R, F, E, Us, CHK>::run(f, lq, r, src, tab, j0, n, Q, S, lane) && ...);
 }
 
 // Writes pred(1..n) of the lane's scenario; returns m_n, sets ovf when a
@@ -167,11 +167,13 @@ __device__ __forceinline__ int rt_lane(Src &src, CInt *tab, int n, int f0, int Q
     r.t2 = tab_at(tab, 3);
     src.init(r.t0, r.t1, r.L, r.qa);
     r.prow = prow0;
-    for (int j0 = 0; j0 <= n; j0 += R) {
-        if (!rt_block<R, F, E>(f, lq, r, src, tab, j0, n, Q, S, lane,
-                               std::make_integer_sequence<int, R>{}))
-            break;
-    }
+    int j0 = 0;
+    for (; j0 + R - 1 <= n; j0 += R) // blocks whose positions all exist
+        rt_block<R, F, E, false>(f, lq, r, src, tab, j0, n, Q, S, lane,
+                                 std::make_integer_sequence<int, R>{});
+    if (j0 <= n) // the last, partial block
+        rt_block<R, F, E, true>(f, lq, r, src, tab, j0, n, Q, S, lane,
+                                std::make_integer_sequence<int, R>{});
     ovf = r.ovf != 0;
     return r.mres;
 }
@@ -191,7 +193,7 @@ struct RkRegs {
     uint16_t *prow;  // pred row of position j (wave-uniform), advanced by S
 };
 
-template <int R, int F, int G, int E, int U> struct RkState {
+template <int R, int F, int G, int E, int U, bool CHK> struct RkState {
     template <class Src>
     __device__ __forceinline__ static bool run(int (&K)[R], int (&lq)[R], RkRegs &r, Src &src,
                                                CInt *tab, int j0, int n, int Q, int64_t S,
@@ -200,7 +202,7 @@ template <int R, int F, int G, int E, int U> struct RkState {
         constexpr int B = key_shift<R>();
         constexpr int M = (1 << B) - 1;
         const int j = j0 + U;
-        if (j > n)
+        if (CHK && j > n)
             return false;
         if (U == 0) {
             if (j == 0)
@@ -233,12 +235,12 @@ template <int R, int F, int G, int E, int U> struct RkState {
     }
 };
 
-template <int R, int F, int G, int E, class Src, int... Us>
+template <int R, int F, int G, int E, bool CHK, class Src, int... Us>
 __device__ __forceinline__ bool rk_block(int (&K)[R], int (&lq)[R], RkRegs &r, Src &src,
                                          CInt *tab, int j0, int n, int Q, int64_t S, int lane,
                                          std::integer_sequence<int, Us...>)
 {
-    return (RkState<R, F, G, E, Us>::run(K, lq, r, src, tab, j0, n, Q, S, lane) && ...);
+    return (RkState<R, F, G, E, Us, CHK>::run(K, lq, r, src, tab, j0, n, Q, S, lane) && ...);
 }
 
 // Writes pred(1..n) of the lane's scenario; returns V(n) (kInf if +inf),
@@ -268,11 +270,13 @@ __device__ __forceinline__ int rk_lane(Src &src, CInt *tab, const TourRec &rec, 
     src.init(r.t0, r.t1, r.L, r.qa);
     r.prow = prow0;
     const int n = rec.n;
-    for (int j0 = 0; j0 <= n; j0 += R) {
-        if (!rk_block<R, F, G, E>(K, lq, r, src, tab, j0, n, Q, S, lane,
-                                  std::make_integer_sequence<int, R>{}))
-            break;
-    }
+    int j0 = 0;
+    for (; j0 + R - 1 <= n; j0 += R) // blocks whose positions all exist
+        rk_block<R, F, G, E, false>(K, lq, r, src, tab, j0, n, Q, S, lane,
+                                    std::make_integer_sequence<int, R>{});
+    if (j0 <= n) // the last, partial block
+        rk_block<R, F, G, E, true>(K, lq, r, src, tab, j0, n, Q, S, lane,
+                                   std::make_integer_sequence<int, R>{});
     ovf = r.ovf != 0;
     return r.mres < kFeasible ? (r.mres >> B) + rec.bn : kInf;
 }

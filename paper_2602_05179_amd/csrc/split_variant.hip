@@ -106,7 +106,7 @@ struct VarRegs {
 // One position j = j0 + U.  LAYERED: the ring holds the previous pass's
 // potentials and this pass's are written out; otherwise the ring holds the
 // pass's own potentials (unlimited fleet).
-template <int R, bool SOFT, bool LAYERED, int U> struct VarState {
+template <int R, bool SOFT, bool LAYERED, int U, bool CHK> struct VarState {
     template <class Src>
     __device__ __forceinline__ static bool run(int (&f)[R], int (&lq)[R], VarRegs &r, Src &src,
                                                CInt *tab, int j0, int n, int Q, int beta,
@@ -115,7 +115,7 @@ template <int R, bool SOFT, bool LAYERED, int U> struct VarState {
         const int j = j0 + U;
         if (U == 0 && j == 0)
             return true;
-        if (j > n)
+        if (CHK && j > n)
             return false;
         const int cj = r.t0.y;
         const int Ln = r.L + r.qa;
@@ -180,12 +180,12 @@ template <int R, bool SOFT, bool LAYERED, int U> struct VarState {
     }
 };
 
-template <int R, bool SOFT, bool LAYERED, class Src, int... Us>
+template <int R, bool SOFT, bool LAYERED, bool CHK, class Src, int... Us>
 __device__ __forceinline__ bool var_block(int (&f)[R], int (&lq)[R], VarRegs &r, Src &src,
                                           CInt *tab, int j0, int n, int Q, int beta, bool has_src,
                                           int64_t S, std::integer_sequence<int, Us...>)
 {
-    return (VarState<R, SOFT, LAYERED, Us>::run(f, lq, r, src, tab, j0, n, Q, beta, has_src, S) &&
+    return (VarState<R, SOFT, LAYERED, Us, CHK>::run(f, lq, r, src, tab, j0, n, Q, beta, has_src, S) &&
             ...);
 }
 
@@ -235,11 +235,13 @@ __device__ __forceinline__ int var_pass(Src dsrc, CInt *tab, const TourRec &rec,
         }
         r.dstp = dst + S; // row j at position j = 1
     }
-    for (int j0 = 0; j0 <= n; j0 += R) {
-        if (!var_block<R, SOFT, LAYERED>(f, lq, r, dsrc, tab, j0, n, Q, beta, has_src, S,
-                                         std::make_integer_sequence<int, R>{}))
-            break;
-    }
+    int j0 = 0;
+    for (; j0 + R - 1 <= n; j0 += R) // blocks whose positions all exist
+        var_block<R, SOFT, LAYERED, false>(f, lq, r, dsrc, tab, j0, n, Q, beta, has_src, S,
+                                           std::make_integer_sequence<int, R>{});
+    if (j0 <= n) // the last, partial block
+        var_block<R, SOFT, LAYERED, true>(f, lq, r, dsrc, tab, j0, n, Q, beta, has_src, S,
+                                          std::make_integer_sequence<int, R>{});
     ovf = r.ovf != 0;
     Ltot = r.lastL;
     return r.mres;
@@ -268,7 +270,7 @@ template <int NL> struct VarMultiRegs {
     int *dstp;
 };
 
-template <int R, int NL, bool SOFT, int U> struct VarMultiState {
+template <int R, int NL, bool SOFT, int U, bool CHK> struct VarMultiState {
     template <class Src>
     __device__ __forceinline__ static bool run(int (&f)[NL][R], int (&lq)[R], VarMultiRegs<NL> &r,
                                                Src &src, CInt *tab, int j0, int n, int Q, int beta,
@@ -277,7 +279,7 @@ template <int R, int NL, bool SOFT, int U> struct VarMultiState {
         const int j = j0 + U;
         if (U == 0 && j == 0)
             return true;
-        if (j > n)
+        if (CHK && j > n)
             return false;
         const int cj = r.t0.y;
         const int Ln = r.L + r.qa;
@@ -345,13 +347,13 @@ template <int R, int NL, bool SOFT, int U> struct VarMultiState {
     }
 };
 
-template <int R, int NL, bool SOFT, class Src, int... Us>
+template <int R, int NL, bool SOFT, bool CHK, class Src, int... Us>
 __device__ __forceinline__ bool var_multi_block(int (&f)[NL][R], int (&lq)[R],
                                                 VarMultiRegs<NL> &r, Src &src, CInt *tab, int j0,
                                                 int n, int Q, int beta, bool has_src, int64_t S,
                                                 std::integer_sequence<int, Us...>)
 {
-    return (VarMultiState<R, NL, SOFT, Us>::run(f, lq, r, src, tab, j0, n, Q, beta, has_src, S) &&
+    return (VarMultiState<R, NL, SOFT, Us, CHK>::run(f, lq, r, src, tab, j0, n, Q, beta, has_src, S) &&
             ...);
 }
 
@@ -402,9 +404,12 @@ __device__ __forceinline__ void var_sweep(Src dsrc, CInt *tab, const TourRec &re
         r.srcp = src + 3 * S;
     }
     r.dstp = dst + S;
+    // one unrolled copy, bound test at every position: a second (untested)
+    // copy of this large block measured slower (three hard rings at n = 200,
+    // S = 10^6, K = 25: 5.11 ms vs 4.75 ms)
     for (int j0 = 0; j0 <= n; j0 += R) {
-        if (!var_multi_block<R, NL, SOFT>(f, lq, r, dsrc, tab, j0, n, Q, beta, has_src, S,
-                                          std::make_integer_sequence<int, R>{}))
+        if (!var_multi_block<R, NL, SOFT, true>(f, lq, r, dsrc, tab, j0, n, Q, beta, has_src,
+                                                S, std::make_integer_sequence<int, R>{}))
             break;
     }
     ovf = r.ovf != 0;
