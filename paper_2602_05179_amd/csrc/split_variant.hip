@@ -138,8 +138,10 @@ template <int R, bool SOFT, bool LAYERED, int U, bool CHK> struct VarState {
 #pragma unroll
             for (int d = 1; d <= R; ++d) {
                 const int fd = f[(U - d) & (R - 1)];
-                const int t = max(L - lq[(U - d) & (R - 1)], 0);
-                m = min(m, fd + (int)__umul24((unsigned)beta, (unsigned)t));
+                // max(L - lq, 0) as one clamped unsigned subtract (L, lq >= 0)
+                const unsigned t =
+                    __builtin_elementwise_sub_sat((unsigned)L, (unsigned)lq[(U - d) & (R - 1)]);
+                m = min(m, fd + (int)__umul24((unsigned)beta, t));
             }
             m = min(m, r.mret + (int)__umul24((unsigned)beta, (unsigned)L));
             // the cell leaving the ring (p = j - R) sits in slot U
@@ -302,8 +304,9 @@ template <int R, int NL, bool SOFT, int U, bool CHK> struct VarMultiState {
                 m[g] = r.mret[g] + (int)__umul24((unsigned)beta, (unsigned)L);
 #pragma unroll
             for (int d = 1; d <= R; ++d) {
-                const int pen = (int)__umul24((unsigned)beta,
-                                              (unsigned)max(L - lq[(U - d) & (R - 1)], 0));
+                const int pen = (int)__umul24(
+                    (unsigned)beta,
+                    __builtin_elementwise_sub_sat((unsigned)L, (unsigned)lq[(U - d) & (R - 1)]));
 #pragma unroll
                 for (int g = 0; g < NL; ++g)
                     m[g] = min(m[g], f[g][(U - d) & (R - 1)] + pen);
