@@ -34,8 +34,6 @@ def _load():
         lib.oracle_split_eval.argtypes = [P, P, i32, P, i32, P, i64, i32, P, P, P, P, ctypes.c_int,
                                           ctypes.c_int]
         lib.oracle_split_eval.restype = ctypes.c_int
-        lib.oracle_split_sample.argtypes = [P, i32, P, i32, P, i64, i32, P, i64, P, P]
-        lib.oracle_split_sample.restype = ctypes.c_int
         lib.oracle_split_values.argtypes = [P, i32, P, i32, P, i64, ctypes.c_int, P, P]
         lib.oracle_split_values.restype = ctypes.c_int
         lib.oracle_split_routes.argtypes = [P, i32, P, i32, P, i64, i32, P, P, P, P, ctypes.c_int]
@@ -80,23 +78,6 @@ def split_eval(tours, lens, dist, demands, Q, *, use_break=True, nthreads=1):
     if rc != 0:
         raise OracleError("oracle_split_eval returned %d" % rc)
     return dict(costs=costs, sums=sums, means=means, cells=cells)
-
-
-def split_sample(tour, dist, demands, Q, idx):
-    """Costs (and feasible-cell counts) of scenarios `idx` of one tour."""
-    lib = _load()
-    tour = np.ascontiguousarray(tour, np.int32)
-    dist = np.ascontiguousarray(dist, np.int32)
-    demands = np.ascontiguousarray(demands, np.int16)
-    idx = np.ascontiguousarray(idx, np.int64)
-    out = np.empty(idx.size, np.int32)
-    cells = np.empty(idx.size, np.int64)
-    rc = lib.oracle_split_sample(_p(tour), int(tour.size), _p(dist), int(dist.shape[0] - 1),
-                                 _p(demands), int(demands.shape[0]), int(Q), _p(idx), int(idx.size),
-                                 _p(out), _p(cells))
-    if rc != 0:
-        raise OracleError("oracle_split_sample returned %d" % rc)
-    return out, cells
 
 
 def split_values(tour, dist, qvis, Q, *, use_break=True):
@@ -167,6 +148,6 @@ def split_variant(tour, dist, demands, Q, *, beta=-1, K=0, nthreads=1):
     return costs
 
 
-__all__ = ["split_eval", "split_sample", "split_values", "split_routes", "split_variant", "brute", "build_oracle",
+__all__ = ["split_eval", "split_values", "split_routes", "split_variant", "brute", "build_oracle",
            "LIB",
            "INF32", "INF64", "NO_PRED", "OracleError"]

@@ -136,24 +136,36 @@ def ou_transitions(U, demand, opt_cost, opt_cap, h, u, rho):
 
 
 def ou_brute(U, I0, demand, opt_cost, opt_cap, h, u, rho):
-    """Cheapest total over all delivery decisions (deliver or not, each day)
-    for every batch element, by enumeration of the 2^T decision sequences."""
+    """Cheapest total over all delivery decisions for every batch element, by
+    enumeration: each day either no delivery or a delivery up to U on one
+    chosen route option r (admissible when its residual capacity holds the
+    delivery).  The route option is part of the enumerated decision, so the
+    minimum over options is reached by enumeration instead of through
+    `ou_transport`, and the unmet demand is written as demand minus what the
+    stock on hand serves."""
     demand = np.asarray(demand)
     T, B = demand.shape
+    R = np.asarray(opt_cost).shape[2]
     out = np.full(B, INF, np.int64)
     for b in range(B):
-        for dec in itertools.product((0, 1), repeat=T):
-            I, total, ok = int(I0[b]), 0, True
+        # a decision per day: -1 = no delivery, r >= 0 = deliver on option r
+        for dec in itertools.product(range(-1, R), repeat=T):
+            stock, total, ok = int(I0[b]), 0, True
             for t in range(T):
                 d = int(demand[t, b])
-                q = U - I if dec[t] else 0
-                tr = ou_transport(q, opt_cost[t, b], opt_cap[t, b], u)
-                if tr >= INF:
-                    ok = False
-                    break
-                J = max(0, I + q - d)
-                total += tr + int(h[J]) + rho * max(0, d - I - q)
-                I = J
+                r = dec[t]
+                if r < 0:
+                    q = 0
+                else:
+                    q = U - stock
+                    if q == 0 or int(opt_cap[t, b, r]) < q:
+                        ok = False  # a delivery of nothing, or one the route cannot carry
+                        break
+                    total += int(opt_cost[t, b, r]) + u * q
+                on_hand = stock + q
+                served = min(on_hand, d)
+                stock = on_hand - served
+                total += int(h[stock]) + rho * (d - served)
             if ok:
                 out[b] = min(out[b], total)
     return np.where(out >= INF, INF, out)

@@ -217,46 +217,6 @@ int oracle_split_eval(const int32_t *tours, const int32_t *lens, int32_t num_tou
 }
 
 /*
- * Costs of selected scenarios of one tour (for spot checks at sizes where
- * evaluating every scenario would take too long).  idx[k] in [0, S).
- */
-int oracle_split_sample(const int32_t *tour, int32_t n, const int32_t *dist, int32_t N,
-                        const int16_t *demands, int64_t S, int32_t Q, const int64_t *idx, int64_t k,
-                        int32_t *costs_out, int64_t *cells_out)
-{
-    int32_t lens = n;
-    if (check_args(tour, &lens, 1, dist, N, demands, S, Q) != 0)
-        return -1;
-    int64_t *V = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
-    int64_t *q = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
-    if (!V || !q) {
-        free(V);
-        free(q);
-        return -2;
-    }
-    for (int64_t r = 0; r < k; ++r) {
-        const int64_t s = idx[r];
-        if (s < 0 || s >= S) {
-            free(V);
-            free(q);
-            return -1;
-        }
-        const int16_t *row = demands + s * (int64_t)N;
-        q[0] = 0;
-        for (int32_t m = 1; m <= n; ++m)
-            q[m] = row[tour[m - 1] - 1];
-        int64_t c = 0;
-        const int64_t v = split_one(tour, n, dist, N + 1, q, Q, 1, V, &c);
-        costs_out[r] = v == OR_INF ? INT32_MAX : (int32_t)v;
-        if (cells_out)
-            cells_out[r] = c;
-    }
-    free(V);
-    free(q);
-    return 0;
-}
-
-/*
  * Full value vector J(0..n) of one scenario given demands in visiting
  * order (qvis[k-1] = demand of sigma_k).  Entries with no split are
  * INT64_MAX.  Used by the pin tests on tiny worked examples.

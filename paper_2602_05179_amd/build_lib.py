@@ -14,12 +14,12 @@ SOURCES = [os.path.join(CSRC, "split_kernels.hip"), os.path.join(CSRC, "split_ap
            os.path.join(CSRC, "split_server.cpp"), os.path.join(CSRC, "split_tune.cpp"),
            os.path.join(CSRC, "split_probe.hip"), os.path.join(CSRC, "split_routes.hip"),
            os.path.join(CSRC, "split_variant.hip"), os.path.join(CSRC, "split_minplus.hip"),
-           os.path.join(CSRC, "split_search.cpp")]
+           os.path.join(CSRC, "split_search.cpp"), os.path.join(CSRC, "split_check.cpp")]
 HEADERS = [os.path.join(INCLUDE, "split_eval.h"), os.path.join(CSRC, "split_internal.h"),
            os.path.join(CSRC, "split_device.h"), os.path.join(CSRC, "window_min_asm.inc"),
            os.path.join(CSRC, "window_argmin_asm.inc"), os.path.join(CSRC, "split_variant.h"),
            os.path.join(CSRC, "split_minplus.h"),
-           os.path.join(CSRC, "window_min_multi_asm.inc")]
+           os.path.join(CSRC, "window_min_multi_asm.inc"), os.path.join(CSRC, "split_check.h")]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are disabled for every GPU object this library

@@ -12,6 +12,7 @@
 #include <string.h>
 #include <vector>
 
+#include "split_check.h"
 #include "split_eval.h"
 #include "split_internal.h"
 #include "split_minplus.h"
@@ -19,35 +20,14 @@
 
 namespace {
 
-thread_local char g_err[512] = "";
-
 int fail(int code, const char *fmt, ...)
 {
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    splitk::vset_error(code, fmt, ap);
     va_end(ap);
     return code;
 }
-
-} // namespace
-
-namespace splitk {
-
-int set_error(int code, const char *fmt, ...)
-{
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(g_err, sizeof(g_err), fmt, ap);
-    va_end(ap);
-    return code;
-}
-
-void clear_error() { g_err[0] = 0; }
-
-} // namespace splitk
-
-namespace {
 
 int hip_fail(hipError_t e, const char *what)
 {
@@ -63,68 +43,8 @@ int hip_fail(hipError_t e, const char *what)
             return hip_fail(e_, what);                                                           \
     } while (0)
 
-// Checks that need only scalars (shared by every form).
-int check_scalars(int32_t num_tours, int32_t N, int64_t S, int32_t Q, int32_t max_len)
-{
-    if (num_tours < 1)
-        return fail(SPLIT_EINVAL, "num_tours must be >= 1 (got %d)", num_tours);
-    if (N < 1)
-        return fail(SPLIT_EINVAL, "N must be >= 1 (got %d)", N);
-    if (S < 1)
-        return fail(SPLIT_EINVAL, "S must be >= 1 (got %lld)", (long long)S);
-    if (Q < 0)
-        return fail(SPLIT_EINVAL, "Q must be >= 0 (got %d)", Q);
-    if (max_len < 0 || max_len > splitk::kMaxLen)
-        return fail(SPLIT_EINVAL, "tour length must be in [0, %d] (got %d)", splitk::kMaxLen,
-                    max_len);
-    const int64_t tiles = splitk::num_tiles(S);
-    if ((int64_t)num_tours * tiles > (int64_t)INT32_MAX)
-        return fail(SPLIT_EINVAL, "num_tours * ceil(S/64) exceeds 2^31-1");
-    return SPLIT_OK;
-}
-
-// Host-side validation of tours and the cost legs they use (host form).
-int check_tours_host(const int32_t *tours, const int32_t *lens, int32_t T, const int32_t *dist,
-                     int32_t N, int32_t *max_len_out, int64_t *total_out)
-{
-    const int64_t N1 = (int64_t)N + 1;
-    int64_t off = 0;
-    int32_t max_len = 0;
-    for (int32_t t = 0; t < T; ++t) {
-        const int32_t n = lens[t];
-        if (n < 0 || n > splitk::kMaxLen)
-            return fail(SPLIT_EINVAL, "lens[%d] = %d outside [0, %d]", t, n, splitk::kMaxLen);
-        int64_t maxc = 0;
-        for (int32_t k = 0; k < n; ++k) {
-            const int32_t c = tours[off + k];
-            if (c < 1 || c > N)
-                return fail(SPLIT_EINVAL, "tour %d position %d: customer id %d outside [1, %d]", t,
-                            k + 1, c, N);
-            const int32_t legs[3] = {dist[c], dist[c * N1],
-                                     k + 1 < n ? dist[c * N1 + tours[off + k + 1]] : 0};
-            if (k + 1 < n && (tours[off + k + 1] < 1 || tours[off + k + 1] > N))
-                return fail(SPLIT_EINVAL, "tour %d position %d: customer id %d outside [1, %d]",
-                            t, k + 2, tours[off + k + 1], N);
-            for (int32_t v : legs) {
-                if (v < 0 || v > SPLIT_MAX_COST)
-                    return fail(SPLIT_EINVAL, "tour %d: travel cost %d outside [0, %d]", t, v,
-                                SPLIT_MAX_COST);
-                if (v > maxc)
-                    maxc = v;
-            }
-        }
-        if (3 * (int64_t)n * maxc >= (int64_t)1 << 29)
-            return fail(SPLIT_EINVAL,
-                        "tour %d: 3 * n * max cost = %lld >= 2^29 (int32 exactness guard)", t,
-                        (long long)(3 * (int64_t)n * maxc));
-        if (n > max_len)
-            max_len = n;
-        off += n;
-    }
-    *max_len_out = max_len;
-    *total_out = off;
-    return SPLIT_OK;
-}
+using splitk::check_scalars;
+using splitk::check_tours_host;
 
 // Device buffers of the synchronous host form, grown on demand.
 struct HostCtx {
@@ -219,12 +139,10 @@ Schedule choose_schedule(int32_t T, int32_t max_len, int32_t N, int64_t S, int32
 
 extern "C" {
 
-const char *split_last_error(void) { return g_err; }
-
 int split_set_schedule(int32_t ring, int32_t first, int32_t group, int32_t every, int32_t waves,
                        int32_t path)
 {
-    g_err[0] = 0;
+    splitk::clear_error();
     if (ring == 0) {
         g_override = splitk::Schedule{0, 0, 0, 0, 0, 0};
         return SPLIT_OK;
@@ -243,7 +161,7 @@ int split_set_schedule(int32_t ring, int32_t first, int32_t group, int32_t every
 
 int split_list_variants(int32_t *out, int32_t cap)
 {
-    g_err[0] = 0;
+    splitk::clear_error();
     if (cap < 0 || (cap > 0 && !out))
         return fail(SPLIT_EINVAL, "bad output buffer");
     splitk::Schedule v[64];
@@ -272,7 +190,7 @@ int split_eval_device(const int32_t *d_tours, const int32_t *d_lens, int32_t num
                       int64_t *d_sums, double *d_means, void *d_workspace, size_t ws_bytes,
                       split_stream_t stream)
 {
-    g_err[0] = 0;
+    splitk::clear_error();
     int rc = check_scalars(num_tours, N, S, Q, max_len);
     if (rc)
         return rc;
@@ -309,7 +227,7 @@ size_t split_routes_workspace_bytes(int32_t n, int32_t N, int64_t S)
 
 int split_routes_set_variant(int32_t ring, int32_t first, int32_t group, int32_t every)
 {
-    g_err[0] = 0;
+    splitk::clear_error();
     if (ring == 0) {
         splitk::set_route_override(splitk::RouteVariant{0, 0, 0, 0});
         return SPLIT_OK;
@@ -324,7 +242,7 @@ int split_routes_set_variant(int32_t ring, int32_t first, int32_t group, int32_t
 
 int split_routes_set_path(int32_t path)
 {
-    g_err[0] = 0;
+    splitk::clear_error();
     if (path < 0 || path > 2)
         return fail(SPLIT_EINVAL, "route path must be 0, 1 or 2 (got %d)", path);
     splitk::set_route_path(path);
@@ -333,7 +251,7 @@ int split_routes_set_path(int32_t path)
 
 int split_routes_list_variants(int32_t *out, int32_t cap)
 {
-    g_err[0] = 0;
+    splitk::clear_error();
     if (cap < 0 || (cap > 0 && !out))
         return fail(SPLIT_EINVAL, "bad output buffer");
     splitk::RouteVariant v[64];
@@ -352,7 +270,7 @@ int split_routes_device(const int32_t *d_tour, int32_t n, const int32_t *d_dist,
                         uint16_t *d_pred, uint16_t *d_cuts, int32_t *d_nroutes,
                         void *d_workspace, size_t ws_bytes, split_stream_t stream)
 {
-    g_err[0] = 0;
+    splitk::clear_error();
     int rc = check_scalars(1, N, S, Q, n);
     if (rc)
         return rc;
@@ -382,7 +300,7 @@ int split_routes_device(const int32_t *d_tour, int32_t n, const int32_t *d_dist,
 
 int split_variant_set_path(int32_t path)
 {
-    g_err[0] = 0;
+    splitk::clear_error();
     if (path < 0 || path > 2)
         return fail(SPLIT_EINVAL, "variant path must be 0, 1 or 2 (got %d)", path);
     splitk::set_variant_path(path);
@@ -401,7 +319,7 @@ int split_variant_device(const int32_t *d_tour, int32_t n, const int32_t *d_dist
                          int32_t *d_costs, int32_t *d_status, void *d_workspace, size_t ws_bytes,
                          split_stream_t stream)
 {
-    g_err[0] = 0;
+    splitk::clear_error();
     int rc = check_scalars(1, N, S, Q, n);
     if (rc)
         return rc;
@@ -428,7 +346,7 @@ int split_minplus_forward_device(const int32_t *d_A, int32_t shared, int32_t T, 
                                  int64_t B, const int32_t *d_J0, int32_t *d_JT, int32_t *d_arg,
                                  split_stream_t stream)
 {
-    g_err[0] = 0;
+    splitk::clear_error();
     if (T < 1 || m < 1 || m > splitk::kMinplusMaxStates || B < 1 || B > (int64_t)INT32_MAX)
         return fail(SPLIT_EINVAL, "need T >= 1, 1 <= m <= %d, 1 <= B < 2^31 (got T=%d m=%d B=%lld)",
                     splitk::kMinplusMaxStates, T, m, (long long)B);
@@ -445,7 +363,7 @@ int split_minplus_forward_device(const int32_t *d_A, int32_t shared, int32_t T, 
 int split_minplus_backtrack_device(const int32_t *d_JT, const int32_t *d_arg, int32_t T,
                                    int32_t m, int64_t B, int32_t *d_path, split_stream_t stream)
 {
-    g_err[0] = 0;
+    splitk::clear_error();
     if (T < 1 || m < 1 || m > splitk::kMinplusMaxStates || B < 1 || B > (int64_t)INT32_MAX)
         return fail(SPLIT_EINVAL, "need T >= 1, 1 <= m <= %d, 1 <= B < 2^31",
                     splitk::kMinplusMaxStates);
@@ -462,7 +380,7 @@ int split_ou_transitions_device(int32_t U, int32_t T, int64_t B, int32_t R,
                                 const int32_t *d_opt_cap, const int32_t *d_h, int32_t u,
                                 int32_t rho, int32_t *d_A, split_stream_t stream)
 {
-    g_err[0] = 0;
+    splitk::clear_error();
     if (U < 0 || U + 1 > splitk::kMinplusMaxStates || T < 1 || B < 1 || R < 1 || R > 64)
         return fail(SPLIT_EINVAL, "need 0 <= U < %d, T >= 1, B >= 1, 1 <= R <= 64",
                     splitk::kMinplusMaxStates);
@@ -478,7 +396,7 @@ int split_ou_transitions_device(int32_t U, int32_t T, int64_t B, int32_t R,
 
 int split_profile_enable(int32_t on)
 {
-    g_err[0] = 0;
+    splitk::clear_error();
     std::lock_guard<std::mutex> lock(g_prof.mu);
     g_prof.on = on != 0;
     return SPLIT_OK;
@@ -486,7 +404,7 @@ int split_profile_enable(int32_t on)
 
 int split_profile_read(double *kernel_ms, int64_t *launches)
 {
-    g_err[0] = 0;
+    splitk::clear_error();
     if (!kernel_ms || !launches)
         return fail(SPLIT_EINVAL, "null pointer argument");
     std::lock_guard<std::mutex> lock(g_prof.mu);
@@ -510,7 +428,7 @@ int split_eval(const int32_t *tours, const int32_t *lens, int32_t num_tours, con
                int32_t N, const int16_t *demands, int64_t S, int32_t Q, int32_t *costs,
                int64_t *sums, double *means)
 {
-    g_err[0] = 0;
+    splitk::clear_error();
     if (!tours || !lens || !dist || !demands || !costs)
         return fail(SPLIT_EINVAL, "null pointer argument");
     int rc = check_scalars(num_tours, N, S, Q, 0);
@@ -587,7 +505,7 @@ int split_count_cells_device(const int32_t *d_tours, const int32_t *d_lens, int3
                              int32_t N, const int16_t *d_demands, int64_t S, int32_t Q,
                              int64_t *d_cells, split_stream_t stream)
 {
-    g_err[0] = 0;
+    splitk::clear_error();
     int rc = check_scalars(num_tours, N, S, Q, 0);
     if (rc)
         return rc;
@@ -613,7 +531,7 @@ int split_plan_create(split_plan **plan, const int32_t *d_tours, const int32_t *
                       const int16_t *d_demands, int64_t S, int32_t Q, int32_t *d_costs,
                       int64_t *d_sums, double *d_means, split_stream_t stream)
 {
-    g_err[0] = 0;
+    splitk::clear_error();
     if (!plan)
         return fail(SPLIT_EINVAL, "null plan pointer");
     int rc = check_scalars(num_tours, N, S, Q, max_len);
@@ -665,7 +583,7 @@ int split_plan_create(split_plan **plan, const int32_t *d_tours, const int32_t *
 
 int split_plan_launch(split_plan *plan, split_stream_t stream)
 {
-    g_err[0] = 0;
+    splitk::clear_error();
     if (!plan || !plan->exec)
         return fail(SPLIT_EINVAL, "null plan");
     HIP_TRY(hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream)), "graph launch");
@@ -674,7 +592,7 @@ int split_plan_launch(split_plan *plan, split_stream_t stream)
 
 int split_plan_destroy(split_plan *plan)
 {
-    g_err[0] = 0;
+    splitk::clear_error();
     if (!plan)
         return SPLIT_OK;
     if (plan->exec)

@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "split_check.h"
+
 namespace splitk {
 
 // Per-tour constants produced by the prep kernel.
@@ -90,9 +92,6 @@ Schedule default_schedule(int32_t N, int64_t S, int32_t Q);
 Schedule choose_schedule(int32_t T, int32_t max_len, int32_t N, int64_t S, int32_t Q,
                          bool *ordered);
 
-// Thread-local error text returned by split_last_error().
-int set_error(int code, const char *fmt, ...);
-void clear_error();
 bool schedule_supported(const Schedule &s);
 
 hipError_t launch_count_mismatch(const int32_t *a, const int32_t *b, int64_t n, int64_t *out,

@@ -82,6 +82,9 @@ def _small():
     (lambda a: a.update(Q=-1), "Q must be"),
     (lambda a: a["tours"].__setitem__(0, 0), "outside [1"),
     (lambda a: a["tours"].__setitem__(3, 99), "outside [1"),
+    # a huge id at a middle position is rejected before it indexes the cost matrix
+    (lambda a: a["tours"].__setitem__(7, 1 << 30), "outside [1"),
+    (lambda a: a["tours"].__setitem__(11, -(1 << 30)), "outside [1"),
     (lambda a: a["dist"].__setitem__((0, a["tours"][0]), -5), "travel cost"),
     (lambda a: a["dist"].__setitem__((a["tours"][2], a["tours"][3]), 1 << 25), "travel cost"),
 ])

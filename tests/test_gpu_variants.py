@@ -89,14 +89,15 @@ def test_hard_unlimited_equals_the_evaluator(binding):
 
 
 def test_variant_paper_scale_sampled(binding):
-    """n=200, S=10^6, Q=150: soft capacity and a fleet bound on the full
-    scenario set, checked on 3000 sampled scenarios."""
+    """n=200, S=10^6, Q=150: soft capacity, a fleet bound, and both
+    together (the configurations the benchmark times) on the full scenario
+    set, checked on 3000 sampled scenarios."""
     inst = W.plain_paper_scale(3, S=1_000_000)
     tour, dist, dem = _one(inst)
     rng = np.random.default_rng(9)
     idx = np.sort(rng.choice(dem.shape[0], size=3000, replace=False))
     idx[-1] = dem.shape[0] - 1  # the ragged last tile
-    for beta, K in ((10, 0), (-1, 25)):
+    for beta, K in ((10, 0), (-1, 25), (10, 25)):
         _say("paper scale beta=%d K=%d" % (beta, K))
         got, status = _gpu(binding, tour, dist, dem, inst.Q, beta, K)
         assert status == 0

@@ -93,3 +93,73 @@ def test_inventory_forward_equals_decision_enumeration(seed):
     J0[np.arange(B), I0] = 0
     JT, _ = M.minplus_forward(A, J0, shared=False)
     assert (JT.min(axis=1) == M.ou_brute(U, I0, demand, cost, cap, h, u, rho)).all()
+
+
+def _golden_ou(golden_dir):
+    import json
+    import os
+    g = json.load(open(os.path.join(golden_dir, "ou_two_options_stockout.json")))
+    fix = lambda rows: np.array([[INF if v is None else v for v in r] for r in rows], np.int64)
+    return g, fix
+
+
+def test_two_option_stockout_golden(golden_dir):
+    """Three route options and stock-outs (App. B: A(I,J) = min_r A(I,J;r),
+    penalty per unit of unmet demand).  U = 3, h = (0, 2, 3, 9), u = 1,
+    rho = 5; options (cost, residual capacity) = (10, 2), (4, 1), (7, 3).
+
+    transport(q) = cheapest option that carries q, plus q:
+      q = 1: every option carries it, cheapest 4 -> 5;
+      q = 2: options 1 and 3 carry it, cheapest 7 -> 9;
+      q = 3: only option 3 carries it -> 10.
+    Day 1, demand 2 (row I, no delivery | deliver up to 3):
+      I = 0: stay -> J = 0, unmet 2: 0 + h0 + 10 = 10 | q = 3 -> J = 1: 10 + h1 = 12
+      I = 1: stay -> J = 0, unmet 1: 5               | q = 2 -> J = 1: 9 + h1 = 11
+      I = 2: stay -> J = 0: h0 = 0                   | q = 1 -> J = 1: 5 + h1 = 7
+      I = 3: stay -> J = 1: h1 = 2                   | (nothing to deliver)
+    Day 2, demand 5 (every choice ends at J = 0):
+      I = 0: stay, unmet 5: 25 | q = 3, unmet 2: 10 + 10 = 20  -> 20
+      I = 1: stay, unmet 4: 20 | q = 2, unmet 2: 9 + 10 = 19   -> 19
+      I = 2: stay, unmet 3: 15 | q = 1, unmet 2: 5 + 10 = 15   -> 15
+      I = 3: stay, unmet 2: 10                                 -> 10
+    From I0 = 0: after day 1 (10, 12, inf, inf); after day 2
+    J(0) = min(10 + 20, 12 + 19) = 30 (skip day 1, deliver on day 2).
+
+    A first-option-with-room rule (10 for q = 2), a strict capacity test
+    (no option for q = 3, option 3 for q = 1), or a dropped or mis-signed
+    stock-out term each changes one of these entries."""
+    g, fix = _golden_ou(golden_dir)
+    T, B, R = 2, 1, 3
+    demand = np.array(g["demand"], np.int64).reshape(T, B)
+    cost = np.broadcast_to(np.array(g["options"]["cost"], np.int64), (T, B, R)).copy()
+    cap = np.broadcast_to(np.array(g["options"]["cap"], np.int64), (T, B, R)).copy()
+    A = M.ou_transitions(g["U"], demand, cost, cap, g["h"], g["u"], g["rho"])
+    assert (A[0, 0] == fix(g["A_day1"])).all()
+    assert (A[1, 0] == fix(g["A_day2"])).all()
+    J0 = np.full((B, g["U"] + 1), INF, np.int64)
+    J0[0, g["I0"]] = 0
+    J1, _ = M.minplus_step(A[0], J0)
+    assert (J1 == fix([g["J_after_day1"]])).all()
+    J2, _ = M.minplus_forward(A, J0, shared=False)
+    assert (J2 == fix([g["J_after_day2"]])).all()
+    assert int(J2.min()) == g["best_total"]
+    assert M.ou_brute(g["U"], [g["I0"]], demand, cost, cap, g["h"], g["u"], g["rho"]).tolist() == [30]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_several_options_equal_elementwise_min_of_single_options(seed):
+    """App. B note (ii): the transition matrix over R route options equals
+    the elementwise minimum of the R matrices built with one option each
+    (each of the single-option form the paper's inventory example pins)."""
+    rng = np.random.default_rng(300 + seed)
+    T, B, R = 3, 4, int(rng.integers(2, 5))
+    U = int(rng.integers(1, 8))
+    demand = rng.integers(0, U + 3, size=(T, B))
+    cost = rng.integers(0, 30, size=(T, B, R))
+    cap = rng.integers(0, U + 1, size=(T, B, R))
+    h = rng.integers(0, 9, size=U + 1)
+    u, rho = int(rng.integers(0, 3)), int(rng.integers(0, 7))
+    A = M.ou_transitions(U, demand, cost, cap, h, u, rho)
+    singles = [M.ou_transitions(U, demand, cost[:, :, r:r + 1], cap[:, :, r:r + 1], h, u, rho)
+               for r in range(R)]
+    assert (A == np.minimum.reduce(singles)).all()
