@@ -457,39 +457,74 @@ int split_plan_launch(split_plan *plan, split_stream_t stream);
 int split_plan_destroy(split_plan *plan);
 
 /*
- * Served form: continuous batching of evaluation requests under an HBM
- * budget.  Each request is one giant tour over its own customers (the same
- * operation as split_eval with num_tours = 1).  The server reserves
- * `budget_bytes` of device memory at creation; a request is admitted, in
- * arrival order, once its own footprint (outputs and workspace, reported in
- * split_server_stats) fits, and runs on one of `num_streams` HIP streams
- * (1..8), so requests admitted while others run overlap on the device.
- * Memory returns to the budget as soon as a request completes.
+ * Served form (the serving loop around the split operator; the paper's
+ * batch loop in App. B sizes batches from free GPU memory and retries
+ * smaller batches on out-of-memory): continuous batching of evaluation
+ * requests under an HBM budget, drained at the granularity of a tile of 64
+ * scenarios.
  *
- * split_server_submit copies the tour (host pointer, ids in [1, N]) and
- *   returns a request id at once.  d_dist (int32 [(N+1)*(N+1)]) and
- *   d_demands (int16 [S*N], 16-byte aligned) are DEVICE pointers that the
- *   caller keeps valid and unmodified until the request completes (the
- *   demands stay resident; the server does not copy them).  costs_out is an
- *   optional HOST buffer of S int32 filled before completion is reported.
- *   SPLIT_ENOMEM if the request alone exceeds the budget.
- * split_server_poll returns SPLIT_EAGAIN while the request runs; once done it
- *   returns its sum and mean (as split_eval) and its latency from submission
- *   to completion in seconds, and forgets the request.  A request whose
- *   inputs fail device-side validation returns SPLIT_EINVAL.
+ * split_server_create reserves the server's device memory: `budget_bytes`
+ *   (0 = three quarters of the free device memory), retried at half the
+ *   size while the reservation fails with out-of-memory (down to 64 MiB);
+ *   split_server_stats reports what was reserved.  `max_len` is the longest
+ *   tour the server accepts (1..65535; it sizes the exact-fallback scratch).
+ * split_server_add_instance registers an instance: `dist` (host, int32
+ *   [(N+1)*(N+1)]) is copied and kept on the host, where each request's
+ *   tour constants are computed; `demands` (host, int16 [S*N]
+ *   scenario-major) are copied into the budget and stay resident until
+ *   split_server_remove_instance (which takes effect once no request uses
+ *   them).  SPLIT_ENOMEM if they can never fit, SPLIT_EAGAIN if the budget
+ *   has no room for them now.
+ * split_server_submit queues one giant tour (host pointer, ids in [1, N],
+ *   copied; validated as split_eval's host form) for evaluation on a
+ *   resident instance with capacity Q, and returns a request id at once.
+ *   costs_out is an optional HOST buffer of S int32, filled before
+ *   completion is reported.
+ * split_server_submit_copy is the same for a request that brings its own
+ *   instance (host pointers, copied at submission): its demands are copied
+ *   to the device at admission and counted until it completes.
+ *   A request is admitted in arrival order once its footprint (tables,
+ *   outputs, the tour-ordered demand copy for pools above 256 customers,
+ *   its own demands if any) fits; admitted requests' tiles join the device
+ *   work queue while earlier requests are still running.
+ * split_server_poll returns SPLIT_EAGAIN while the request is pending or
+ *   running; once done it returns its sum and mean (as split_eval), its
+ *   latency from submission to the result in seconds, and forgets the
+ *   request.  A negative demand found on the device gives SPLIT_EINVAL.
  * split_server_wait blocks until the request is done (poll still needed).
- * split_server_destroy waits for all admitted and pending requests.
+ * split_server_destroy completes every admitted and pending request first.
+ * Requests may be submitted and polled from several threads.
  */
-int split_server_create(split_server **server, size_t budget_bytes, int32_t num_streams);
-int split_server_submit(split_server *server, const int32_t *tour, int32_t n,
-                        const int32_t *d_dist, int32_t N, const int16_t *d_demands, int64_t S,
-                        int32_t Q, int32_t *costs_out, int64_t *request_id);
+typedef struct {
+    int64_t submitted, completed, pending, running;
+    size_t bytes_in_use, peak_bytes, capacity; /* arena bytes (the budget less fixed structures) */
+    int64_t drains;                            /* drain launches so far */
+    int64_t instances;                         /* resident instances */
+    size_t deferred_bytes;  /* retired memory held until the drains running at retirement end */
+    int64_t blocked_rounds; /* scheduler rounds in which the next request did not fit */
+} split_server_stats_t;
+
+int split_server_create(split_server **server, size_t budget_bytes, int32_t max_len);
+int split_server_add_instance(split_server *server, const int32_t *dist, int32_t N,
+                              const int16_t *demands, int64_t S, int64_t *instance_id);
+int split_server_remove_instance(split_server *server, int64_t instance_id);
+int split_server_submit(split_server *server, int64_t instance_id, const int32_t *tour,
+                        int32_t n, int32_t Q, int32_t *costs_out, int64_t *request_id);
+int split_server_submit_copy(split_server *server, const int32_t *tour, int32_t n,
+                             const int32_t *dist, int32_t N, const int16_t *demands, int64_t S,
+                             int32_t Q, int32_t *costs_out, int64_t *request_id);
 int split_server_poll(split_server *server, int64_t request_id, int64_t *sum, double *mean,
                       double *latency_s);
 int split_server_wait(split_server *server, int64_t request_id);
-int split_server_stats(split_server *server, int64_t *submitted, int64_t *completed,
-                       int64_t *pending, size_t *bytes_in_use, size_t *peak_bytes);
+int split_server_stats(split_server *server, split_server_stats_t *stats);
 int split_server_destroy(split_server *server);
+
+/*
+ * Test hook (for callers exercising the out-of-memory path): the library's
+ * next `count` device reservations made by split_server_create report
+ * out-of-memory, as a full device would.  0 turns it off.
+ */
+int split_debug_fail_allocations(int32_t count);
 
 #ifdef __cplusplus
 }

@@ -38,7 +38,11 @@ EXPORTED = (
     "split_profile_enable",
     "split_profile_read",
     "split_server_create",
+    "split_server_add_instance",
+    "split_server_remove_instance",
     "split_server_submit",
+    "split_server_submit_copy",
+    "split_debug_fail_allocations",
     "split_server_poll",
     "split_server_wait",
     "split_server_stats",
@@ -76,6 +80,14 @@ class SplitError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__("split library error %d: %s" % (code, msg))
         self.code = code
+
+
+class ServerStats(ctypes.Structure):
+    """split_server_stats_t"""
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("pending", ctypes.c_int64),
+                ("running", ctypes.c_int64), ("bytes_in_use", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t),
+                ("capacity", ctypes.c_size_t), ("drains", ctypes.c_int64), ("instances", ctypes.c_int64),
+                ("deferred_bytes", ctypes.c_size_t), ("blocked_rounds", ctypes.c_int64)]
 
 
 def _load():
@@ -117,17 +129,24 @@ def _load():
     lib.split_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.split_server_create.restype = ctypes.c_int
     lib.split_server_create.argtypes = [ctypes.POINTER(P), sz, i32]
+    lib.split_server_add_instance.restype = ctypes.c_int
+    lib.split_server_add_instance.argtypes = [P, P, i32, P, i64, ctypes.POINTER(i64)]
+    lib.split_server_remove_instance.restype = ctypes.c_int
+    lib.split_server_remove_instance.argtypes = [P, i64]
     lib.split_server_submit.restype = ctypes.c_int
-    lib.split_server_submit.argtypes = [P, P, i32, P, i32, P, i64, i32, P, ctypes.POINTER(i64)]
+    lib.split_server_submit.argtypes = [P, i64, P, i32, i32, P, ctypes.POINTER(i64)]
+    lib.split_server_submit_copy.restype = ctypes.c_int
+    lib.split_server_submit_copy.argtypes = [P, P, i32, P, i32, P, i64, i32, P, ctypes.POINTER(i64)]
     lib.split_server_poll.restype = ctypes.c_int
     lib.split_server_poll.argtypes = [P, i64, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_double)]
     lib.split_server_wait.restype = ctypes.c_int
     lib.split_server_wait.argtypes = [P, i64]
     lib.split_server_stats.restype = ctypes.c_int
-    lib.split_server_stats.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
-                                       ctypes.POINTER(sz), ctypes.POINTER(sz)]
+    lib.split_server_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
     lib.split_server_destroy.restype = ctypes.c_int
+    lib.split_debug_fail_allocations.restype = ctypes.c_int
+    lib.split_debug_fail_allocations.argtypes = [i32]
     lib.split_server_destroy.argtypes = [P]
     lib.split_tune_device.restype = ctypes.c_int
     lib.split_tune_device.argtypes = [P, P, i32, i32, P, i32, P, i64, i32, i32, P, ctypes.POINTER(ctypes.c_double)]
@@ -612,58 +631,84 @@ class Plan:
 
 
 class Server:
-    """Served form: continuous batching of single-tour requests under an HBM
-    budget (C ABI split_server_*).  Demands and cost matrices are device
-    tensors the caller keeps alive until the request completes; this wrapper
-    holds a reference to them until the request is polled."""
+    """Served form (C ABI split_server_*): continuous batching of single-tour
+    requests under an HBM budget.  Instances (cost matrix + demand scenarios,
+    host arrays) are registered once and stay resident; requests are tours
+    evaluated on them, or tours that bring their own instance."""
 
-    def __init__(self, budget_bytes: int, streams: int = 4):
+    def __init__(self, budget_bytes: int = 0, max_len: int = 1024):
         self._h = ctypes.c_void_p()
-        _check(lib.split_server_create(ctypes.byref(self._h), int(budget_bytes), int(streams)))
-        self._keep = {}
+        _check(lib.split_server_create(ctypes.byref(self._h), int(budget_bytes), int(max_len)))
+        self._costs = {}
 
-    def submit(self, tour, dist, demands, Q, *, want_costs=False) -> int:
+    def add_instance(self, dist, demands) -> int:
+        dist = np.ascontiguousarray(dist, np.int32)
+        demands = np.ascontiguousarray(demands, np.int16)
+        iid = ctypes.c_int64()
+        _check(lib.split_server_add_instance(self._h, _np_ptr(dist), int(dist.shape[0] - 1), _np_ptr(demands),
+                                             int(demands.shape[0]), ctypes.byref(iid)))
+        return iid.value
+
+    def remove_instance(self, iid: int):
+        _check(lib.split_server_remove_instance(self._h, int(iid)))
+
+    def submit(self, iid: int, tour, Q, S: int = 0, *, want_costs=False) -> int:
+        """Evaluate `tour` on resident instance `iid` (S = its scenario count,
+        needed only with want_costs)."""
         tour = np.ascontiguousarray(tour, np.int32)
-        N = int(dist.shape[0] - 1)
-        S = int(demands.shape[0])
-        costs = np.empty(S, np.int32) if want_costs else None
+        costs = np.empty(int(S), np.int32) if want_costs else None
         rid = ctypes.c_int64()
-        _check(lib.split_server_submit(self._h, _np_ptr(tour) if tour.size else None, int(tour.size), _dptr(dist),
-                                       N, _dptr(demands), S, int(Q),
-                                       _np_ptr(costs) if costs is not None else None, ctypes.byref(rid)))
-        self._keep[rid.value] = (dist, demands, costs)
+        _check(lib.split_server_submit(self._h, int(iid), _np_ptr(tour) if tour.size else None, int(tour.size),
+                                       int(Q), _np_ptr(costs) if costs is not None else None, ctypes.byref(rid)))
+        self._costs[rid.value] = costs
+        return rid.value
+
+    def submit_copy(self, tour, dist, demands, Q, *, want_costs=False) -> int:
+        tour = np.ascontiguousarray(tour, np.int32)
+        dist = np.ascontiguousarray(dist, np.int32)
+        demands = np.ascontiguousarray(demands, np.int16)
+        costs = np.empty(int(demands.shape[0]), np.int32) if want_costs else None
+        rid = ctypes.c_int64()
+        _check(lib.split_server_submit_copy(self._h, _np_ptr(tour) if tour.size else None, int(tour.size),
+                                            _np_ptr(dist), int(dist.shape[0] - 1), _np_ptr(demands),
+                                            int(demands.shape[0]), int(Q),
+                                            _np_ptr(costs) if costs is not None else None, ctypes.byref(rid)))
+        self._costs[rid.value] = costs
         return rid.value
 
     def poll(self, rid: int):
-        """None while running, else dict(sum, mean, latency_s, costs)."""
+        """None while pending or running, else dict(sum, mean, latency_s, costs)."""
         sm, mn, lat = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
         rc = lib.split_server_poll(self._h, int(rid), ctypes.byref(sm), ctypes.byref(mn), ctypes.byref(lat))
         if rc == SPLIT_EAGAIN:
             return None
-        keep = self._keep.pop(int(rid), (None, None, None))
+        costs = self._costs.pop(int(rid), None)
         _check(rc)
-        return dict(sum=sm.value, mean=mn.value, latency_s=lat.value, costs=keep[2])
+        return dict(sum=sm.value, mean=mn.value, latency_s=lat.value, costs=costs)
 
     def wait(self, rid: int):
         _check(lib.split_server_wait(self._h, int(rid)))
         return self.poll(rid)
 
     def stats(self):
-        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-        d, e = ctypes.c_size_t(), ctypes.c_size_t()
-        _check(lib.split_server_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d),
-                                      ctypes.byref(e)))
-        return dict(submitted=a.value, completed=b.value, pending=c.value, bytes_in_use=d.value,
-                    peak_bytes=e.value)
+        st = ServerStats()
+        _check(lib.split_server_stats(self._h, ctypes.byref(st)))
+        return {name: getattr(st, name) for name, _ in ServerStats._fields_}
 
     def close(self):
         if self._h:
             lib.split_server_destroy(self._h)
             self._h = ctypes.c_void_p()
-            self._keep.clear()
+            self._costs.clear()
 
     def __del__(self):
         try:
             self.close()
         except Exception:
             pass
+
+
+def debug_fail_allocations(count: int):
+    """Test hook: the next `count` device reservations of split_server_create
+    report out-of-memory."""
+    _check(lib.split_debug_fail_allocations(int(count)))

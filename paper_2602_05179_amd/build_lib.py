@@ -14,12 +14,14 @@ SOURCES = [os.path.join(CSRC, "split_kernels.hip"), os.path.join(CSRC, "split_ap
            os.path.join(CSRC, "split_server.cpp"), os.path.join(CSRC, "split_tune.cpp"),
            os.path.join(CSRC, "split_probe.hip"), os.path.join(CSRC, "split_routes.hip"),
            os.path.join(CSRC, "split_variant.hip"), os.path.join(CSRC, "split_minplus.hip"),
-           os.path.join(CSRC, "split_search.cpp"), os.path.join(CSRC, "split_check.cpp")]
+           os.path.join(CSRC, "split_search.cpp"), os.path.join(CSRC, "split_check.cpp"),
+           os.path.join(CSRC, "split_serve.hip")]
 HEADERS = [os.path.join(INCLUDE, "split_eval.h"), os.path.join(CSRC, "split_internal.h"),
            os.path.join(CSRC, "split_device.h"), os.path.join(CSRC, "window_min_asm.inc"),
            os.path.join(CSRC, "window_argmin_asm.inc"), os.path.join(CSRC, "split_variant.h"),
            os.path.join(CSRC, "split_minplus.h"),
-           os.path.join(CSRC, "window_min_multi_asm.inc"), os.path.join(CSRC, "split_check.h")]
+           os.path.join(CSRC, "window_min_multi_asm.inc"), os.path.join(CSRC, "split_check.h"),
+           os.path.join(CSRC, "split_serve.h"), os.path.join(CSRC, "split_dp.h")]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are disabled for every GPU object this library
@@ -46,15 +48,23 @@ def _jobs() -> int:
     return max(1, min(16, n, len(SOURCES)))
 
 
-def build_library(out: str = LIB, extra=()) -> str:
+def build_library(out: str = LIB, extra=(), incremental: bool = False) -> str:
     """Compile the kernels and the C ABI into one shared object (one hipcc
-    process per source, in parallel, then one link)."""
+    process per source, in parallel, then one link).  `incremental` keeps
+    object files and recompiles only sources newer than their object (or
+    than any header)."""
     objdir = os.path.join(os.path.dirname(out), "_build")
     os.makedirs(objdir, exist_ok=True)
     compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    newest_header = max(os.path.getmtime(h) for h in HEADERS)
 
     def compile_one(src):
-        obj = os.path.join(objdir, os.path.basename(src) + ".%d.o" % os.getpid())
+        if incremental:
+            obj = os.path.join(objdir, os.path.basename(src) + ".o")
+            if os.path.exists(obj) and os.path.getmtime(obj) >= max(os.path.getmtime(src), newest_header):
+                return obj, 0
+        else:
+            obj = os.path.join(objdir, os.path.basename(src) + ".%d.o" % os.getpid())
         cmd = [hipcc(), *compile_flags, "-I", INCLUDE, "-I", CSRC, *extra, "-c", "-o", obj, src]
         return obj, subprocess.run(cmd).returncode
 
@@ -69,9 +79,10 @@ def build_library(out: str = LIB, extra=()) -> str:
         subprocess.run([hipcc(), *HIPCC_FLAGS, *extra, "-o", tmp, *objs], check=True)
         os.replace(tmp, out)
     finally:
-        for o in objs:
-            if os.path.exists(o):
-                os.remove(o)
+        if not incremental:
+            for o in objs:
+                if os.path.exists(o):
+                    os.remove(o)
     return out
 
 
@@ -83,4 +94,5 @@ def is_stale(out: str = LIB) -> bool:
 
 
 if __name__ == "__main__":
-    print(build_library())
+    import sys
+    print(build_library(incremental="--incremental" in sys.argv))

@@ -43,10 +43,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <utility>
-
 #include "split_eval.h"
 #include "split_device.h"
+#include "split_dp.h"
 #include "split_internal.h"
 
 namespace splitk {
@@ -235,105 +234,6 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// the per-lane recursion, ring of R potentials in registers
-//
-// One DpState<...>::run advances every lane of the wave by one tour
-// position j (j = R*block + U); ring slot (j - d) mod R = (U - d) mod R holds
-// predecessor p = j - d, so every slot is a compile-time register.  Loads
-// run one position ahead: while position j is relaxed the demand of j+2 and
-// the table entry of j+3 are in flight, and the demand of j+1 has arrived,
-// so the load L_{j+1} is known and the next position's head checks are
-// issued inside this position's window block.
-// ---------------------------------------------------------------------------
-#include "window_min_asm.inc"
-
-struct DpRegs {
-    int L;       // load of positions 1..j (at the start of position j)
-    int qa;      // demand of position j+1 (arrived)
-    int2 t0;     // table entry of position j {customer, c}
-    int2 t1;     // table entry of position j+1
-    int2 t2;     // table entry of position j+2 (in flight)
-    uint64_t cp1; // lanes rejecting d = F at position j (computed at j-1)
-    uint64_t cp2; // lanes rejecting d = F + G at position j (computed at j-1)
-    int mres;     // m of the last position relaxed (m_n after the loop)
-    int ovf;      // 1 when a window reached past the ring
-};
-
-// CHK: the block may run past position n (the tour's last block); a full
-// block skips the per-position bound test
-template <int R, int F, int G, int E, int U, bool CHK> struct DpState {
-    __device__ __forceinline__ static bool run(int (&f)[R], int (&lq)[R], DpRegs &r,
-                                               const uint8_t *row, CInt *tab, int j0, int n,
-                                               int Q)
-    {
-        const int j = j0 + U;
-        if (U == 0 && j == 0)
-            return true;
-        if (CHK && j > n)
-            return false;
-        const int cj = r.t0.y;
-        const int Ln = r.L + r.qa;
-        r.qa = row[r.t2.x];
-        const int2 t3 = tab_at(tab, j + 3);
-        uint64_t cn1, cn2;
-        const int m = WindowMin<R, F, G, E>::template run<U>(f, lq, r.L, Ln, j, r.cp1, r.cp2, cn1,
-                                                             cn2, r.ovf);
-        r.mres = m; // the last position relaxed is j = n
-        f[U] = m + cj;
-        lq[U] = r.L + Q;
-        r.L = Ln;
-        r.cp1 = cn1;
-        r.cp2 = cn2;
-        r.t0 = r.t1;
-        r.t1 = r.t2;
-        r.t2 = t3;
-        return true;
-    }
-};
-
-template <int R, int F, int G, int E, bool CHK, int... Us>
-__device__ __forceinline__ bool dp_block(int (&f)[R], int (&lq)[R], DpRegs &r, const uint8_t *row,
-                                         CInt *tab, int j0, int n, int Q,
-                                         std::integer_sequence<int, Us...>)
-{
-    return (DpState<R, F, G, E, Us, CHK>::run(f, lq, r, row, tab, j0, n, Q) && ...);
-}
-
-// Returns m_n of the lane's scenario; sets ovf when a window left the ring.
-template <int R, int F, int G, int E>
-__device__ __forceinline__ int dp_lane(const uint8_t *row, CInt *tab, int n, int f0, int Q,
-                                       bool &ovf)
-{
-    int f[R], lq[R];
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-        f[i] = kInf;
-        lq[i] = kNeg;
-    }
-    f[0] = f0; // p = 0: V(0) + a_1
-    lq[0] = Q; // L_0 + Q
-    DpRegs r;
-    r.mres = kInf;
-    r.ovf = 0;
-    r.cp1 = ~0ull; // position 1 starts in the tail
-    r.cp2 = ~0ull;
-    r.t0 = tab_at(tab, 1);
-    r.t1 = tab_at(tab, 2);
-    r.t2 = tab_at(tab, 3);
-    r.L = row[r.t0.x];
-    r.qa = row[r.t1.x];
-    int j0 = 0;
-    for (; j0 + R - 1 <= n; j0 += R) // blocks whose positions all exist
-        dp_block<R, F, G, E, false>(f, lq, r, row, tab, j0, n, Q,
-                                    std::make_integer_sequence<int, R>{});
-    if (j0 <= n) // the last, partial block
-        dp_block<R, F, G, E, true>(f, lq, r, row, tab, j0, n, Q,
-                                   std::make_integer_sequence<int, R>{});
-    ovf = r.ovf != 0;
-    return r.mres;
-}
-
-// ---------------------------------------------------------------------------
 // main evaluation kernel: a workgroup of W waves stages one tile of 64
 // scenario rows and runs W different tours over it (wave w takes tour
 // g*W + w), so tours sharing a scenario set share one LDS copy of it.
@@ -471,113 +371,6 @@ __global__ __launch_bounds__(kPermThreads) void permute_tile_kernel(
     }
 }
 
-struct DpRegsO {
-    int L;       // load of positions 1..j (at the start of position j)
-    int2 t0;     // table entry of position j {customer, c}
-    int2 t1;     // table entry of position j+1 (in flight)
-    uint64_t cp1; // lanes rejecting d = F at position j (computed at j-1)
-    uint64_t cp2; // lanes rejecting d = F + G at position j (computed at j-1)
-    int mres;     // m of the last position relaxed (m_n after the loop)
-    int ovf;      // 1 when a window reached past the ring
-    u32x4 cur[2], nxt[2]; // demand bytes of the current / next 32 positions
-};
-
-__device__ __forceinline__ int byte_at(const u32x4 (&seg)[2], int b)
-{
-    const u32x4 &v = seg[b >> 4];
-    const int w = (b >> 2) & 3;
-    const uint32_t x = w == 0 ? v.x : w == 1 ? v.y : w == 2 ? v.z : v.w;
-    return (int)((x >> (8 * (b & 3))) & 0xFFu);
-}
-
-// position j = j0 + 1 + U of a block of R positions (j0 a multiple of R)
-template <int R, int F, int G, int E, int U, bool CHK> struct DpStateO {
-    __device__ __forceinline__ static bool run(int (&f)[R], int (&lq)[R], DpRegsO &r,
-                                               const u32x4 *row, int64_t segs, CInt *tab,
-                                               int j0, int n, int Q)
-    {
-        constexpr int SL = (U + 1) & (R - 1);
-        constexpr int B = U & 31; // byte of position j in the current segment
-        const int j = j0 + 1 + U;
-        if (CHK && j > n)
-            return false;
-        const int qn = B == 31 ? byte_at(r.nxt, 0) : byte_at(r.cur, B + 1);
-        const int cj = r.t0.y;
-        const int Ln = r.L + qn;
-        r.t0 = r.t1;
-        r.t1 = tab_at(tab, j + 2);
-        uint64_t cn1, cn2;
-        const int m = WindowMin<R, F, G, E>::template run<SL>(f, lq, r.L, Ln, j, r.cp1, r.cp2,
-                                                              cn1, cn2, r.ovf);
-        r.mres = m;
-        f[SL] = m + cj;
-        lq[SL] = r.L + Q;
-        r.L = Ln;
-        r.cp1 = cn1;
-        r.cp2 = cn2;
-        if (B == 31) { // next 32 positions: rotate and prefetch the one after
-            r.cur[0] = r.nxt[0];
-            r.cur[1] = r.nxt[1];
-            const int64_t seg = (j + 32) >> 5; // segment holding positions j+33..j+64
-            if (seg < segs) {
-                r.nxt[0] = __builtin_nontemporal_load(row + 2 * seg);
-                r.nxt[1] = __builtin_nontemporal_load(row + 2 * seg + 1);
-            }
-        }
-        return true;
-    }
-};
-
-template <int R, int F, int G, int E, bool CHK, int... Us>
-__device__ __forceinline__ bool dp_block_o(int (&f)[R], int (&lq)[R], DpRegsO &r, const u32x4 *row,
-                                           int64_t segs, CInt *tab, int j0, int n, int Q,
-                                           std::integer_sequence<int, Us...>)
-{
-    return (DpStateO<R, F, G, E, Us, CHK>::run(f, lq, r, row, segs, tab, j0, n, Q) && ...);
-}
-
-template <int R, int F, int G, int E>
-__device__ __forceinline__ int dp_lane_ordered(const uint8_t *rowb, int pitch, CInt *tab, int n,
-                                               int f0, int Q, bool &ovf)
-{
-    int f[R], lq[R];
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-        f[i] = kInf;
-        lq[i] = kNeg;
-    }
-    f[0] = f0;
-    lq[0] = Q;
-    DpRegsO r;
-    r.mres = kInf;
-    r.ovf = 0;
-    r.cp1 = ~0ull; // position 1 starts in the tail
-    r.cp2 = ~0ull;
-    r.t0 = tab_at(tab, 1);
-    r.t1 = tab_at(tab, 2);
-    const u32x4 *row = reinterpret_cast<const u32x4 *>(rowb);
-    const int64_t segs = pitch / 32;
-    r.cur[0] = __builtin_nontemporal_load(row);
-    r.cur[1] = __builtin_nontemporal_load(row + 1);
-    if (segs > 1) {
-        r.nxt[0] = __builtin_nontemporal_load(row + 2);
-        r.nxt[1] = __builtin_nontemporal_load(row + 3);
-    } else {
-        r.nxt[0] = r.cur[0];
-        r.nxt[1] = r.cur[1];
-    }
-    r.L = byte_at(r.cur, 0);
-    int j0 = 0;
-    for (; j0 + R <= n; j0 += R) // blocks whose positions all exist
-        dp_block_o<R, F, G, E, false>(f, lq, r, row, segs, tab, j0, n, Q,
-                                      std::make_integer_sequence<int, R>{});
-    if (j0 < n) // the last, partial block
-        dp_block_o<R, F, G, E, true>(f, lq, r, row, segs, tab, j0, n, Q,
-                                     std::make_integer_sequence<int, R>{});
-    ovf = r.ovf != 0;
-    return r.mres;
-}
-
 // grid = units (u -> tile u / T, tour u % T), one wave each
 template <int R, int F, int G, int E>
 __global__ __launch_bounds__(kWave) void split_ordered_kernel(int64_t S, int32_t Q, int32_t T,
@@ -652,27 +445,8 @@ __global__ __launch_bounds__(kWave) void fallback_final_kernel(const int16_t *__
         const int n = rec.n;
         int v = 0;
         bool negq = false;
-        if (lane < rows) {
-            const int16_t *qrow = demands + (s0 + lane) * N;
-            V[lane] = 0; // V(0), laid out [j][lane]
-            for (int j = 1; j <= n; ++j) {
-                const int bj = ab[j - 1].y;
-                int best = kInf;
-                int load = 0;
-                for (int p = j - 1; p >= 0; --p) {
-                    const int q = qrow[tab[p + 1].x];
-                    negq = negq || q < 0;
-                    load += q;
-                    if (load > Q)
-                        break;
-                    const int vp = V[(int64_t)p * kWave + lane];
-                    if (vp < kInf)
-                        best = min(best, vp + ab[p].x + bj);
-                }
-                V[(int64_t)j * kWave + lane] = best;
-            }
-            v = V[(int64_t)n * kWave + lane];
-        }
+        if (lane < rows)
+            v = exact_lane(demands + (s0 + lane) * N, tab, ab, n, Q, V, lane, negq);
         if (ballot(negq) != 0) {
             if (lane == 0)
                 atomicOr(&ws.rec[t].status, ST_BAD_DEMAND);

@@ -1,24 +1,39 @@
 // split_server.cpp -- served form: continuous batching of evaluation
-// requests under an HBM budget.
+// requests under an HBM budget, drained at tile granularity.
 //
-// A request is one giant tour with its own cost matrix and demand scenarios
-// (device-resident, owned by the caller until the request completes).  The
-// server owns one device arena of `budget` bytes; a request is admitted when
-// its own device footprint (tour, outputs, workspace) fits in the arena,
-// in arrival order, and is then enqueued on one of a few HIP streams, so
-// kernels of requests admitted while others are running overlap on the
-// device.  A scheduler thread admits, launches and retires requests; a
-// retired request's memory returns to the arena at once, which admits the
-// next ones.  Results (sum, mean, optionally per-scenario costs) are copied
-// to host memory and kept until polled.
+// Instances (a cost matrix and a demand scenario set) are registered once:
+// the demands are copied into the server's device arena and stay resident,
+// counted against the budget; the cost matrix stays on the host, where the
+// tour constants of every request are computed.  A request is one giant
+// tour evaluated on a resident instance, or one that brings its own
+// instance (copied at admission and released at completion).
 //
-// The paper's batching loop sizes a batch from free GPU memory and retries
-// with a smaller batch on allocation failure (App. B, adaptive batching);
-// here the same concern is handled up front by admission against a fixed
-// arena, so no device allocation happens while requests run.
+// The scheduler thread admits requests in arrival order while the arena,
+// the job table and the queue have room (the paper's batching loop sizes
+// its batches from free GPU memory, App. B; here admission against the
+// arena plays that role and nothing is allocated per request).  Admission
+// copies the request's tables into its arena block on the copy stream
+// (from per-slot pinned staging), runs the permute launch for large pools,
+// and a one-wave publish kernel appends the jobs to a device work queue.
+// Drain kernels (split_serve.hip) take tiles from the queue; the scheduler
+// keeps at most two drains per queue in flight and launches the next one
+// while work remains.  The wave that finishes a job's last tile writes its
+// result to pinned host memory, which the scheduler polls: no event or
+// allocation per request.
+//
+// Reuse of device memory: a retired job's arena block and table slot are
+// released only once every drain that was running when it retired has
+// ended, so no running drain can hold cached lines of memory that a later
+// job reuses.
+//
+// The server's own reservation follows the paper's adaptive batching
+// (App. B, Alg. "GPU-Based DP with Adaptive Batching"): the budget defaults
+// to a share of free device memory, and a reservation that fails with
+// out-of-memory is retried at half the size.
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -34,12 +49,26 @@
 
 #include "split_eval.h"
 #include "split_internal.h"
+#include "split_serve.h"
 
 namespace {
 
 using Clock = std::chrono::steady_clock;
 
 #define sfail splitk::set_error
+
+std::atomic<int> g_fail_allocs{0}; // test hook: device allocations to fail
+
+// Device allocation through the failure hook.
+hipError_t dev_alloc(void **p, size_t bytes)
+{
+    int n = g_fail_allocs.load();
+    while (n > 0) {
+        if (g_fail_allocs.compare_exchange_weak(n, n - 1))
+            return hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
 
 // First-fit allocator over one device range (offsets only; 256-byte units).
 class Arena {
@@ -54,7 +83,7 @@ class Arena {
     }
     bool alloc(size_t bytes, size_t *off)
     {
-        bytes = (bytes + 255) & ~(size_t)255;
+        bytes = round(bytes);
         for (auto it = free_.begin(); it != free_.end(); ++it) {
             if (it->second >= bytes) {
                 *off = it->first;
@@ -72,7 +101,7 @@ class Arena {
     }
     void release(size_t off, size_t bytes)
     {
-        bytes = (bytes + 255) & ~(size_t)255;
+        bytes = round(bytes);
         used_ -= bytes;
         auto it = free_.emplace(off, bytes).first;
         auto nx = std::next(it);
@@ -88,6 +117,7 @@ class Arena {
             }
         }
     }
+    static size_t round(size_t b) { return (b + 255) & ~(size_t)255; }
     size_t used() const { return used_; }
     size_t peak() const { return peak_; }
     size_t capacity() const { return cap_; }
@@ -97,31 +127,55 @@ class Arena {
     size_t cap_ = 0, used_ = 0, peak_ = 0;
 };
 
+size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Instance {
+    int64_t id = 0;
+    int32_t N = 0;
+    int64_t S = 0;
+    std::vector<int32_t> dist;    // host copy, (N+1)^2
+    std::vector<int16_t> h_dem;   // transient instances: demands until admission
+    size_t off = 0, bytes = 0;    // arena block of the demands (bytes 0: not resident yet)
+    int refs = 0;                 // requests referring to it
+    bool transient = false;
+    bool removed = false;
+};
+
 enum ReqState { PENDING, RUNNING, DONE };
 
 struct Request {
     int64_t id = 0;
-    std::vector<int32_t> tour;
-    const int32_t *d_dist = nullptr;
-    int32_t N = 0;
-    const int16_t *d_demands = nullptr;
-    int64_t S = 0;
-    int32_t Q = 0;
+    Instance *inst = nullptr;
+    int32_t n = 0, Q = 0;
     int32_t *costs_out = nullptr; // host, may be null
+    // host-computed tour constants
+    std::vector<int2> tab, ab;
+    int32_t f0 = 0, bn = 0, variant = 0, pitch = 0;
     bool ordered = false;
-    size_t bytes = 0, off = 0;
-    int stream = 0;
+    // admission
+    size_t off = 0, bytes = 0;
+    int slot = -1;
+    int32_t seq = 0;
     ReqState state = PENDING;
-    hipEvent_t done = nullptr;
     Clock::time_point t_submit, t_done;
-    // pinned host staging: [0] = n (lens), [1..n] tour; results after
-    int32_t *h_in = nullptr;
-    int64_t *h_sum = nullptr;
-    double *h_mean = nullptr;
-    int32_t *h_costs = nullptr; // pinned bounce buffer for costs (if requested)
     int64_t sum = 0;
     double mean = 0.0;
     int error = SPLIT_OK;
+};
+
+// Memory released once the drains that were running at retirement have
+// ended (drain ids below `mark` only).
+struct Deferred {
+    uint64_t mark;
+    size_t off, bytes; // arena block (bytes 0: none)
+    int slot;          // job slot (-1: none)
+};
+
+struct Drain {
+    uint64_t id;
+    int stream;
+    hipEvent_t done;
+    Clock::time_point launched;
 };
 
 } // namespace
@@ -132,223 +186,502 @@ struct split_server {
     std::thread worker;
     bool stop = false;
     int device = 0;
+    int32_t max_len = 0;
+
+    // device memory: fixed structures, then the arena
+    char *dev_base = nullptr;
+    splitk::ServeJob *d_jobs = nullptr;
+    splitk::ServeQueue *d_queue[2] = {nullptr, nullptr}; // 0 fused, 1 ordered
+    int *d_scratch = nullptr;
+    uint32_t *d_scratch_mask = nullptr;
     char *arena_base = nullptr;
     Arena arena;
-    std::vector<hipStream_t> streams;
-    std::vector<int> stream_load;
+
+    // pinned host memory: results, per-slot staging (descriptor and tables)
+    char *pin_base = nullptr;
+    splitk::ServeResult *h_results = nullptr;
+    char *h_stage = nullptr; // [kServeMaxJobs][stage_bytes]
+    size_t stage_bytes = 0;
+
+    hipStream_t copy_stream = nullptr, out_stream = nullptr;
+    hipStream_t drain_stream[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    std::vector<hipEvent_t> event_pool;
+    std::deque<Drain> drains[2];
+    int drain_rr[2] = {0, 0};
+    int drain_grid[2] = {0, 0};
+    uint64_t next_drain_id = 1;
+    int64_t drains_launched = 0;
+    int64_t life_us = 1000;
+    int64_t blocked = 0;        // scheduler rounds whose next request did not fit
+    size_t deferred_bytes = 0;  // retired memory waiting for running drains to end
+    hipEvent_t pub_event = nullptr; // recorded after the latest publish launch
+    bool pub_recorded = false;
+    splitk::ServeCtl ctl{};
+
+    std::vector<int> free_slots;
+    std::vector<Request *> slot_req; // [kServeMaxJobs]
+    int32_t seq_counter = 0;
+    int64_t outstanding[2] = {0, 0}; // published, not finished, per queue
     std::deque<Request *> pending;
     std::vector<Request *> running;
+    std::vector<Deferred> deferred;
     std::unordered_map<int64_t, Request *> all;
-    int64_t next_id = 1;
+    std::unordered_map<int64_t, Instance *> instances;
+    int64_t next_id = 1, next_inst = 1;
     int64_t submitted = 0, completed = 0;
-    int error = SPLIT_OK;
-    char error_text[256] = "";
+    int failed = SPLIT_OK; // a HIP error stops all further device work
+    char fail_text[256] = "";
 
-    // device footprint of a request, laid out inside its arena block
-    static size_t footprint(const Request &r, size_t *ws_off, size_t *tour_off, size_t *out_off)
+    // ----- helpers (scheduler thread unless noted) -----
+    size_t footprint(const Request &r) const
     {
-        const int32_t n = (int32_t)r.tour.size();
+        const int64_t S = r.inst->S;
         size_t b = 0;
-        *ws_off = b;
-        b += (splitk::workspace_bytes(1, n, r.N, r.S, r.ordered) + 255) & ~(size_t)255;
-        *tour_off = b;
-        b += ((size_t)(n + 1) * 4 + 255) & ~(size_t)255; // lens + tour
-        *out_off = b;
-        b += ((size_t)r.S * 4 + 16 + 255) & ~(size_t)255; // sums, means, costs
+        b += a256(((size_t)r.n + splitk::kTabPad) * sizeof(int2)); // tab
+        b += a256((size_t)std::max(r.n, 1) * sizeof(int2));        // ab
+        b += a256(sizeof(splitk::TourRec));                         // rec (permute)
+        b += a256((size_t)S * 4);                                   // costs
+        if (r.ordered) {
+            b += a256((size_t)splitk::num_tiles(S));              // tile_bad
+            b += a256((size_t)S * (size_t)r.pitch);               // tour-ordered copy
+        }
+        if (r.inst->transient)
+            b += a256((size_t)S * r.inst->N * 2);                 // own demands
         return b;
     }
 
-    int launch(Request *r)
+    uint64_t min_running_drain() const
     {
-        size_t ws_off, tour_off, out_off;
-        footprint(*r, &ws_off, &tour_off, &out_off);
-        char *base = arena_base + r->off;
-        int32_t *d_in = reinterpret_cast<int32_t *>(base + tour_off);
-        int64_t *d_sum = reinterpret_cast<int64_t *>(base + out_off);
-        double *d_mean = reinterpret_cast<double *>(base + out_off + 8);
-        int32_t *d_costs = reinterpret_cast<int32_t *>(base + out_off + 16);
-        const int32_t n = (int32_t)r->tour.size();
-        hipStream_t st = streams[r->stream];
-        hipError_t e = hipMemcpyAsync(d_in, r->h_in, (size_t)(n + 1) * 4, hipMemcpyHostToDevice, st);
-        if (e != hipSuccess)
-            return SPLIT_EDEVICE;
-        const splitk::Workspace ws =
-            splitk::carve_workspace(base + ws_off, 1, n, r->N, r->S, r->ordered);
-        bool ordered = false;
-        splitk::Schedule sched = splitk::choose_schedule(1, n, r->N, r->S, r->Q, &ordered);
-        if (ordered != r->ordered) // the footprint was sized for r->ordered
-            sched = splitk::default_schedule(r->N, r->S, r->Q);
-        e = splitk::launch_eval(d_in + 1, d_in, 1, n, r->d_dist, r->N, r->d_demands, r->S, r->Q,
-                                d_costs, d_sum, d_mean, ws, st, sched);
-        if (e != hipSuccess)
-            return SPLIT_EDEVICE;
-        e = hipMemcpyAsync(r->h_sum, d_sum, 16, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess && r->h_costs)
-            e = hipMemcpyAsync(r->h_costs, d_costs, (size_t)r->S * 4, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess)
-            e = hipEventRecord(r->done, st);
-        return e == hipSuccess ? SPLIT_OK : SPLIT_EDEVICE;
+        uint64_t m = next_drain_id;
+        for (int q = 0; q < 2; ++q)
+            for (const Drain &d : drains[q])
+                m = std::min(m, d.id);
+        return m;
+    }
+
+    void fail_all(const char *what, hipError_t e)
+    {
+        if (failed == SPLIT_OK) {
+            failed = SPLIT_EDEVICE;
+            snprintf(fail_text, sizeof(fail_text), "%s: %s", what, hipGetErrorString(e));
+        }
+    }
+
+    // Admits one request: staging, copies, permute.  Returns false when
+    // resources are short (the request stays pending).
+    bool admit(Request *r, std::vector<Request *> &batch)
+    {
+        if (free_slots.empty())
+            return false;
+        const int qi = r->ordered ? 1 : 0;
+        if (outstanding[qi] >= splitk::kServeQueueCap - 2)
+            return false;
+        const size_t bytes = footprint(*r);
+        size_t off = 0;
+        if (!arena.alloc(bytes, &off))
+            return false;
+        r->off = off;
+        r->bytes = bytes;
+        r->slot = free_slots.back();
+        free_slots.pop_back();
+        slot_req[r->slot] = r;
+        r->seq = ++seq_counter;
+        if (seq_counter >= (1 << 30))
+            seq_counter = 0;
+
+        Instance *in = r->inst;
+        const int64_t S = in->S;
+        char *blk = arena_base + off;
+        size_t o = 0;
+        int2 *d_tab = reinterpret_cast<int2 *>(blk + o);
+        o += a256(((size_t)r->n + splitk::kTabPad) * sizeof(int2));
+        int2 *d_ab = reinterpret_cast<int2 *>(blk + o);
+        o += a256((size_t)std::max(r->n, 1) * sizeof(int2));
+        splitk::TourRec *d_rec = reinterpret_cast<splitk::TourRec *>(blk + o);
+        o += a256(sizeof(splitk::TourRec));
+        int32_t *d_costs = reinterpret_cast<int32_t *>(blk + o);
+        o += a256((size_t)S * 4);
+        uint8_t *d_bad = nullptr, *d_perm = nullptr;
+        if (r->ordered) {
+            d_bad = reinterpret_cast<uint8_t *>(blk + o);
+            o += a256((size_t)splitk::num_tiles(S));
+            d_perm = reinterpret_cast<uint8_t *>(blk + o);
+            o += a256((size_t)S * (size_t)r->pitch);
+        }
+        const int16_t *d_dem = nullptr;
+        if (in->transient) {
+            int16_t *dd = reinterpret_cast<int16_t *>(blk + o);
+            o += a256((size_t)S * in->N * 2);
+            hipError_t e = hipMemcpyAsync(dd, in->h_dem.data(), (size_t)S * in->N * 2,
+                                          hipMemcpyHostToDevice, copy_stream);
+            if (e != hipSuccess) {
+                fail_all("copy demands", e);
+                return true;
+            }
+            in->h_dem.clear();
+            in->h_dem.shrink_to_fit();
+            d_dem = dd;
+        } else {
+            d_dem = reinterpret_cast<const int16_t *>(arena_base + in->off);
+        }
+
+        // pinned staging of this slot: the job descriptor (read by the
+        // publish kernel), then tab, ab, rec laid out as in the arena block
+        char *st = h_stage + (size_t)r->slot * stage_bytes + a256(sizeof(splitk::ServeJob));
+        const size_t tab_b = ((size_t)r->n + splitk::kTabPad) * sizeof(int2);
+        const size_t ab_b = (size_t)r->n * sizeof(int2);
+        memcpy(st, r->tab.data(), tab_b);
+        memcpy(st + a256(tab_b), r->ab.data(), ab_b);
+        splitk::TourRec rec{};
+        rec.n = r->n;
+        rec.f0 = r->f0;
+        rec.bn = r->bn;
+        rec.status = 0;
+        rec.maxc = 0;
+        memcpy(st + a256(tab_b) + a256((size_t)std::max(r->n, 1) * sizeof(int2)), &rec,
+               sizeof(rec));
+        const size_t head_b = a256(tab_b) + a256((size_t)std::max(r->n, 1) * sizeof(int2)) +
+                              sizeof(splitk::TourRec);
+        hipError_t e = hipMemcpyAsync(d_tab, st, head_b, hipMemcpyHostToDevice, copy_stream);
+        if (e != hipSuccess) {
+            fail_all("copy tables", e);
+            return true;
+        }
+        if (r->ordered) {
+            splitk::Workspace ws{};
+            ws.tab = d_tab;
+            ws.rec = d_rec;
+            ws.tile_bad = d_bad;
+            ws.perm = d_perm;
+            ws.max_len = r->n;
+            e = splitk::launch_permute(d_dem, in->N, S, 1, r->n, ws, copy_stream);
+            if (e != hipSuccess) {
+                fail_all("permute launch", e);
+                return true;
+            }
+        }
+        splitk::ServeJob j{};
+        j.demands = d_dem;
+        j.perm = d_perm;
+        j.tile_bad = d_bad;
+        j.tab = d_tab;
+        j.ab = d_ab;
+        j.costs = d_costs;
+        j.S = S;
+        j.N = in->N;
+        j.n = r->n;
+        j.Q = r->Q;
+        j.f0 = r->f0;
+        j.bn = r->bn;
+        j.tiles = (int32_t)splitk::num_tiles(S);
+        j.variant = r->variant;
+        j.pitch = r->pitch;
+        j.seq = r->seq;
+        memcpy(h_stage + (size_t)r->slot * stage_bytes, &j, sizeof(j));
+        batch.push_back(r);
+        return true;
+    }
+
+    // Publish launches for the requests admitted this round (at most
+    // kPublishMax per launch), on the copy stream after their tables.
+    void publish(std::vector<Request *> &batch)
+    {
+        if (batch.empty() || failed)
+            return;
+        for (size_t i = 0; i < batch.size(); i += splitk::kPublishMax) {
+            splitk::PublishBatch pb{};
+            pb.count = (int32_t)std::min(batch.size() - i, (size_t)splitk::kPublishMax);
+            for (int k = 0; k < pb.count; ++k) {
+                const Request *r = batch[i + k];
+                pb.entry[k] = r->slot | ((r->ordered ? 1 : 0) << 30);
+            }
+            hipError_t e = splitk::serve_launch_publish(d_queue[0], d_queue[1], d_jobs, h_stage,
+                                                        stage_bytes, pb, copy_stream);
+            if (e != hipSuccess) {
+                fail_all("publish launch", e);
+                return;
+            }
+        }
+        hipError_t e = hipEventRecord(pub_event, copy_stream);
+        if (e != hipSuccess) {
+            fail_all("publish event", e);
+            return;
+        }
+        pub_recorded = true;
+        for (Request *r : batch) {
+            outstanding[r->ordered ? 1 : 0]++;
+            r->state = RUNNING;
+            running.push_back(r);
+        }
+        batch.clear();
+    }
+
+    hipEvent_t get_event()
+    {
+        if (event_pool.empty())
+            return nullptr;
+        hipEvent_t e = event_pool.back();
+        event_pool.pop_back();
+        return e;
+    }
+
+    void manage_drains(Clock::time_point now)
+    {
+        const auto life = std::chrono::microseconds(life_us);
+        for (int qi = 0; qi < 2; ++qi) {
+            // retire finished drains
+            while (!drains[qi].empty()) {
+                Drain &d = drains[qi].front();
+                const hipError_t q = hipEventQuery(d.done);
+                if (q == hipErrorNotReady)
+                    break;
+                if (q != hipSuccess)
+                    fail_all("drain", q);
+                event_pool.push_back(d.done);
+                drains[qi].pop_front();
+            }
+            if (failed || outstanding[qi] == 0)
+                continue;
+            const bool none = drains[qi].empty();
+            const bool aging = drains[qi].size() == 1 && now - drains[qi].back().launched > life / 2;
+            if (!none && !aging)
+                continue;
+            hipEvent_t ev = get_event();
+            if (!ev)
+                continue;
+            const int si = drain_rr[qi]++ & 1;
+            hipStream_t st = drain_stream[qi][si];
+            // the drain starts after the latest publication has landed
+            hipError_t e = pub_recorded ? hipStreamWaitEvent(st, pub_event, 0) : hipSuccess;
+            if (e == hipSuccess)
+                e = splitk::serve_launch_drain(qi == 1, ctl, d_queue[qi], drain_grid[qi], st);
+            if (e == hipSuccess)
+                e = hipEventRecord(ev, st);
+            if (e != hipSuccess) {
+                event_pool.push_back(ev);
+                fail_all("drain launch", e);
+                continue;
+            }
+            drains[qi].push_back(Drain{next_drain_id++, si, ev, now});
+            drains_launched++;
+        }
+    }
+
+    // Polls finished jobs (results in pinned memory).  Called unlocked; the
+    // request objects it touches are owned by the scheduler while RUNNING.
+    void collect(std::vector<Request *> &done)
+    {
+        for (size_t i = 0; i < running.size();) {
+            Request *r = running[i];
+            const splitk::ServeResult *res = h_results + r->slot;
+            const int32_t seq = __atomic_load_n(&res->seq, __ATOMIC_ACQUIRE);
+            if (seq != r->seq) {
+                ++i;
+                continue;
+            }
+            r->sum = res->sum;
+            r->mean = res->mean;
+            if (res->flags & 1)
+                r->error = SPLIT_EINVAL;
+            else if (res->flags)
+                r->error = SPLIT_EDEVICE;
+            if (r->costs_out && r->error == SPLIT_OK) {
+                const char *d_costs = arena_base + r->off +
+                                      a256(((size_t)r->n + splitk::kTabPad) * sizeof(int2)) +
+                                      a256((size_t)std::max(r->n, 1) * sizeof(int2)) +
+                                      a256(sizeof(splitk::TourRec));
+                hipError_t e = hipMemcpyAsync(r->costs_out, d_costs, (size_t)r->inst->S * 4,
+                                              hipMemcpyDeviceToHost, out_stream);
+                if (e == hipSuccess)
+                    e = hipStreamSynchronize(out_stream);
+                if (e != hipSuccess) {
+                    r->error = SPLIT_EDEVICE;
+                    fail_all("copy costs", e);
+                }
+            }
+            r->t_done = Clock::now();
+            outstanding[r->ordered ? 1 : 0]--;
+            done.push_back(r);
+            running[i] = running.back();
+            running.pop_back();
+        }
+    }
+
+    void release_deferred()
+    {
+        const uint64_t m = min_running_drain();
+        for (size_t i = 0; i < deferred.size();) {
+            if (deferred[i].mark <= m) {
+                if (deferred[i].bytes) {
+                    arena.release(deferred[i].off, deferred[i].bytes);
+                    deferred_bytes -= Arena::round(deferred[i].bytes);
+                }
+                if (deferred[i].slot >= 0) {
+                    slot_req[deferred[i].slot] = nullptr;
+                    free_slots.push_back(deferred[i].slot);
+                }
+                deferred[i] = deferred.back();
+                deferred.pop_back();
+            } else {
+                ++i;
+            }
+        }
     }
 
     void retire(Request *r)
     {
-        r->t_done = Clock::now();
-        r->sum = *r->h_sum;
-        r->mean = *r->h_mean;
-        if (r->error == SPLIT_OK && r->sum == SPLIT_SUM_INVALID)
-            r->error = SPLIT_EINVAL;
-        if (r->h_costs && r->costs_out)
-            memcpy(r->costs_out, r->h_costs, (size_t)r->S * 4);
-        arena.release(r->off, r->bytes);
-        stream_load[r->stream]--;
+        // every drain launched so far may have touched the job's memory
+        deferred.push_back(Deferred{next_drain_id, r->off, r->bytes, r->slot});
+        deferred_bytes += Arena::round(r->bytes);
+        Instance *in = r->inst;
+        in->refs--;
+        if (in->transient) {
+            all_instances_erase(in);
+        } else if (in->removed && in->refs == 0 && in->bytes) {
+            deferred.push_back(Deferred{next_drain_id, in->off, in->bytes, -1});
+            deferred_bytes += Arena::round(in->bytes);
+            all_instances_erase(in);
+        }
+        r->inst = nullptr;
         r->state = DONE;
         completed++;
+    }
+
+    void all_instances_erase(Instance *in)
+    {
+        instances.erase(in->id);
+        delete in;
     }
 
     void loop()
     {
         (void)hipSetDevice(device);
+        std::vector<Request *> batch, done;
         std::unique_lock<std::mutex> lk(mu);
         while (true) {
+            const auto now = Clock::now();
             bool progress = false;
-            // admit in arrival order while the arena has room
-            while (!pending.empty()) {
-                Request *r = pending.front();
-                if (!arena.alloc(r->bytes, &r->off))
-                    break;
-                pending.pop_front();
-                int best = 0;
-                for (size_t s = 1; s < streams.size(); ++s)
-                    if (stream_load[s] < stream_load[best])
-                        best = (int)s;
-                r->stream = best;
-                stream_load[best]++;
-                r->state = RUNNING;
-                const int rc = launch(r);
-                if (rc != SPLIT_OK) {
-                    r->error = rc;
-                    error = rc;
-                    snprintf(error_text, sizeof(error_text), "launch failed for request %lld",
-                             (long long)r->id);
-                }
-                running.push_back(r);
-                progress = true;
-            }
-            // retire finished requests
-            for (size_t i = 0; i < running.size();) {
-                Request *r = running[i];
-                const hipError_t q = r->error ? hipSuccess : hipEventQuery(r->done);
-                if (q == hipErrorNotReady) {
-                    ++i;
-                    continue;
-                }
-                if (q != hipSuccess) {
-                    r->error = SPLIT_EDEVICE;
-                    error = SPLIT_EDEVICE;
-                }
+            // completions (pinned memory reads only)
+            done.clear();
+            collect(done);
+            for (Request *r : done)
                 retire(r);
-                running[i] = running.back();
-                running.pop_back();
+            if (!done.empty()) {
+                progress = true;
+                cv_done.notify_all();
+            }
+            manage_drains(now);
+            release_deferred();
+            // admission in arrival order
+            while (!pending.empty() && !failed) {
+                Request *r = pending.front();
+                if (!admit(r, batch)) {
+                    blocked++;
+                    break;
+                }
+                pending.pop_front();
                 progress = true;
             }
-            if (progress)
+            publish(batch);
+            manage_drains(Clock::now());
+            if (failed) {
+                // no further device work: every open request fails
+                for (Request *r : pending) {
+                    r->error = SPLIT_EDEVICE;
+                    r->state = DONE;
+                    if (--r->inst->refs == 0 && r->inst->transient)
+                        all_instances_erase(r->inst);
+                    r->inst = nullptr;
+                    completed++;
+                }
+                pending.clear();
+                for (Request *r : running) {
+                    r->error = SPLIT_EDEVICE;
+                    r->state = DONE;
+                    completed++;
+                }
+                running.clear();
                 cv_done.notify_all();
+            }
             if (stop && pending.empty() && running.empty())
                 break;
             if (!progress) {
-                if (running.empty())
-                    cv_work.wait(lk, [&] { return stop || !pending.empty(); });
-                else
-                    cv_work.wait_for(lk, std::chrono::microseconds(20));
+                if (running.empty() && pending.empty()) {
+                    bool drains_left = !drains[0].empty() || !drains[1].empty() ||
+                                       !deferred.empty();
+                    if (drains_left)
+                        cv_work.wait_for(lk, std::chrono::microseconds(200));
+                    else
+                        cv_work.wait(lk, [&] { return stop || !pending.empty(); });
+                } else {
+                    lk.unlock();
+                    std::this_thread::sleep_for(std::chrono::microseconds(5));
+                    lk.lock();
+                }
             }
         }
+        // wait for the drains to end before memory is released
+        for (int qi = 0; qi < 2; ++qi)
+            for (Drain &d : drains[qi]) {
+                (void)hipEventSynchronize(d.done);
+                event_pool.push_back(d.done);
+            }
+        drains[0].clear();
+        drains[1].clear();
     }
 };
 
-extern "C" {
+namespace {
 
-int split_server_create(split_server **out, size_t budget_bytes, int32_t num_streams)
+// Tour constants on the host (the prep kernel's arithmetic for one tour):
+// tab[j] = {sigma_j - 1, c_j}, ab[k-1] = {a_k, b_k}; validation as
+// split_eval's host form.
+int prepare(Request *r, const int32_t *tour, int32_t n, const Instance &in, int32_t Q)
 {
-    splitk::clear_error();
-    if (!out || budget_bytes < 4096 || num_streams < 1 || num_streams > 8)
-        return sfail(SPLIT_EINVAL, "need budget >= 4096 bytes and 1..8 streams");
-    split_server *s = new split_server();
-    if (hipGetDevice(&s->device) != hipSuccess) {
-        delete s;
-        return sfail(SPLIT_EDEVICE, "no device");
-    }
-    if (hipMalloc(&s->arena_base, budget_bytes) != hipSuccess) {
-        delete s;
-        return sfail(SPLIT_ENOMEM, "cannot reserve %zu bytes of device memory", budget_bytes);
-    }
-    s->arena.init(budget_bytes);
-    s->streams.resize(num_streams);
-    s->stream_load.assign(num_streams, 0);
-    for (auto &st : s->streams)
-        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
-            (void)hipFree(s->arena_base);
-            delete s;
-            return sfail(SPLIT_EDEVICE, "stream creation failed");
+    const int32_t N = in.N;
+    int32_t lens[1] = {n};
+    int32_t max_len = 0;
+    int64_t total = 0;
+    int rc = splitk::check_tours_host(tour, lens, 1, in.dist.data(), N, &max_len, &total);
+    if (rc)
+        return rc;
+    const int64_t N1 = (int64_t)N + 1;
+    const int32_t *dist = in.dist.data();
+    r->n = n;
+    r->Q = Q;
+    r->tab.assign((size_t)n + splitk::kTabPad, int2{0, 0});
+    r->ab.assign((size_t)std::max(n, 1), int2{0, 0});
+    int64_t D = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        const int32_t c = tour[k];
+        const int64_t out = dist[c], in_ = dist[(int64_t)c * N1];
+        int64_t ck = 0, arc = 0;
+        if (k + 1 < n) {
+            const int32_t cn = tour[k + 1];
+            arc = dist[(int64_t)c * N1 + cn];
+            ck = in_ + dist[cn] - arc;
         }
-    s->worker = std::thread([s] { s->loop(); });
-    *out = s;
+        r->tab[(size_t)k + 1] = int2{c - 1, (int)ck};
+        r->ab[(size_t)k] = int2{(int)(out - D), (int)(D + in_)};
+        D += arc;
+    }
+    r->f0 = n > 0 ? dist[tour[0]] : 0;
+    r->bn = n > 0 ? r->ab[(size_t)n - 1].y : 0;
+    r->variant = Q > 200 ? splitk::SV_R64_16 : Q > 100 ? splitk::SV_R32_8 : splitk::SV_R32_6;
+    r->ordered = N > splitk::kServeFusedMaxN;
+    r->pitch = r->ordered ? splitk::ordered_pitch(n) : 0;
     return SPLIT_OK;
 }
 
-int split_server_submit(split_server *s, const int32_t *tour, int32_t n, const int32_t *d_dist,
-                        int32_t N, const int16_t *d_demands, int64_t S, int32_t Q,
-                        int32_t *costs_out, int64_t *id)
+int enqueue(split_server *s, Request *r, int64_t *id)
 {
-    splitk::clear_error();
-    if (!s || !id || !d_dist || !d_demands || (n > 0 && !tour))
-        return sfail(SPLIT_EINVAL, "null argument");
-    if (n < 0 || n > splitk::kMaxLen || N < 1 || S < 1 || Q < 0)
-        return sfail(SPLIT_EINVAL, "bad sizes n=%d N=%d S=%lld Q=%d", n, N, (long long)S, Q);
-    if (reinterpret_cast<uintptr_t>(d_demands) % 16)
-        return sfail(SPLIT_EINVAL, "demands must be 16-byte aligned");
-    for (int32_t k = 0; k < n; ++k)
-        if (tour[k] < 1 || tour[k] > N)
-            return sfail(SPLIT_EINVAL, "tour position %d: customer id %d outside [1, %d]", k + 1,
-                         tour[k], N);
-    Request *r = new Request();
-    r->tour.assign(tour, tour + n);
-    r->d_dist = d_dist;
-    r->N = N;
-    r->d_demands = d_demands;
-    r->S = S;
-    r->Q = Q;
-    r->costs_out = costs_out;
-    (void)splitk::choose_schedule(1, n, N, S, Q, &r->ordered);
-    size_t a, b, c;
-    r->bytes = split_server::footprint(*r, &a, &b, &c);
-    if (r->bytes > s->arena.capacity()) {
-        const size_t need = r->bytes;
-        delete r;
-        return sfail(SPLIT_ENOMEM, "request needs %zu bytes, the budget is %zu", need,
-                     s->arena.capacity());
-    }
-    // pinned staging: lens + tour, then results
-    const size_t pin = (size_t)(n + 1) * 4 + 16 + 16 + (costs_out ? (size_t)S * 4 : 0);
-    char *h = nullptr;
-    if (hipHostMalloc(reinterpret_cast<void **>(&h), pin, hipHostMallocDefault) != hipSuccess) {
-        delete r;
-        return sfail(SPLIT_ENOMEM, "pinned staging allocation failed");
-    }
-    r->h_in = reinterpret_cast<int32_t *>(h);
-    r->h_in[0] = n;
-    if (n)
-        memcpy(r->h_in + 1, tour, (size_t)n * 4);
-    char *res = h + (((size_t)(n + 1) * 4 + 15) & ~(size_t)15);
-    r->h_sum = reinterpret_cast<int64_t *>(res);
-    r->h_mean = reinterpret_cast<double *>(res + 8);
-    r->h_costs = costs_out ? reinterpret_cast<int32_t *>(res + 16) : nullptr;
-    if (hipEventCreateWithFlags(&r->done, hipEventDisableTiming) != hipSuccess) {
-        (void)hipHostFree(h);
-        delete r;
-        return sfail(SPLIT_EDEVICE, "event creation failed");
-    }
     {
         std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stop) {
+            r->inst->refs--;
+            delete r;
+            return sfail(SPLIT_EINVAL, "server is shutting down");
+        }
         r->id = s->next_id++;
         r->t_submit = Clock::now();
         s->all[r->id] = r;
@@ -360,13 +693,296 @@ int split_server_submit(split_server *s, const int32_t *tour, int32_t n, const i
     return SPLIT_OK;
 }
 
-static void free_request(Request *r)
+} // namespace
+
+extern "C" {
+
+int split_debug_fail_allocations(int32_t count)
 {
-    if (r->done)
-        (void)hipEventDestroy(r->done);
-    if (r->h_in)
-        (void)hipHostFree(r->h_in);
-    delete r;
+    splitk::clear_error();
+    if (count < 0)
+        return sfail(SPLIT_EINVAL, "count must be >= 0");
+    g_fail_allocs.store(count);
+    return SPLIT_OK;
+}
+
+int split_server_create(split_server **out, size_t budget_bytes, int32_t max_len)
+{
+    splitk::clear_error();
+    if (!out || max_len < 1 || max_len > splitk::kMaxLen)
+        return sfail(SPLIT_EINVAL, "need an output pointer and 1 <= max_len <= %d", splitk::kMaxLen);
+    split_server *s = new split_server();
+    s->max_len = max_len;
+    auto bail = [&](int code, const char *what, hipError_t e) {
+        if (s->dev_base)
+            (void)hipFree(s->dev_base);
+        if (s->pin_base)
+            (void)hipHostFree(s->pin_base);
+        for (hipEvent_t ev : s->event_pool)
+            (void)hipEventDestroy(ev);
+        if (s->pub_event)
+            (void)hipEventDestroy(s->pub_event);
+        for (hipStream_t st : {s->copy_stream, s->out_stream, s->drain_stream[0][0],
+                               s->drain_stream[0][1], s->drain_stream[1][0], s->drain_stream[1][1]})
+            if (st)
+                (void)hipStreamDestroy(st);
+        delete s;
+        return sfail(code, "%s: %s", what, hipGetErrorString(e));
+    };
+    hipError_t e = hipGetDevice(&s->device);
+    if (e != hipSuccess)
+        return bail(SPLIT_EDEVICE, "no device", e);
+
+    // fixed device structures
+    const size_t jobs_b = a256(sizeof(splitk::ServeJob) * splitk::kServeMaxJobs);
+    const size_t queue_b = a256(sizeof(splitk::ServeQueue));
+    const size_t scratch_b =
+        a256((size_t)splitk::kServeScratchSlots * splitk::kTile * ((size_t)max_len + 1) * 4);
+    const size_t fixed = jobs_b + 2 * queue_b + scratch_b + 256;
+    size_t budget = budget_bytes;
+    if (budget == 0) { // a share of free device memory (adaptive batch size)
+        size_t fr = 0, tot = 0;
+        e = hipMemGetInfo(&fr, &tot);
+        if (e != hipSuccess)
+            return bail(SPLIT_EDEVICE, "memory info", e);
+        budget = fr / 4 * 3;
+    }
+    const size_t floor_b = (size_t)64 << 20;
+    if (budget < floor_b + fixed)
+        budget = floor_b + fixed;
+    // reserve, halving on out-of-memory down to the floor
+    for (;;) {
+        e = dev_alloc(reinterpret_cast<void **>(&s->dev_base), budget);
+        if (e == hipSuccess)
+            break;
+        (void)hipGetLastError();
+        if (e != hipErrorOutOfMemory || budget / 2 < floor_b + fixed)
+            return bail(SPLIT_ENOMEM, "cannot reserve device memory", e);
+        budget /= 2;
+    }
+    char *p = s->dev_base;
+    s->d_jobs = reinterpret_cast<splitk::ServeJob *>(p);
+    p += jobs_b;
+    s->d_queue[0] = reinterpret_cast<splitk::ServeQueue *>(p);
+    p += queue_b;
+    s->d_queue[1] = reinterpret_cast<splitk::ServeQueue *>(p);
+    p += queue_b;
+    s->d_scratch = reinterpret_cast<int *>(p);
+    p += scratch_b;
+    s->d_scratch_mask = reinterpret_cast<uint32_t *>(p);
+    p += 256;
+    s->arena_base = p;
+    s->arena.init(budget - fixed);
+    e = hipMemset(s->dev_base, 0, fixed);
+    if (e != hipSuccess)
+        return bail(SPLIT_EDEVICE, "clear server structures", e);
+
+    // pinned host memory: results, per-slot staging
+    s->stage_bytes = a256(sizeof(splitk::ServeJob)) +
+                     a256(((size_t)max_len + splitk::kTabPad) * sizeof(int2)) +
+                     a256((size_t)max_len * sizeof(int2)) + a256(sizeof(splitk::TourRec));
+    const size_t res_b = a256(sizeof(splitk::ServeResult) * splitk::kServeMaxJobs);
+    const size_t pin = res_b + s->stage_bytes * splitk::kServeMaxJobs;
+    e = hipHostMalloc(reinterpret_cast<void **>(&s->pin_base), pin, hipHostMallocCoherent);
+    if (e != hipSuccess)
+        return bail(SPLIT_ENOMEM, "pinned host memory", e);
+    memset(s->pin_base, 0, res_b);
+    char *h = s->pin_base;
+    s->h_results = reinterpret_cast<splitk::ServeResult *>(h);
+    h += res_b;
+    s->h_stage = h;
+
+    e = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&s->out_stream, hipStreamNonBlocking);
+    for (int q = 0; q < 2 && e == hipSuccess; ++q)
+        for (int k = 0; k < 2 && e == hipSuccess; ++k)
+            e = hipStreamCreateWithFlags(&s->drain_stream[q][k], hipStreamNonBlocking);
+    if (e != hipSuccess)
+        return bail(SPLIT_EDEVICE, "stream creation", e);
+    for (int k = 0; k < 8 && e == hipSuccess; ++k) {
+        hipEvent_t ev = nullptr;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess)
+            s->event_pool.push_back(ev);
+    }
+    if (e != hipSuccess)
+        return bail(SPLIT_EDEVICE, "event creation", e);
+    s->drain_grid[0] = splitk::serve_drain_grid(false);
+    s->drain_grid[1] = splitk::serve_drain_grid(true);
+    if (s->drain_grid[0] < 1 || s->drain_grid[1] < 1)
+        return bail(SPLIT_EDEVICE, "drain occupancy", hipGetLastError());
+    s->ctl.jobs = s->d_jobs;
+    s->ctl.results = s->h_results;
+    s->ctl.scratch = s->d_scratch;
+    s->ctl.scratch_mask = s->d_scratch_mask;
+    s->ctl.max_len = max_len;
+    int rate_khz = 0; // the device wall clock the drain waves read
+    e = hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, s->device);
+    if (e != hipSuccess || rate_khz <= 0)
+        rate_khz = 100000;
+    // a drain wave leaves after 20 us on an empty queue and takes no new
+    // tile after 1 ms, so retired memory comes back within a few ms
+    s->ctl.idle_ticks = (long long)rate_khz / 50; // 20 us
+    s->ctl.life_ticks = (long long)rate_khz;      // 1 ms
+    s->life_us = 1000;
+    e = hipEventCreateWithFlags(&s->pub_event, hipEventDisableTiming);
+    if (e != hipSuccess)
+        return bail(SPLIT_EDEVICE, "event creation", e);
+    s->slot_req.assign(splitk::kServeMaxJobs, nullptr);
+    for (int k = splitk::kServeMaxJobs - 1; k >= 0; --k)
+        s->free_slots.push_back(k);
+    s->worker = std::thread([s] { s->loop(); });
+    *out = s;
+    return SPLIT_OK;
+}
+
+int split_server_add_instance(split_server *s, const int32_t *dist, int32_t N,
+                              const int16_t *demands, int64_t S, int64_t *instance_id)
+{
+    splitk::clear_error();
+    if (!s || !dist || !demands || !instance_id)
+        return sfail(SPLIT_EINVAL, "null argument");
+    if (N < 1 || N >= 65535 || S < 1)
+        return sfail(SPLIT_EINVAL, "need 1 <= N < 65535 and S >= 1 (got N=%d S=%lld)", N,
+                     (long long)S);
+    Instance *in = new Instance();
+    in->N = N;
+    in->S = S;
+    in->dist.assign(dist, dist + ((size_t)N + 1) * ((size_t)N + 1));
+    const size_t bytes = a256((size_t)S * N * 2);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->failed) {
+            delete in;
+            return sfail(s->failed, "server failed: %s", s->fail_text);
+        }
+        if (bytes > s->arena.capacity()) {
+            delete in;
+            return sfail(SPLIT_ENOMEM, "instance needs %zu bytes, the budget holds %zu", bytes,
+                         s->arena.capacity());
+        }
+        if (!s->arena.alloc(bytes, &in->off)) {
+            delete in;
+            return sfail(SPLIT_EAGAIN, "no room for the instance now (%zu bytes in use)",
+                         s->arena.used());
+        }
+        in->bytes = bytes;
+        in->id = s->next_inst++;
+        s->instances[in->id] = in;
+    }
+    // the block was free and no running drain touched it since it was freed
+    hipError_t e = hipMemcpy(s->arena_base + in->off, demands, (size_t)S * N * 2,
+                             hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->arena.release(in->off, in->bytes);
+        s->instances.erase(in->id);
+        delete in;
+        return sfail(SPLIT_EDEVICE, "copy demands: %s", hipGetErrorString(e));
+    }
+    *instance_id = in->id;
+    return SPLIT_OK;
+}
+
+int split_server_remove_instance(split_server *s, int64_t instance_id)
+{
+    splitk::clear_error();
+    if (!s)
+        return sfail(SPLIT_EINVAL, "null server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->instances.find(instance_id);
+    if (it == s->instances.end() || it->second->transient || it->second->removed)
+        return sfail(SPLIT_EINVAL, "unknown instance %lld", (long long)instance_id);
+    Instance *in = it->second;
+    in->removed = true;
+    if (in->refs == 0) {
+        s->deferred.push_back(Deferred{s->next_drain_id, in->off, in->bytes, -1});
+        s->deferred_bytes += Arena::round(in->bytes);
+        s->instances.erase(it);
+        delete in;
+    }
+    s->cv_work.notify_one();
+    return SPLIT_OK;
+}
+
+int split_server_submit(split_server *s, int64_t instance_id, const int32_t *tour, int32_t n,
+                        int32_t Q, int32_t *costs_out, int64_t *id)
+{
+    splitk::clear_error();
+    if (!s || !id || (n > 0 && !tour))
+        return sfail(SPLIT_EINVAL, "null argument");
+    if (n < 0 || n > s->max_len || Q < 0)
+        return sfail(SPLIT_EINVAL, "need 0 <= n <= %d and Q >= 0 (got n=%d Q=%d)", s->max_len, n,
+                     Q);
+    Instance *in = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->instances.find(instance_id);
+        if (it == s->instances.end() || it->second->removed || it->second->transient)
+            return sfail(SPLIT_EINVAL, "unknown instance %lld", (long long)instance_id);
+        in = it->second;
+        in->refs++; // held until the request retires
+    }
+    Request *r = new Request();
+    r->inst = in;
+    r->costs_out = costs_out;
+    const int rc = prepare(r, tour, n, *in, Q);
+    if (rc != SPLIT_OK) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        in->refs--;
+        delete r;
+        return rc;
+    }
+    if (s->footprint(*r) > s->arena.capacity()) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        in->refs--;
+        const size_t need = s->footprint(*r);
+        delete r;
+        return sfail(SPLIT_ENOMEM, "request needs %zu bytes, the budget holds %zu", need,
+                     s->arena.capacity());
+    }
+    return enqueue(s, r, id);
+}
+
+int split_server_submit_copy(split_server *s, const int32_t *tour, int32_t n, const int32_t *dist,
+                             int32_t N, const int16_t *demands, int64_t S, int32_t Q,
+                             int32_t *costs_out, int64_t *id)
+{
+    splitk::clear_error();
+    if (!s || !id || !dist || !demands || (n > 0 && !tour))
+        return sfail(SPLIT_EINVAL, "null argument");
+    if (n < 0 || n > s->max_len || Q < 0 || N < 1 || N >= 65535 || S < 1)
+        return sfail(SPLIT_EINVAL, "bad sizes n=%d N=%d S=%lld Q=%d", n, N, (long long)S, Q);
+    Instance *in = new Instance();
+    in->N = N;
+    in->S = S;
+    in->transient = true;
+    in->refs = 1;
+    in->dist.assign(dist, dist + ((size_t)N + 1) * ((size_t)N + 1));
+    Request *r = new Request();
+    r->inst = in;
+    r->costs_out = costs_out;
+    const int rc = prepare(r, tour, n, *in, Q);
+    if (rc != SPLIT_OK) {
+        delete r;
+        delete in;
+        return rc;
+    }
+    const size_t need = s->footprint(*r);
+    if (need > s->arena.capacity()) {
+        delete r;
+        delete in;
+        return sfail(SPLIT_ENOMEM, "request needs %zu bytes, the budget holds %zu", need,
+                     s->arena.capacity());
+    }
+    in->h_dem.assign(demands, demands + (size_t)S * N);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        in->id = -(s->next_inst++); // transient ids are negative (never looked up)
+        s->instances[in->id] = in;
+    }
+    return enqueue(s, r, id);
 }
 
 int split_server_poll(split_server *s, int64_t id, int64_t *sum, double *mean, double *latency_s)
@@ -392,10 +1008,11 @@ int split_server_poll(split_server *s, int64_t id, int64_t *sum, double *mean, d
         *mean = r->mean;
     if (latency_s)
         *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
-    free_request(r);
+    delete r;
     if (rc == SPLIT_EINVAL)
-        return sfail(rc, "request %lld: invalid input found on the device", (long long)id);
-    return rc == SPLIT_OK ? SPLIT_OK : sfail(rc, "request %lld failed on the device", (long long)id);
+        return sfail(rc, "request %lld: negative demand found on the device", (long long)id);
+    return rc == SPLIT_OK ? SPLIT_OK
+                          : sfail(rc, "request %lld failed on the device", (long long)id);
 }
 
 int split_server_wait(split_server *s, int64_t id)
@@ -404,32 +1021,37 @@ int split_server_wait(split_server *s, int64_t id)
     if (!s)
         return sfail(SPLIT_EINVAL, "null server");
     std::unique_lock<std::mutex> lk(s->mu);
-    auto it = s->all.find(id);
-    if (it == s->all.end())
+    if (s->all.find(id) == s->all.end())
         return sfail(SPLIT_EINVAL, "unknown request id %lld", (long long)id);
-    Request *r = it->second;
-    s->cv_done.wait(lk, [&] { return r->state == DONE; });
+    // the request is looked up again at every wake-up: another thread may
+    // have polled (and freed) it meanwhile
+    s->cv_done.wait(lk, [&] {
+        auto it = s->all.find(id);
+        return it == s->all.end() || it->second->state == DONE;
+    });
     return SPLIT_OK;
 }
 
-int split_server_stats(split_server *s, int64_t *submitted, int64_t *completed, int64_t *pending,
-                       size_t *bytes_in_use, size_t *peak_bytes)
+int split_server_stats(split_server *s, split_server_stats_t *out)
 {
     splitk::clear_error();
-    if (!s)
-        return sfail(SPLIT_EINVAL, "null server");
+    if (!s || !out)
+        return sfail(SPLIT_EINVAL, "null argument");
     std::lock_guard<std::mutex> lk(s->mu);
-    if (submitted)
-        *submitted = s->submitted;
-    if (completed)
-        *completed = s->completed;
-    if (pending)
-        *pending = (int64_t)s->pending.size();
-    if (bytes_in_use)
-        *bytes_in_use = s->arena.used();
-    if (peak_bytes)
-        *peak_bytes = s->arena.peak();
-    return SPLIT_OK;
+    out->submitted = s->submitted;
+    out->completed = s->completed;
+    out->pending = (int64_t)s->pending.size();
+    out->running = (int64_t)s->running.size();
+    out->bytes_in_use = s->arena.used();
+    out->peak_bytes = s->arena.peak();
+    out->capacity = s->arena.capacity();
+    out->drains = s->drains_launched;
+    out->deferred_bytes = s->deferred_bytes;
+    out->blocked_rounds = s->blocked;
+    out->instances = 0;
+    for (auto &kv : s->instances)
+        out->instances += kv.second->transient ? 0 : 1;
+    return s->failed ? sfail(s->failed, "server failed: %s", s->fail_text) : SPLIT_OK;
 }
 
 int split_server_destroy(split_server *s)
@@ -444,11 +1066,22 @@ int split_server_destroy(split_server *s)
     s->cv_work.notify_all();
     if (s->worker.joinable())
         s->worker.join();
+    (void)hipStreamSynchronize(s->copy_stream);
+    (void)hipDeviceSynchronize();
     for (auto &kv : s->all)
-        free_request(kv.second);
-    for (auto &st : s->streams)
-        (void)hipStreamDestroy(st);
-    (void)hipFree(s->arena_base);
+        delete kv.second;
+    for (auto &kv : s->instances)
+        delete kv.second;
+    for (hipEvent_t ev : s->event_pool)
+        (void)hipEventDestroy(ev);
+    if (s->pub_event)
+        (void)hipEventDestroy(s->pub_event);
+    for (hipStream_t st : {s->copy_stream, s->out_stream, s->drain_stream[0][0],
+                           s->drain_stream[0][1], s->drain_stream[1][0], s->drain_stream[1][1]})
+        if (st)
+            (void)hipStreamDestroy(st);
+    (void)hipFree(s->dev_base);
+    (void)hipHostFree(s->pin_base);
     delete s;
     return SPLIT_OK;
 }

@@ -1,8 +1,15 @@
-"""Served form on the GPU: continuous batching under an HBM budget.
+"""Served form on the GPU: continuous batching under an HBM budget, drained
+at tile granularity.
 
 Each request's result must be the same alone and in the mix (exactly: all
-results are integers and one IEEE division), and equal to the oracle's."""
+results are integers and one IEEE division), and equal to the oracle's.
+Both drains are covered (pools of at most 256 customers staged in LDS,
+larger pools streamed from the tour-ordered copy), both request forms
+(resident instances, requests that bring their own instance), the exact
+fallback, admission under a budget that forces queueing, the
+reservation's halving on out-of-memory, and concurrent clients."""
 import sys
+import threading
 
 import numpy as np
 import pytest
@@ -27,90 +34,218 @@ def binding():
     return b
 
 
-def _requests(seed, count, n_hi=1000, S_hi=20_000):
+def _instances(seed, count, n_hi=1000, S_hi=20_000):
     rng = np.random.default_rng(seed)
     out = []
     for k in range(count):
         n = int(rng.integers(1, n_hi + 1)) if k % 5 else int(rng.integers(1, 40))
         S = int(rng.integers(1, S_hi)) if k % 3 else int(rng.integers(1, 200))
         Q = int(rng.choice([80, 150, 300]))
-        inst = W.plain_normal(int(rng.integers(0, 2**31 - 1)), n, S, Q)
-        out.append(inst)
+        out.append(W.plain_normal(int(rng.integers(0, 2**31 - 1)), n, S, Q))
     return out
 
 
-def _dev(inst):
-    d = torch.from_numpy(np.ascontiguousarray(inst.dist)).cuda()
-    q = torch.from_numpy(np.ascontiguousarray(inst.demands)).cuda()
-    return d, q
+def _ref(inst, tour=None):
+    tours = inst.tours if tour is None else np.asarray(tour, np.int32)
+    lens = np.array([tours.size], np.int32)
+    r = oracle.split_eval(tours, lens, inst.dist, inst.demands, inst.Q, nthreads=8)
+    return r["costs"][0], int(r["sums"][0]), float(r["means"][0])
+
+
+def _same(res, ref, label):
+    costs, sm, mn = ref
+    assert np.array_equal(res["costs"], costs), label
+    assert res["sum"] == sm, label
+    assert np.float64(res["mean"]).tobytes() == np.float64(mn).tobytes(), label
 
 
 def test_alone_equals_mix_equals_oracle(binding):
-    reqs = _requests(31, 24)
-    devs = [_dev(r) for r in reqs]
-    srv = binding.Server(2 << 30, streams=4)
+    insts = _instances(31, 24)
+    srv = binding.Server(4 << 30, max_len=1024)
+    ids = []
+    for inst in insts:
+        ids.append(srv.add_instance(inst.dist, inst.demands))
+    rng = np.random.default_rng(77)
+    # every instance with its own tour and a second, reversed tour
+    work = []
+    for inst, iid in zip(insts, ids):
+        work.append((inst, iid, inst.tours))
+        work.append((inst, iid, inst.tours[::-1].copy()))
     alone = []
-    for inst, (d, q) in zip(reqs, devs):
+    for inst, iid, tour in work:
         _say("alone " + inst.name)
-        rid = srv.submit(inst.tours, d, q, inst.Q, want_costs=True)
-        alone.append(srv.wait(rid))
-    _say("mix of %d" % len(reqs))
-    ids = [srv.submit(inst.tours, d, q, inst.Q, want_costs=True) for inst, (d, q) in zip(reqs, devs)]
-    mix = [srv.wait(i) for i in ids]
+        alone.append(srv.wait(srv.submit(iid, tour, inst.Q, inst.S, want_costs=True)))
+    _say("mix of %d" % len(work))
+    order = rng.permutation(len(work))
+    rids = {}
+    for k in order:
+        inst, iid, tour = work[k]
+        rids[k] = srv.submit(iid, tour, inst.Q, inst.S, want_costs=True)
+    mix = {k: srv.wait(r) for k, r in rids.items()}
     st = srv.stats()
     srv.close()
-    assert st["peak_bytes"] <= 2 << 30
-    for inst, a, m in zip(reqs, alone, mix):
-        assert np.array_equal(a["costs"], m["costs"]), inst.name
-        assert a["sum"] == m["sum"] and a["mean"] == m["mean"], inst.name
-        ref = oracle.split_eval(inst.tours, inst.lens, inst.dist, inst.demands, inst.Q, nthreads=8)
-        assert np.array_equal(m["costs"], ref["costs"][0]), inst.name
-        assert m["sum"] == ref["sums"][0] and m["mean"] == ref["means"][0], inst.name
-        assert m["latency_s"] > 0
+    assert st["peak_bytes"] <= st["capacity"]
+    assert st["completed"] == 2 * len(work)
+    for k, (inst, iid, tour) in enumerate(work):
+        ref = _ref(inst, tour)
+        _same(alone[k], ref, "alone " + inst.name)
+        _same(mix[k], ref, "mix " + inst.name)
+        assert mix[k]["latency_s"] > 0
 
 
-def test_tight_budget_admits_one_at_a_time(binding):
-    reqs = _requests(32, 6, n_hi=300, S_hi=5000)
-    devs = [_dev(r) for r in reqs]
-    # find the largest footprint by admitting alone with a generous budget
-    srv = binding.Server(1 << 30, streams=2)
-    peaks = []
-    for inst, (d, q) in zip(reqs, devs):
-        srv.wait(srv.submit(inst.tours, d, q, inst.Q))
-    big = srv.stats()["peak_bytes"]
-    srv.close()
-    srv = binding.Server(big, streams=4)
-    ids = [srv.submit(inst.tours, d, q, inst.Q, want_costs=True) for inst, (d, q) in zip(reqs, devs)]
-    res = [srv.wait(i) for i in ids]
+def test_requests_with_their_own_instance(binding):
+    insts = _instances(41, 10, n_hi=600, S_hi=8000)
+    srv = binding.Server(2 << 30, max_len=1024)
+    rids = [srv.submit_copy(inst.tours, inst.dist, inst.demands, inst.Q, want_costs=True) for inst in insts]
+    res = [srv.wait(r) for r in rids]
     st = srv.stats()
     srv.close()
-    assert st["peak_bytes"] <= big
-    for inst, r in zip(reqs, res):
-        ref = oracle.split_eval(inst.tours, inst.lens, inst.dist, inst.demands, inst.Q)
-        assert np.array_equal(r["costs"], ref["costs"][0]) and r["sum"] == ref["sums"][0]
-    del peaks
+    assert st["bytes_in_use"] == 0, "own instances are released at completion"
+    for inst, r in zip(insts, res):
+        _say("own instance " + inst.name)
+        _same(r, _ref(inst), inst.name)
+
+
+@pytest.mark.parametrize("N", [120, 700])
+def test_exact_fallback_tiles(binding, N):
+    """Windows past the 64-entry register ring (unit demands, large Q) and
+    demands past a byte take the exact path inside the drain."""
+    rng = np.random.default_rng(N)
+    dist = W.dist_round(W.coords(rng, N))
+    tour = (rng.permutation(N) + 1).astype(np.int32)
+    dem = rng.integers(1, 12, size=(64 * 7 + 5, N)).astype(np.int16)
+    dem[64:128] = 1                                      # windows of ~100 positions at Q = 300
+    dem[64 * 3:64 * 4] = rng.integers(200, 300, size=(64, N))  # past a byte, hard capacity 300
+    srv = binding.Server(1 << 30, max_len=1024)
+    iid = srv.add_instance(dist, dem)
+    for Q in (300, 120):
+        _say("fallback N=%d Q=%d" % (N, Q))
+        r = srv.wait(srv.submit(iid, tour, Q, dem.shape[0], want_costs=True))
+        inst = W.Instance(name="fb", tours=tour, lens=np.array([N], np.int32), dist=dist, demands=dem, Q=Q,
+                          seed=N)
+        _same(r, _ref(inst), "fallback N=%d Q=%d" % (N, Q))
+    srv.close()
+
+
+def test_budget_forces_queueing(binding):
+    """A budget that holds about two requests: the rest wait for memory,
+    every result is still exact and the arena never exceeds the budget."""
+    insts = _instances(32, 8, n_hi=400, S_hi=6000)
+    base = binding.Server(1 << 30, max_len=512)
+    ids = [base.add_instance(i.dist, i.demands) for i in insts]
+    resident = base.stats()["bytes_in_use"]
+    peak = 0
+    for inst, iid in zip(insts, ids):
+        base.wait(base.submit(iid, inst.tours, inst.Q))
+        peak = max(peak, base.stats()["peak_bytes"] - resident)
+    base.close()
+    budget = resident + 2 * peak + (96 << 20)  # fixed structures take part of the reservation
+    srv = binding.Server(budget, max_len=512)
+    ids = [srv.add_instance(i.dist, i.demands) for i in insts]
+    rids = [srv.submit(iid, inst.tours, inst.Q, inst.S, want_costs=True) for inst, iid in zip(insts, ids)]
+    res = [srv.wait(r) for r in rids]
+    st = srv.stats()
+    srv.close()
+    assert st["peak_bytes"] <= st["capacity"]
+    for inst, r in zip(insts, res):
+        _same(r, _ref(inst), "queued " + inst.name)
+
+
+def test_reservation_halves_on_out_of_memory(binding):
+    """The paper's batch loop retries with a smaller batch after an
+    out-of-memory error; the server's reservation does the same."""
+    binding.debug_fail_allocations(0)
+    full = binding.Server(1 << 30, max_len=256)
+    cap_full = full.stats()["capacity"]
+    full.close()
+    binding.debug_fail_allocations(2)
+    try:
+        srv = binding.Server(1 << 30, max_len=256)
+    finally:
+        binding.debug_fail_allocations(0)
+    cap = srv.stats()["capacity"]
+    assert cap < cap_full // 3, (cap, cap_full)
+    inst = W.plain_normal(7, 150, 3000, 150)
+    iid = srv.add_instance(inst.dist, inst.demands)
+    r = srv.wait(srv.submit(iid, inst.tours, inst.Q, inst.S, want_costs=True))
+    srv.close()
+    _same(r, _ref(inst), "after halving")
+
+
+def test_concurrent_clients(binding):
+    insts = _instances(33, 6, n_hi=300, S_hi=3000)
+    srv = binding.Server(1 << 30, max_len=512)
+    ids = [srv.add_instance(i.dist, i.demands) for i in insts]
+    out = {}
+    errors = []
+
+    def client(k):
+        try:
+            got = []
+            for rep in range(4):
+                inst, iid = insts[(k + rep) % len(insts)], ids[(k + rep) % len(insts)]
+                rid = srv.submit(iid, inst.tours, inst.Q, inst.S, want_costs=True)
+                got.append(((k + rep) % len(insts), srv.wait(rid)))
+            out[k] = got
+        except Exception as e:  # reported below
+            errors.append(e)
+
+    threads = [threading.Thread(target=client, args=(k,)) for k in range(6)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    srv.close()
+    assert not errors, errors
+    refs = [_ref(i) for i in insts]
+    for k, got in out.items():
+        for idx, r in got:
+            _same(r, refs[idx], "client %d" % k)
 
 
 def test_oversized_request_and_bad_input(binding):
     inst = W.plain_normal(5, 200, 5000, 150)
-    d, q = _dev(inst)
-    srv = binding.Server(1 << 16, streams=1)
+    srv = binding.Server(1 << 20, max_len=256)  # raised to the 64 MiB floor
+    cap = srv.stats()["capacity"]
+    big = np.ones((cap // (2 * 200) + 64, 200), np.int16)  # demands past the whole budget
     with pytest.raises(binding.SplitError) as e:
-        srv.submit(inst.tours, d, q, inst.Q)
+        srv.add_instance(inst.dist, big)
     assert e.value.code == binding.SPLIT_ENOMEM
+    with pytest.raises(binding.SplitError) as e:
+        srv.submit_copy(inst.tours, inst.dist, big, inst.Q)
+    assert e.value.code == binding.SPLIT_ENOMEM
+    del big
+    srv.close()
+    srv = binding.Server(1 << 30, max_len=256)
+    iid = srv.add_instance(inst.dist, inst.demands)
     bad = inst.tours.copy()
     bad[3] = 0
     with pytest.raises(binding.SplitError) as e:
-        srv.submit(bad, d, q, inst.Q)
+        srv.submit(iid, bad, inst.Q)
     assert e.value.code == binding.SPLIT_EINVAL
-    srv.close()
-    # a negative travel cost is found on the device and reported at poll
-    dist = inst.dist.copy()
-    dist[0, inst.tours[0]] = -4
-    d2 = torch.from_numpy(dist).cuda()
-    srv = binding.Server(1 << 30, streams=1)
-    rid = srv.submit(inst.tours, d2, q, inst.Q)
+    bad[3] = 10 ** 6  # an id far past the cost matrix is rejected before it is read
+    with pytest.raises(binding.SplitError) as e:
+        srv.submit(iid, bad, inst.Q)
+    assert e.value.code == binding.SPLIT_EINVAL
+    with pytest.raises(binding.SplitError) as e:
+        srv.submit(iid + 100, inst.tours, inst.Q)
+    assert e.value.code == binding.SPLIT_EINVAL
+    long_tour = np.ones(300, np.int32)
+    with pytest.raises(binding.SplitError) as e:  # longer than the server's max_len
+        srv.submit(iid, long_tour, inst.Q)
+    assert e.value.code == binding.SPLIT_EINVAL
+    # a negative demand is found on the device and reported at poll
+    dem = inst.demands.copy()
+    dem[17, inst.tours[5] - 1] = -3
+    iid2 = srv.add_instance(inst.dist, dem)
+    rid = srv.submit(iid2, inst.tours, inst.Q)
     with pytest.raises(binding.SplitError) as e:
         srv.wait(rid)
     assert e.value.code == binding.SPLIT_EINVAL
+    # the server keeps serving after a rejected request
+    r = srv.wait(srv.submit(iid, inst.tours, inst.Q, inst.S, want_costs=True))
+    _same(r, _ref(inst), "after errors")
+    srv.remove_instance(iid)
+    srv.remove_instance(iid2)
+    assert srv.stats()["instances"] == 0
     srv.close()
