@@ -306,6 +306,38 @@ int split_ou_transitions_device(int32_t U, int32_t T, int64_t B, int32_t R,
                                 int32_t rho, int32_t *d_A, split_stream_t stream);
 
 /*
+ * split_ou_dp_device -- the whole order-up-to inventory DP in one launch
+ * (App. B: the illustrative matrix form and its note on parallelism over
+ * scenarios x transitions x route options, with the minimum taken first
+ * over route options and then over predecessor states; the batched DP
+ * records its minimisers).  For valid inputs the results are exactly those
+ * of split_ou_transitions_device followed by split_minplus_forward_device
+ * (shared = 0) on the same arguments, but no transition matrix is formed:
+ * from level I with day demand d the no-delivery action lands on
+ * max(0, I - d) and the delivery of U - I on max(0, U - d), so each level
+ * has one no-delivery predecessor (level 0: every I <= d) and the delivery
+ * level every I < U.
+ *   d_demand, d_opt_cost, d_opt_cap, d_h, u, rho: as split_ou_transitions_device
+ *   d_J0     int32 [B][U+1]  initial cost-to-go (INT32_MAX where not allowed;
+ *            a negative entry reads as +inf)
+ *   d_JT     out int32 [B][U+1]  J_T
+ *   d_arg    out int32 [T][B][U+1] (may be NULL): the smallest predecessor
+ *            level attaining J_{t+1}(J), -1 where it is +inf (the layout of
+ *            split_minplus_forward_device, so split_minplus_backtrack_device
+ *            recovers the state paths)
+ *   d_status out int32 (may be NULL): 0, or 1 when a negative demand,
+ *            option cost or h entry was read (results then unspecified;
+ *            every access stays in bounds)
+ *   0 <= U <= 31, T >= 1, 1 <= B < 2^31, 1 <= R <= 64, u, rho >= 0.
+ * Device pointers, enqueued on `stream`; SPLIT_EINVAL on bad sizes or null
+ * required pointers, before anything is enqueued.
+ */
+int split_ou_dp_device(int32_t U, int32_t T, int64_t B, int32_t R, const int32_t *d_demand,
+                       const int32_t *d_opt_cost, const int32_t *d_opt_cap, const int32_t *d_h,
+                       int32_t u, int32_t rho, const int32_t *d_J0, int32_t *d_JT,
+                       int32_t *d_arg, int32_t *d_status, split_stream_t stream);
+
+/*
  * First-stage candidate search: a genetic algorithm over giant tours whose
  * candidates are all evaluated on every scenario by the batched split (the
  * paper's candidate-based scheme, Sec. 4 "decision quality under fixed

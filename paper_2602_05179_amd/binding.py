@@ -25,6 +25,7 @@ SPLIT_NO_PRED = 0xFFFF
 
 EXPORTED = (
     "split_last_error",
+    "split_ou_dp_device",
     "split_eval",
     "split_workspace_bytes",
     "split_eval_device",
@@ -183,6 +184,8 @@ def _load():
     lib.split_ou_transitions_device.argtypes = [i32, i32, i64, i32, P, P, P, P, i32, i32, P, P]
     lib.split_variant_device.argtypes = [P, i32, P, i32, P, i64, i32, i32, i32, P, P, P, sz, P]
     lib.split_routes_list_variants.argtypes = [ctypes.POINTER(i32), i32]
+    lib.split_ou_dp_device.restype = ctypes.c_int
+    lib.split_ou_dp_device.argtypes = [i32, i32, i64, i32, P, P, P, P, i32, i32, P, P, P, P, P]
     return lib
 
 
@@ -492,6 +495,30 @@ def minplus_forward(A, J0, *, shared, record_arg=True, stream=None):
     arg = torch.empty((T, B, m), dtype=torch.int32, device=J0.device) if record_arg else None
     _check(lib.split_minplus_forward_device(_dptr(A), 1 if shared else 0, T, m, B, _dptr(J0), _dptr(JT),
                                             _dptr(arg) if arg is not None else None, _stream_handle(stream)))
+    return JT, arg
+
+
+def ou_dp(U, demand, opt_cost, opt_cap, h, u, rho, J0, *, record_arg=True, status=None, stream=None):
+    """The order-up-to inventory DP in one launch (no transition matrices):
+    demand int32 [T, B], opt_cost / opt_cap int32 [T, B, R], h int32 [U+1],
+    J0 int32 [B, U+1].  Returns (J_T [B, U+1], arg [T, B, U+1] or None).
+    `status`: an int32 device tensor of one element that receives 1 when a
+    negative demand, option cost or h entry was read (else 0), or None."""
+    torch = _torch()
+    for name, t in (("demand", demand), ("opt_cost", opt_cost), ("opt_cap", opt_cap), ("h", h), ("J0", J0)):
+        _check_i32(name, t)
+    T, B = (int(x) for x in demand.shape)
+    R = int(opt_cost.shape[2])
+    m = int(U) + 1
+    if tuple(opt_cost.shape) != (T, B, R) or tuple(opt_cap.shape) != (T, B, R) or tuple(h.shape) != (m,) \
+            or tuple(J0.shape) != (B, m):
+        raise SplitError(SPLIT_EINVAL, "shape mismatch: demand %s opt_cost %s opt_cap %s h %s J0 %s" % (
+            tuple(demand.shape), tuple(opt_cost.shape), tuple(opt_cap.shape), tuple(h.shape), tuple(J0.shape)))
+    JT = torch.empty((B, m), dtype=torch.int32, device=J0.device)
+    arg = torch.empty((T, B, m), dtype=torch.int32, device=J0.device) if record_arg else None
+    _check(lib.split_ou_dp_device(int(U), T, B, R, _dptr(demand), _dptr(opt_cost), _dptr(opt_cap), _dptr(h),
+                                  int(u), int(rho), _dptr(J0), _dptr(JT), _dptr(arg) if arg is not None else None,
+                                  _dptr(status) if status is not None else None, _stream_handle(stream)))
     return JT, arg
 
 

@@ -394,6 +394,26 @@ int split_ou_transitions_device(int32_t U, int32_t T, int64_t B, int32_t R,
     return SPLIT_OK;
 }
 
+int split_ou_dp_device(int32_t U, int32_t T, int64_t B, int32_t R, const int32_t *d_demand,
+                       const int32_t *d_opt_cost, const int32_t *d_opt_cap, const int32_t *d_h,
+                       int32_t u, int32_t rho, const int32_t *d_J0, int32_t *d_JT,
+                       int32_t *d_arg, int32_t *d_status, split_stream_t stream)
+{
+    splitk::clear_error();
+    if (U < 0 || U + 1 > splitk::kOuMaxStates || T < 1 || B < 1 || B > (int64_t)INT32_MAX ||
+        R < 1 || R > 64)
+        return fail(SPLIT_EINVAL, "need 0 <= U < %d, T >= 1, 1 <= B < 2^31, 1 <= R <= 64 "
+                    "(got U=%d T=%d B=%lld R=%d)", splitk::kOuMaxStates, U, T, (long long)B, R);
+    if (u < 0 || rho < 0)
+        return fail(SPLIT_EINVAL, "u and rho must be >= 0");
+    if (!d_demand || !d_opt_cost || !d_opt_cap || !d_h || !d_J0 || !d_JT)
+        return fail(SPLIT_EINVAL, "null pointer argument");
+    HIP_TRY(splitk::launch_ou_dp(U, T, B, R, d_demand, d_opt_cost, d_opt_cap, d_h, u, rho, d_J0,
+                                 d_JT, d_arg, d_status, static_cast<hipStream_t>(stream)),
+            "launch");
+    return SPLIT_OK;
+}
+
 int split_profile_enable(int32_t on)
 {
     splitk::clear_error();

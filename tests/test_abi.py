@@ -248,6 +248,13 @@ def test_minplus_and_variant_entry_points_reject_bad_arguments_before_device_wor
                                (3, 1, 1, 65, 0, 0), (3, 1, 1, 2, -1, 0), (3, 1, 1, 2, 0, -1)):
         assert lib.split_ou_transitions_device(U, T, B, R, fake, fake, fake, fake, u, rho, fake, None) == \
             binding.SPLIT_EINVAL, (U, T, B, R, u, rho)
+    for U, T, B, R, u, rho in ((-1, 1, 1, 1, 0, 0), (32, 1, 1, 1, 0, 0), (3, 0, 1, 1, 0, 0), (3, 1, 0, 1, 0, 0),
+                               (3, 1, 1 << 31, 1, 0, 0), (3, 1, 1, 0, 0, 0), (3, 1, 1, 65, 0, 0), (3, 1, 1, 2, -1, 0),
+                               (3, 1, 1, 2, 0, -1)):
+        assert lib.split_ou_dp_device(U, T, B, R, fake, fake, fake, fake, u, rho, fake, fake, None, None, None) == \
+            binding.SPLIT_EINVAL, (U, T, B, R, u, rho)
+    assert lib.split_ou_dp_device(3, 1, 1, 1, fake, fake, fake, fake, 0, 0, None, fake, None, None, None) == \
+        binding.SPLIT_EINVAL
     f = lib.split_variant_device
     assert f(fake, 5, fake, 5, fake, 10, 3, 1 << 24, 0, fake, fake, fake, 1 << 20, None) == binding.SPLIT_EINVAL
     assert f(fake, 5, fake, 5, fake, 10, 3, 2, -1, fake, fake, fake, 1 << 20, None) == binding.SPLIT_EINVAL
