@@ -489,6 +489,29 @@ int split_plan_launch(split_plan *plan, split_stream_t stream);
 int split_plan_destroy(split_plan *plan);
 
 /*
+ * split_eval_device_noalloc -- split_eval_device for callers that cannot
+ * allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same arguments less the
+ * workspace, whose role a fixed device array inside the library takes
+ * (SPLIT_NOALLOC_SCRATCH_BYTES, 32 MiB; each device the library runs on
+ * holds its own copy until the process ends).  The call allocates nothing
+ * and issues no memset: the kernels clear what must start at zero.  Calls
+ * whose workspace (as split_workspace_bytes sizes it for the tile path)
+ * exceeds the array return SPLIT_EINVAL naming both sizes, before anything
+ * is enqueued; the tour-ordered demand copy is never used, so every call
+ * stages tiles in LDS.  Results equal split_eval_device's.  Calls that
+ * overlap on one device share the array and race: serialise them (one
+ * stream, or events) per device.
+ * split_noalloc_scratch_bytes returns the array's size.
+ */
+#define SPLIT_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int split_eval_device_noalloc(const int32_t *d_tours, const int32_t *d_lens, int32_t num_tours,
+                              int32_t max_len, const int32_t *d_dist, int32_t N,
+                              const int16_t *d_demands, int64_t S, int32_t Q, int32_t *d_costs,
+                              int64_t *d_sums, double *d_means, split_stream_t stream);
+size_t split_noalloc_scratch_bytes(void);
+
+/*
  * Served form (the serving loop around the split operator; the paper's
  * batch loop in App. B sizes batches from free GPU memory and retries
  * smaller batches on out-of-memory): continuous batching of evaluation

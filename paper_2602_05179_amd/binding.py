@@ -25,6 +25,8 @@ SPLIT_NO_PRED = 0xFFFF
 
 EXPORTED = (
     "split_last_error",
+    "split_eval_device_noalloc",
+    "split_noalloc_scratch_bytes",
     "split_ou_dp_device",
     "split_eval",
     "split_workspace_bytes",
@@ -186,6 +188,10 @@ def _load():
     lib.split_routes_list_variants.argtypes = [ctypes.POINTER(i32), i32]
     lib.split_ou_dp_device.restype = ctypes.c_int
     lib.split_ou_dp_device.argtypes = [i32, i32, i64, i32, P, P, P, P, i32, i32, P, P, P, P, P]
+    lib.split_eval_device_noalloc.restype = ctypes.c_int
+    lib.split_eval_device_noalloc.argtypes = [P, P, i32, i32, P, i32, P, i64, i32, P, P, P, P]
+    lib.split_noalloc_scratch_bytes.restype = sz
+    lib.split_noalloc_scratch_bytes.argtypes = []
     return lib
 
 
@@ -327,6 +333,27 @@ def split_eval_device(tours, lens, dist, demands, Q, *, max_len=None, out=None, 
                                  int(workspace.numel()), _stream_handle(stream)))
     out.workspace = workspace
     return out
+
+
+def split_eval_device_noalloc(tours, lens, dist, demands, Q, *, max_len=None, out=None, stream=None):
+    """split_eval_device with its scratch in the library's fixed device array
+    (no workspace argument, no allocation by the library).  Calls that
+    overlap on one device share that array and race."""
+    T = int(lens.numel())
+    N = int(dist.shape[0] - 1)
+    S = int(demands.shape[0])
+    if max_len is None:
+        max_len = int(lens.max().item()) if T else 0
+    out = out if out is not None else DeviceOutputs(T, S, demands.device)
+    _check(lib.split_eval_device_noalloc(_dptr(tours), _dptr(lens), T, int(max_len), _dptr(dist), N,
+                                         _dptr(demands), S, int(Q), _dptr(out.costs), _dptr(out.sums),
+                                         _dptr(out.means), _stream_handle(stream)))
+    return out
+
+
+def noalloc_scratch_bytes() -> int:
+    """Size of the fixed device array behind split_eval_device_noalloc."""
+    return int(lib.split_noalloc_scratch_bytes())
 
 
 def split_count_cells_device(tours, lens, demands, N, Q, *, stream=None):

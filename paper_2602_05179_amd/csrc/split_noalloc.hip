@@ -25,7 +25,7 @@
 
 namespace {
 
-constexpr size_t kScratchBytes = (size_t)32 << 20; // SPLIT_NOALLOC_SCRATCH_BYTES
+constexpr size_t kScratchBytes = SPLIT_NOALLOC_SCRATCH_BYTES;
 constexpr int kMaxDevices = 64;
 
 static __device__ __align__(256) char scratch[kScratchBytes];
@@ -56,6 +56,8 @@ int scratch_ptr(void **out)
 }
 
 } // namespace
+
+extern "C" size_t split_noalloc_scratch_bytes(void) { return kScratchBytes; }
 
 extern "C" int split_eval_device_noalloc(const int32_t *d_tours, const int32_t *d_lens,
                                          int32_t num_tours, int32_t max_len,

@@ -62,8 +62,10 @@ def test_noalloc_equals_device_form_twice(binding):
 
 
 def test_noalloc_rejects_sizes_past_the_array(binding):
+    # rejected on the host before any device work: the pointers are never used
     P = ctypes.c_void_p
     fake = P(256)
+    assert binding.noalloc_scratch_bytes() == 32 << 20
     rc = binding.lib.split_eval_device_noalloc(fake, fake, 64, 4000, fake, 4000, fake, 1_000_000, 150,
                                                fake, fake, fake, None)
     assert rc == binding.SPLIT_EINVAL and "scratch" in binding.last_error()
