@@ -525,10 +525,11 @@ def minplus_forward(A, J0, *, shared, record_arg=True, stream=None):
     return JT, arg
 
 
-def ou_dp(U, demand, opt_cost, opt_cap, h, u, rho, J0, *, record_arg=True, status=None, stream=None):
+def ou_dp(U, demand, opt_cost, opt_cap, h, u, rho, J0, *, record_arg=True, status=None, out=None, stream=None):
     """The order-up-to inventory DP in one launch (no transition matrices):
     demand int32 [T, B], opt_cost / opt_cap int32 [T, B, R], h int32 [U+1],
-    J0 int32 [B, U+1].  Returns (J_T [B, U+1], arg [T, B, U+1] or None).
+    J0 int32 [B, U+1].  Returns (J_T [B, U+1], arg [T, B, U+1] or None);
+    `out`: a (J_T, arg) pair of preallocated tensors to write instead.
     `status`: an int32 device tensor of one element that receives 1 when a
     negative demand, option cost or h entry was read (else 0), or None."""
     torch = _torch()
@@ -541,8 +542,15 @@ def ou_dp(U, demand, opt_cost, opt_cap, h, u, rho, J0, *, record_arg=True, statu
             or tuple(J0.shape) != (B, m):
         raise SplitError(SPLIT_EINVAL, "shape mismatch: demand %s opt_cost %s opt_cap %s h %s J0 %s" % (
             tuple(demand.shape), tuple(opt_cost.shape), tuple(opt_cap.shape), tuple(h.shape), tuple(J0.shape)))
-    JT = torch.empty((B, m), dtype=torch.int32, device=J0.device)
-    arg = torch.empty((T, B, m), dtype=torch.int32, device=J0.device) if record_arg else None
+    if out is not None:
+        JT, arg = out
+        _check_i32("JT", JT)
+        if tuple(JT.shape) != (B, m) or (arg is not None and (tuple(arg.shape) != (T, B, m) or
+                                                           not arg.is_contiguous() or arg.dtype != torch.int32)):
+            raise SplitError(SPLIT_EINVAL, "out tensors have the wrong shape or type")
+    else:
+        JT = torch.empty((B, m), dtype=torch.int32, device=J0.device)
+        arg = torch.empty((T, B, m), dtype=torch.int32, device=J0.device) if record_arg else None
     _check(lib.split_ou_dp_device(int(U), T, B, R, _dptr(demand), _dptr(opt_cost), _dptr(opt_cap), _dptr(h),
                                   int(u), int(rho), _dptr(J0), _dptr(JT), _dptr(arg) if arg is not None else None,
                                   _dptr(status) if status is not None else None, _stream_handle(stream)))

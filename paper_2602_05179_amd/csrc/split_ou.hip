@@ -71,7 +71,11 @@ __global__ __launch_bounds__(kWave) void ou_status_zero_kernel(int32_t *status)
 }
 
 // M: compile-time bound on the states (m = U + 1 <= M).  Grid: one wave per
-// 64 problems.  LDS: the lane columns (2M slots) and h.
+// 64 problems.  LDS: the lane columns (2M slots), one buffer that holds the
+// option scatter and serves as the transpose buffer for coalesced reads of
+// J_0 and writes of J_T and the minimisers (the 64 problems of a wave own a
+// contiguous [64][m] block of each), h and the unit transport cost of every
+// delivery size.
 template <int M>
 __global__ __launch_bounds__(kWave) void ou_dp_kernel(
     int32_t U, int32_t T, int64_t B, int32_t R, const int32_t *__restrict__ demand,
@@ -80,30 +84,49 @@ __global__ __launch_bounds__(kWave) void ou_dp_kernel(
     int32_t *__restrict__ JT, int32_t *__restrict__ arg, int32_t *__restrict__ status)
 {
     __shared__ uint32_t col[2 * M][kWave]; // col[s][lane]: J_t(s) for s < m, +inf after
+    // one buffer, two uses (one wave per workgroup, so its LDS operations
+    // keep program order): tm[s][lane], the cheapest route option by the
+    // first source it serves (live during step 1 of a day), and xp, the
+    // [lane][m] transpose buffer of J_0, J_T and the minimisers (step 3)
+    __shared__ uint32_t buf[M * kWave];
+    uint32_t(&tm)[M][kWave] = *reinterpret_cast<uint32_t(*)[M][kWave]>(buf);
+    uint32_t *xp = buf;
     __shared__ uint32_t hs[M];
+    __shared__ uint32_t uqs[M]; // u * (U - I), saturated
     const int lane = threadIdx.x;
-    const int64_t b = (int64_t)blockIdx.x * kWave + lane;
+    const int64_t b0 = (int64_t)blockIdx.x * kWave;
+    const int64_t b = b0 + lane;
     const bool live = b < B;
     const int m = U + 1;
+    const int rows = (int)min<int64_t>(kWave, B - b0); // problems of this wave
+    const int words = rows * m;                           // contiguous words per block
     bool bad = false;
     if (lane < M) {
         const int32_t hv = lane < m ? h[lane] : 0;
         bad = hv < 0;
-        hs[lane] = hv < 0 ? 0u : (uint32_t)hv;
+        hs[lane] = hv < 0 ? 0u : (uint32_t)hv; // levels past U: never added to a finite value
+        uqs[lane] = lane < U ? ou_clamp((uint64_t)(uint32_t)u * (uint64_t)(U - lane)) : kOuInf;
     }
     for (int s = m; s < 2 * M; ++s)
         col[s][lane] = kOuInf;
+    // J_0 of the wave's problems: coalesced words, then each lane its row
+    for (int w = lane; w < words; w += kWave)
+        xp[w] = min((uint32_t)J0[b0 * m + w], kOuInf);
     __syncthreads();
-
     uint32_t J[M];
 #pragma unroll
     for (int I = 0; I < M; ++I)
-        J[I] = (live && I < m) ? min((uint32_t)J0[b * m + I], kOuInf) : kOuInf;
+        J[I] = (live && I < m) ? xp[lane * m + I] : kOuInf;
 
     // day 0 inputs
     int nd = 0;
     int nc[kOuPre], ncap[kOuPre];
     const int RP = R < kOuPre ? R : kOuPre;
+#pragma unroll
+    for (int r = 0; r < kOuPre; ++r) {
+        nc[r] = 0;
+        ncap[r] = -1;
+    }
     if (live) {
         nd = demand[b];
 #pragma unroll
@@ -132,32 +155,26 @@ __global__ __launch_bounds__(kWave) void ou_dp_kernel(
                     ncap[r] = opt_cap[tn * R + r];
                 }
         }
-        if (!live) {
-            d = 0;
-#pragma unroll
-            for (int r = 0; r < kOuPre; ++r) {
-                c[r] = 0;
-                cap[r] = -1;
-            }
-        }
         bad = bad || d < 0;
-        d = max(d, 0);
+        d = live ? max(d, 0) : 0;
 
         // 1. cheapest option with room for the delivery q = U - I of every
-        //    source I < U (minimum over route options)
-        uint32_t tr[M];
+        //    source I < U (minimum over route options): option r serves
+        //    source I when cap_r >= U - I
+        //    option r serves the sources I >= U - cap_r: scatter its cost
+        //    to that first source (per-lane LDS column, atomic minimum),
+        //    then a prefix minimum over I
 #pragma unroll
         for (int I = 0; I < M; ++I)
-            tr[I] = kOuInf;
+            tm[I][lane] = kOuInf;
 #pragma unroll
         for (int r = 0; r < kOuPre; ++r) {
             if (r < RP) {
-                bad = bad || c[r] < 0;
-                const uint32_t cr = c[r] < 0 ? kOuInf : (uint32_t)c[r];
-#pragma unroll
-                for (int I = 0; I < M; ++I)
-                    if (cap[r] >= U - I)
-                        tr[I] = min(tr[I], cr);
+                bad = bad || (live && c[r] < 0);
+                const uint32_t cr = (c[r] < 0 || !live) ? kOuInf : (uint32_t)c[r];
+                const int first = max(U - cap[r], 0); // > M - 1: serves none
+                if (first < M)
+                    atomicMin(&tm[first][lane], cr);
             }
         }
         for (int r = kOuPre; r < R; ++r) { // options past the prefetched ones
@@ -165,76 +182,108 @@ __global__ __launch_bounds__(kWave) void ou_dp_kernel(
             const int kv = live ? opt_cap[tb * R + r] : -1;
             bad = bad || cv < 0;
             const uint32_t cr = cv < 0 ? kOuInf : (uint32_t)cv;
+            const int first = max(U - kv, 0);
+            if (first < M)
+                atomicMin(&tm[first][lane], cr);
+        }
+        uint32_t tr[M]; // (sources I >= U have no delivery: their u * (U - I) is +inf)
+        {
+            uint32_t run = kOuInf;
 #pragma unroll
-            for (int I = 0; I < M; ++I)
-                if (kv >= U - I)
-                    tr[I] = min(tr[I], cr);
+            for (int I = 0; I < M; ++I) {
+                run = min(run, tm[I][lane]);
+                tr[I] = run;
+            }
         }
 
         // 2. delivery: every source I < U lands on level Jd; no delivery:
-        //    sources I <= d land on level 0
+        //    sources I <= d land on level 0 (cost h[0] + rho (d - I))
         const int Jd = max(0, U - d);
         const uint32_t dconst =
             ou_sat(hs[Jd], ou_clamp((uint64_t)(uint32_t)rho * (uint64_t)(uint32_t)max(0, d - U)));
         const uint32_t h0 = hs[0];
         uint32_t bestD = kOuInf, best0 = kOuInf;
         int argD = -1, arg0 = -1;
+        // no delivery into level 0 costs h[0] + rho (d - I): in 32 bits
+        // (c0 - rho I) when rho d and h[0] stay below 2^30 on every lane of
+        // the wave, else exactly through the high product
+        const uint32_t rd_hi = __umulhi((uint32_t)rho, (uint32_t)d);
+        const uint32_t rd_lo = (uint32_t)rho * (uint32_t)d;
+        const bool small = rd_hi == 0u && rd_lo < (1u << 30) && h0 < (1u << 30);
+        const uint32_t c0 = h0 + rd_lo;
+        // levels I >= m hold +inf throughout, so every term they give is +inf
+        if (__all(small)) {
 #pragma unroll
-        for (int I = 0; I < M; ++I) {
-            if (I < m) {
+            for (int I = 0; I < M; ++I) {
                 col[I][lane] = J[I];
-                if (I < U) {
-                    const uint32_t uq = ou_clamp((uint64_t)(uint32_t)u * (uint64_t)(U - I));
-                    const uint32_t v = ou_sat(J[I], ou_sat(ou_sat(tr[I], uq), dconst));
-                    if (v < bestD) {
-                        bestD = v;
-                        argD = I;
-                    }
-                }
-                if (I <= d) {
-                    const uint32_t sh = ou_clamp((uint64_t)(uint32_t)rho * (uint64_t)(uint32_t)(d - I));
-                    const uint32_t v = ou_sat(J[I], ou_sat(h0, sh));
-                    if (v < best0) {
-                        best0 = v;
-                        arg0 = I;
-                    }
-                }
+                const uint32_t v = ou_sat(J[I], ou_sat(ou_sat(tr[I], uqs[I]), dconst));
+                const bool lt = v < bestD;
+                bestD = lt ? v : bestD;
+                argD = lt ? I : argD;
+                const uint32_t v0 = I <= d ? min(J[I] + (c0 - (uint32_t)rho * (uint32_t)I), kOuInf)
+                                           : kOuInf;
+                const bool lt0 = v0 < best0;
+                best0 = lt0 ? v0 : best0;
+                arg0 = lt0 ? I : arg0;
+            }
+        } else {
+#pragma unroll
+            for (int I = 0; I < M; ++I) {
+                col[I][lane] = J[I];
+                const uint32_t v = ou_sat(J[I], ou_sat(ou_sat(tr[I], uqs[I]), dconst));
+                const bool lt = v < bestD;
+                bestD = lt ? v : bestD;
+                argD = lt ? I : argD;
+                const uint32_t k = (uint32_t)max(d - I, 0);
+                const uint32_t lo = (uint32_t)rho * k;
+                const uint32_t hi = __umulhi((uint32_t)rho, k);
+                const uint32_t sh = (hi != 0u || lo > kOuInf) ? kOuInf : lo;
+                const uint32_t v0 = I <= d ? ou_sat(J[I], ou_sat(h0, sh)) : kOuInf;
+                const bool lt0 = v0 < best0;
+                best0 = lt0 ? v0 : best0;
+                arg0 = lt0 ? I : arg0;
             }
         }
 
-        // 3. every level: the shifted no-delivery term, merged with the
-        //    delivery minimum on level Jd (ties: the smallest source)
+        // 3. the delivery level merged once (ties: the smallest source):
+        //    its no-delivery term is J_t(Jd + d) + h[Jd] (level 0: best0)
         const int dd = d < m ? d : m; // reads past m - 1 hit the +inf slots
-        int32_t *argt = arg ? arg + tb * m : nullptr;
+        uint32_t vJ = Jd == 0 ? best0 : ou_sat(col[Jd + dd][lane], hs[Jd]);
+        int aJ = Jd == 0 ? arg0 : Jd + d;
+        if (bestD < vJ || (bestD == vJ && argD < aJ)) {
+            vJ = bestD;
+            aJ = argD;
+        }
+        // every level: the shifted no-delivery term, or the merged value
+        // (levels K >= m read +inf slots and stay +inf)
 #pragma unroll
         for (int K = 0; K < M; ++K) {
-            if (K < m) {
-                uint32_t v;
-                int a;
-                if (K == 0) {
-                    v = best0;
-                    a = arg0;
-                } else {
-                    v = ou_sat(col[K + dd][lane], hs[K]);
-                    a = K + d;
-                }
-                if (K == Jd && (bestD < v || (bestD == v && argD < a))) {
-                    v = bestD;
-                    a = argD;
-                }
-                J[K] = v;
-                if (argt && live)
-                    argt[K] = v >= kOuInf ? -1 : a;
-            }
+            uint32_t v = K == 0 ? best0 : ou_sat(col[K + dd][lane], hs[K]);
+            int a = K == 0 ? arg0 : K + d;
+            const bool atJ = K == Jd;
+            v = atJ ? vJ : v;
+            a = atJ ? aJ : a;
+            J[K] = v;
+            if (K < m)
+                xp[lane * m + K] = (uint32_t)(v >= kOuInf ? -1 : a);
+        }
+        if (arg) { // the wave's [64][m] block of day t, coalesced
+            __syncthreads();
+            int32_t *dst = arg + ((int64_t)t * B + b0) * m;
+            for (int w = lane; w < words; w += kWave)
+                dst[w] = (int32_t)xp[w];
+            __syncthreads();
         }
     }
-    if (live) {
+    __syncthreads();
 #pragma unroll
-        for (int K = 0; K < M; ++K)
-            if (K < m)
-                JT[b * m + K] = (int32_t)J[K];
-    }
-    if (status && __builtin_amdgcn_read_exec() != 0) {
+    for (int K = 0; K < M; ++K)
+        if (K < m)
+            xp[lane * m + K] = J[K];
+    __syncthreads();
+    for (int w = lane; w < words; w += kWave)
+        JT[b0 * m + w] = (int32_t)xp[w];
+    if (status) {
         const uint64_t any = __ballot(bad);
         if (any != 0 && lane == __builtin_ctzll(any))
             atomicOr(status, 1);
@@ -261,6 +310,9 @@ hipError_t launch_ou_dp(int32_t U, int32_t T, int64_t B, int32_t R, const int32_
                            demand, opt_cost, opt_cap, h, u, rho, J0, JT, arg, status);
     else if (m <= 16)
         hipLaunchKernelGGL(ou_dp_kernel<16>, dim3(blocks), dim3(kWave), 0, stream, U, T, B, R,
+                           demand, opt_cost, opt_cap, h, u, rho, J0, JT, arg, status);
+    else if (m <= 24)
+        hipLaunchKernelGGL(ou_dp_kernel<24>, dim3(blocks), dim3(kWave), 0, stream, U, T, B, R,
                            demand, opt_cost, opt_cap, h, u, rho, J0, JT, arg, status);
     else
         hipLaunchKernelGGL(ou_dp_kernel<kOuMaxStates>, dim3(blocks), dim3(kWave), 0, stream, U,
