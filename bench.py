@@ -102,31 +102,33 @@ def timed_steps(torch, fn, steps, warmup):
 
 def cpu_baseline(inst):
     """The oracle (as it stands) on a bounded sample of the same workload:
-    every scenario on all usable host threads, repeated until about 12 s of
-    CPU time (cores x wall) is spent, then one thread on a prefix."""
+    the median of at least five passes over every scenario on all usable
+    host threads (more passes while under about 12 s of CPU time), then one
+    thread on a prefix."""
+    import numpy as np
     import oracle
     cores = max(1, min(16, len(os.sched_getaffinity(0))))
-    reps, t_all, cells = 0, 0.0, 0.0
-    while reps == 0 or (t_all * cores < 12.0 and t_all < 30.0):
+    times, cells = [], 0.0
+    while len(times) < 5 or (sum(times) * cores < 12.0 and sum(times) < 30.0):
         t0 = time.perf_counter()
         r = oracle.split_eval(inst.tours, inst.lens, inst.dist, inst.demands, inst.Q, nthreads=cores)
-        t_all += time.perf_counter() - t0
-        cells += float(r["cells"].sum())
-        reps += 1
+        times.append(time.perf_counter() - t0)
+        cells = float(r["cells"].sum())
+    t_med = float(np.median(times))
     S_one = min(inst.S, 250_000)
     t0 = time.perf_counter()
     r1 = oracle.split_eval(inst.tours, inst.lens, inst.dist, inst.demands[:S_one], inst.Q, nthreads=1)
     t_one = time.perf_counter() - t0
     return {
-        "value": cells / t_all,
+        "value": cells / t_med,
         "unit": "cells/s",
         "cores": cores,
         "kind": "oracle",
-        "sample": "all %d scenarios x %d passes on %d threads (%.2f s wall, %.1f s CPU); scenarios/s %.4g; "
-                  "1 thread: first %d scenarios (%.2f s), %.4g cells/s" % (
-                      inst.S, reps, cores, t_all, t_all * cores, inst.S * reps / t_all, S_one, t_one,
+        "sample": "all %d scenarios, median of %d passes on %d threads (%.3f s per pass, %.1f s CPU in all); "
+                  "scenarios/s %.4g; 1 thread: first %d scenarios (%.2f s), %.4g cells/s" % (
+                      inst.S, len(times), cores, t_med, sum(times) * cores, inst.S / t_med, S_one, t_one,
                       float(r1["cells"].sum()) / t_one),
-        "cells_per_scenario_sample": cells / (inst.S * reps),
+        "cells_per_scenario_sample": cells / inst.S,
     }
 
 
@@ -161,19 +163,130 @@ def batched_vs_plain(torch, binding, W, reps):
         for tt, ll, oo, ww, ml in singles:
             binding.split_eval_device(tt, ll, d, q, inst.Q, max_len=ml, out=oo, workspace=ww)
 
-    t_plain = timed_steps(torch, plain, max(1, reps // 4), 1)
-    same = all(torch.equal(singles[k][2].costs[0], plan.out.costs[k]) for k in range(0, T, 17))
+    t_plain_host = timed_steps(torch, plain, max(1, reps // 4), 1)
+    # the same 256 one-tour launches captured in one graph, so that the
+    # comparison is between device work and not host launch overhead
+    t_plain_graph = None
+    try:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            plain()
+        torch.cuda.current_stream().wait_stream(side)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            plain()
+        t_plain_graph = timed_steps(torch, g.replay, reps, 2)
+    except RuntimeError as e:  # capture refused: keep the host-loop figure only
+        log("plain per-tour graph capture failed: %s" % e)
+    same = all(torch.equal(singles[k][2].costs[0], plan.out.costs[k]) for k in range(T))
+    same = same and all(torch.equal(singles[k][2].sums, plan.out.sums[k:k + 1]) for k in range(T))
     plan.close()
+    t_plain = t_plain_graph if t_plain_graph else t_plain_host
     return {
         "workload": inst.name,
         "cells": cells,
         "batched_graph_ms": t_graph * 1e3,
         "batched_graph_cells_per_s": cells / t_graph,
+        "batched_frac_valu_peak": cells / t_graph / 1e12 / VALU_PEAK_TOPS,
         "batched_eager_ms": t_eager * 1e3,
-        "plain_per_tour_ms": t_plain * 1e3,
+        "plain_per_tour_graph_ms": t_plain_graph * 1e3 if t_plain_graph else None,
+        "plain_per_tour_host_loop_ms": t_plain_host * 1e3,
         "plain_per_tour_cells_per_s": cells / t_plain,
         "speedup_batched_vs_plain": t_plain / t_graph,
+        "speedup_basis": "256 one-tour launches captured in one graph vs one batched graph" if t_plain_graph
+                         else "host loop of 256 one-tour launches vs one batched graph",
         "batched_equals_plain": bool(same),
+    }
+
+
+def latency_small(torch, binding, W, reps=400):
+    """Config n=20, S=1000, Q=30: latency of one evaluation (launch to
+    result on the host), p50/p99 over repeated calls, for the captured graph
+    (inputs resident), the eager device form and the host form (host
+    buffers in and out, copies included)."""
+    import numpy as np
+    inst = W.plain_small(1, S=1000)
+    tours, lens, dist, dem = W.as_arrays(inst)
+    dev = torch.device("cuda:0")
+    t, l, d, q = (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (tours, lens, dist, dem))
+    n = int(lens.max())
+    cells = int(binding.split_count_cells_device(t, l, q, inst.N, inst.Q).sum().item())
+    plan = binding.Plan(t, l, d, q, inst.Q, max_len=n)
+    ws = torch.empty(binding.workspace_bytes(1, n, inst.N, inst.S, inst.Q), dtype=torch.uint8, device=dev)
+    out = binding.DeviceOutputs(1, inst.S, dev)
+
+    def lat(fn):
+        for _ in range(20):
+            fn()
+        torch.cuda.synchronize()
+        xs = np.empty(reps)
+        for i in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            xs[i] = time.perf_counter() - t0
+        us = xs * 1e6
+        return {"p50_us": float(np.percentile(us, 50)), "p99_us": float(np.percentile(us, 99)),
+                "mean_us": float(us.mean())}
+
+    res = {"workload": inst.name + ", uniform demands U{1..10}, int32 rounded Euclidean costs",
+           "cells": cells, "reps": reps}
+    res["graph"] = lat(plan.launch)
+    res["eager"] = lat(lambda: binding.split_eval_device(t, l, d, q, inst.Q, max_len=n, out=out, workspace=ws))
+    res["host_form"] = lat(lambda: binding.split_eval(tours, lens, dist, dem, inst.Q))
+    res["graph_cells_per_s"] = cells / (res["graph"]["p50_us"] * 1e-6)
+    plan.close()
+    return res
+
+
+def medium_rotating(torch, binding, W, buffers=16, reps=48):
+    """Config n=100, S=10^5, Q=100 (20 MB of demands, small enough to sit in
+    the 256 MB Infinity Cache): the main kernel timed with HIP events while
+    the calls rotate over `buffers` device copies of the demand tensor, so
+    every call reads its demands from HBM."""
+    import numpy as np
+    inst = W.plain_medium(2, S=100_000)
+    tours, lens, dist, dem = W.as_arrays(inst)
+    dev = torch.device("cuda:0")
+    t, l, d = (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (tours, lens, dist))
+    qs = [torch.from_numpy(dem).to(dev) for _ in range(buffers)]
+    n, S = int(lens.max()), inst.S
+    cells = int(binding.split_count_cells_device(t, l, qs[0], inst.N, inst.Q).sum().item())
+    ws = torch.empty(binding.workspace_bytes(1, n, inst.N, S, inst.Q), dtype=torch.uint8, device=dev)
+    out = binding.DeviceOutputs(1, S, dev)
+    ref = None
+    for k in range(buffers):
+        binding.split_eval_device(t, l, d, qs[k], inst.Q, max_len=n, out=out, workspace=ws)
+        c = out.costs.clone()
+        ref = c if ref is None else ref
+        assert torch.equal(c, ref), "rotating buffers disagree"
+    torch.cuda.synchronize()
+    binding.profile_read()
+    binding.profile_enable(True)
+    t0 = time.perf_counter()
+    for i in range(reps):
+        binding.split_eval_device(t, l, d, qs[i % buffers], inst.Q, max_len=n, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    kms, launches = binding.profile_read()
+    binding.profile_enable(False)
+    kernel_s = kms / 1e3 / max(launches, 1)
+    alg_bytes = dem.nbytes + S * 4
+    t_valu = cells / (VALU_PEAK_TOPS * 1e12)
+    t_hbm = alg_bytes / (HBM_PEAK_GBS * 1e9)
+    return {
+        "workload": inst.name + ", demands round(Normal(mu,0.3mu))>=1, mu~U{1..20}; %d rotating demand buffers "
+                                "(%.0f MB)" % (buffers, buffers * dem.nbytes / 1e6),
+        "cells": cells,
+        "kernel_ms": kernel_s * 1e3,
+        "call_ms": wall * 1e3,
+        "cells_per_s": cells / kernel_s,
+        "scenarios_per_s": S / kernel_s,
+        "roofline": {"bound": "alu" if t_valu >= t_hbm else "hbm",
+                     "achieved_tops": cells / kernel_s / 1e12, "achieved_gbs": alg_bytes / kernel_s / 1e9,
+                     "frac": max(t_valu, t_hbm) / kernel_s, "algorithmic_bytes": alg_bytes,
+                     "t_valu_us": t_valu * 1e6, "t_hbm_us": t_hbm * 1e6},
     }
 
 
@@ -221,13 +334,19 @@ def route_recovery(torch, binding, t, d, q, inst, cells, eval_costs, steps, warm
 
 def split_variants(torch, binding, t, d, q, inst, cells, steps, warmup):
     """The split variants on the headline tour and scenarios: soft capacity
-    (overload penalty beta per unit, unlimited fleet) and a fleet bound K
-    (hard capacity; each of the K passes relaxes the same admissible
-    windows, so its algorithmic work is K times the plain split's cells)."""
+    (overload penalty beta per unit) and a fleet bound K (at most K routes).
+
+    Algorithmic work per pass (the roofline's unit, one int32 op each): the
+    hard split's Bellman cells; soft capacity adds two ops per position (a
+    predecessor that leaves the hard window joins one running minimum once,
+    and that minimum is combined with the window's).  A fleet bound of K
+    runs K passes over the same windows.  Bytes: demands read once, costs
+    written once."""
     dev = q.device
     n, S = int(t.numel()), inst.S
     out = binding.VariantOutputs(S, dev)
     res = {}
+    alg_bytes = q.numel() * 2 + S * 4
     for beta, K in ((10, 0), (-1, 25), (10, 25)):
         ws = torch.empty(binding.variant_workspace_bytes(n, inst.N, S, K), dtype=torch.uint8, device=dev)
 
@@ -237,13 +356,15 @@ def split_variants(torch, binding, t, d, q, inst, cells, steps, warmup):
         sec = timed_steps(torch, step, max(1, steps // 4), max(1, warmup // 2))
         status = int(out.status.item())
         key = "beta%d_K%d" % (beta, K)
-        entry = {"ms_per_call": sec * 1e3, "scenarios_per_s": S / sec, "status": status}
-        if beta < 0:
-            entry["cells_per_s"] = K * cells / sec
-        else:
-            # soft capacity admits every predecessor: the dense relaxation count
-            entry["dense_relaxations_per_s"] = (K or 1) * S * n * (n + 1) / 2 / sec
-        res[key] = entry
+        per_pass = cells + (2 * n * S if beta >= 0 else 0)
+        ops = (K or 1) * per_pass
+        t_valu = ops / (VALU_PEAK_TOPS * 1e12)
+        t_hbm = alg_bytes / (HBM_PEAK_GBS * 1e9)
+        res[key] = {"ms_per_call": sec * 1e3, "scenarios_per_s": S / sec, "status": status,
+                    "algorithmic_ops": ops, "ops_per_s": ops / sec,
+                    "roofline": {"bound": "alu" if t_valu >= t_hbm else "hbm", "unit": "TOP/s",
+                                 "achieved": ops / sec / 1e12, "peak": VALU_PEAK_TOPS,
+                                 "frac": max(t_valu, t_hbm) / sec, "basis": "whole call"}}
         del ws
     res["workload"] = "split variants of the same tour: n=%d, S=%d, Q=%d (beta: penalty per unit of " \
                       "overload, -1 = hard capacity; K: fleet bound, 0 = unlimited)" % (n, S, inst.Q)
@@ -251,44 +372,84 @@ def split_variants(torch, binding, t, d, q, inst, cells, steps, warmup):
 
 
 def inventory_minplus(torch, binding, W, steps, warmup):
-    """The order-up-to inventory DP on the generic min-plus update: transition
-    generator, forward pass with recorded minimisers, backtracking.  The
-    forward pass streams one int32 matrix per (day, problem): HBM-bound."""
+    """The order-up-to inventory DP: the fused kernel (route-option minimum,
+    predecessor minimum and recorded minimisers in one launch, no
+    transition matrices), then for comparison the two-pass form (transition
+    generator writing A, generic min-plus forward reading it), and the
+    backtracking.  Algorithmic bytes: demands and route options read once,
+    J_0 read, J_T and the minimisers written."""
     import numpy as np
     inst = W.inventory_ou()
     dev = torch.device("cuda:0")
     T, B = inst.demand.shape
+    R = inst.opt_cost.shape[2]
     m = inst.U + 1
     dem, cost, cap, h = (torch.from_numpy(np.ascontiguousarray(a)).to(dev)
                          for a in (inst.demand, inst.opt_cost, inst.opt_cap, inst.h))
     J0 = torch.full((B, m), int(binding.MINPLUS_INF), dtype=torch.int32, device=dev)
     J0[torch.arange(B, device=dev), torch.from_numpy(inst.I0.astype(np.int64)).to(dev)] = 0
+    res = {}
+    fJT = torch.empty((B, m), dtype=torch.int32, device=dev)
+    farg = torch.empty((T, B, m), dtype=torch.int32, device=dev)
+
+    def fused():
+        binding.ou_dp(inst.U, dem, cost, cap, h, inst.u, inst.rho, J0, out=(fJT, farg))
+
+    t_fused_call = timed_steps(torch, fused, steps, warmup)
+    # device time of the launch: a captured graph of `reps` calls, HIP events
+    reps = 20
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fused()
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(reps):
+            fused()
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    t_fused = e0.elapsed_time(e1) / 1e3 / reps
+    res["fused"] = (fJT, farg)
     A = binding.ou_transitions(inst.U, dem, cost, cap, h, inst.u, inst.rho)
     t_gen = timed_steps(torch, lambda: binding.ou_transitions(inst.U, dem, cost, cap, h, inst.u, inst.rho, out=A),
                         steps, warmup)
-    res = {}
 
     def fwd():
         res["out"] = binding.minplus_forward(A, J0, shared=False)
 
     t_fwd = timed_steps(torch, fwd, steps, warmup)
     JT, arg = res["out"]
-    t_bt = timed_steps(torch, lambda: binding.minplus_backtrack(JT, arg), steps, warmup)
+    fJT, farg = res["fused"]
+    same = bool(torch.equal(JT, fJT) and torch.equal(arg, farg))
+    t_bt = timed_steps(torch, lambda: binding.minplus_backtrack(fJT, farg), steps, warmup)
+    alg_bytes = T * B * 4 + 2 * T * B * R * 4 + 2 * B * m * 4 + T * B * m * 4
     a_bytes = T * B * m * m * 4
-    fwd_bytes = a_bytes + T * B * m * 4 + 2 * B * m * 4  # A read, minimisers written, J read and written
+    del A
     return {
         "workload": inst.name,
         "problems": B,
         "states": m,
         "days": T,
-        "generator_ms": t_gen * 1e3,
-        "generator_gbs": a_bytes / t_gen / 1e9,
-        "forward_ms": t_fwd * 1e3,
-        "forward_gbs": fwd_bytes / t_fwd / 1e9,
-        "forward_hbm_frac": fwd_bytes / t_fwd / 1e9 / HBM_PEAK_GBS,
-        "forward_minplus_ops_per_s": T * B * m * m / t_fwd,
+        "fused_ms": t_fused * 1e3,
+        "fused_call_ms": t_fused_call * 1e3,
+        "fused_algorithmic_bytes": alg_bytes,
+        "roofline": {"bound": "hbm", "unit": "GB/s", "achieved": alg_bytes / t_fused / 1e9, "peak": HBM_PEAK_GBS,
+                     "frac": alg_bytes / t_fused / 1e9 / HBM_PEAK_GBS,
+                     "basis": "device time per launch: HIP events around a captured graph of 20 launches"},
+        "fused_problem_days_per_s": T * B / t_fused,
+        "fused_equals_two_pass": same,
+        "two_pass_generator_ms": t_gen * 1e3,
+        "two_pass_forward_ms": t_fwd * 1e3,
+        "two_pass_matrix_bytes": a_bytes,
+        "speedup_fused_vs_two_pass": (t_gen + t_fwd) / t_fused,
         "backtrack_ms": t_bt * 1e3,
-        "mean_terminal_cost": float(JT.double().min(dim=1).values.mean().item()),
+        "mean_terminal_cost": float(fJT.double().min(dim=1).values.mean().item()),
     }
 
 
@@ -425,6 +586,7 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--scenarios", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-small", action="store_true", help="skip the n=20 latency and n=100 sections")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-routes", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
@@ -533,8 +695,18 @@ def main():
             "valu_insts_per_launch": valu_insts,
             "valu_issue_frac": (valu_insts * 64 / kernel_s / 1e12 / VALU_PEAK_TOPS
                                 if valu_insts else None),
+            "traffic_source": ("committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary %s, taken at this kernel_hash"
+                               % os.path.relpath(TRAFFIC_FILE, ROOT)) if traffic is not None else None,
+            "valu_insts_source": ("committed rocprofv3 SQ_INSTS_VALU summary %s, taken at this kernel_hash"
+                                  % os.path.relpath(COUNTERS_FILE, ROOT)) if valu_insts is not None else None,
+            "kernel_ms_source": "HIP events around each main-kernel launch on its stream, in this run",
         },
     }
+    if not args.no_small:
+        log("latency at n=20, S=1000, Q=30")
+        result["latency_n20_S1e3"] = latency_small(torch, binding, W)
+        log("n=100, S=10^5, Q=100 over rotating demand buffers")
+        result["medium_n100_S1e5"] = medium_rotating(torch, binding, W)
     if not args.no_routes:
         log("route recovery (n=%d, S=%d)" % (n, S))
         rr = route_recovery(torch, binding, t, d, q, inst, cells, out.costs[0], args.steps, args.warmup)
