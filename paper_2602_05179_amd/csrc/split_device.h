@@ -17,6 +17,13 @@ enum : int { ST_OK = 0, ST_BAD_TOUR = 1, ST_BAD_DEMAND = 2 };
 
 typedef const __attribute__((address_space(4))) int CInt; // scalar-loadable table words
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+// Global-memory views of generic pointers: loads through them are global
+// (not flat) loads, counted by vmcnt only, so a prefetch in flight is not
+// waited for by the lgkmcnt waits of scalar and LDS loads, and the compiler
+// can wait for one load without draining the younger ones.  Use only for
+// pointers into device memory.
+typedef const __attribute__((address_space(1))) u32x4 GU32x4;
+typedef const __attribute__((address_space(1))) int16_t GI16;
 
 // table entry j of a per-tour table viewed as scalar-loadable words
 __device__ __forceinline__ int2 tab_at(CInt *tab, int j) { return make_int2(tab[2 * j], tab[2 * j + 1]); }
@@ -52,7 +59,8 @@ __device__ __forceinline__ bool stage_tile_u8(const int16_t *__restrict__ src, u
     __syncthreads();
     const int64_t chunks = elems >> 3; // full 8-element (16-byte) chunks
     uint32_t bad = 0;
-    const u32x4 *src4 = reinterpret_cast<const u32x4 *>(src);
+    GU32x4 *src4 = (GU32x4 *)reinterpret_cast<const u32x4 *>(src);
+    GI16 *gsrc = (GI16 *)src;
     uint2 *dst8 = reinterpret_cast<uint2 *>(lds);
     int64_t i = tid;
     for (; i + 3 * nthreads < chunks; i += 4 * nthreads) {
@@ -80,7 +88,7 @@ __device__ __forceinline__ bool stage_tile_u8(const int16_t *__restrict__ src, u
         dst8[i] = o;
     }
     for (int64_t e = (chunks << 3) + tid; e < elems; e += nthreads) {
-        const int v = src[e];
+        const int v = gsrc[e];
         bad |= (v < 0 || v > 255) ? 1u : 0u;
         lds[e] = (uint8_t)v;
     }

@@ -144,7 +144,7 @@ __device__ __forceinline__ int byte_at(const u32x4 (&seg)[2], int b)
 // position j = j0 + 1 + U of a block of R positions (j0 a multiple of R)
 template <int R, int F, int G, int E, int U, bool CHK> struct DpStateO {
     __device__ __forceinline__ static bool run(int (&f)[R], int (&lq)[R], DpRegsO &r,
-                                               const u32x4 *row, int64_t segs, CInt *tab,
+                                               GU32x4 *row, int64_t segs, CInt *tab,
                                                int j0, int n, int Q)
     {
         constexpr int SL = (U + 1) & (R - 1);
@@ -180,7 +180,7 @@ template <int R, int F, int G, int E, int U, bool CHK> struct DpStateO {
 };
 
 template <int R, int F, int G, int E, bool CHK, int... Us>
-__device__ __forceinline__ bool dp_block_o(int (&f)[R], int (&lq)[R], DpRegsO &r, const u32x4 *row,
+__device__ __forceinline__ bool dp_block_o(int (&f)[R], int (&lq)[R], DpRegsO &r, GU32x4 *row,
                                            int64_t segs, CInt *tab, int j0, int n, int Q,
                                            std::integer_sequence<int, Us...>)
 {
@@ -206,7 +206,7 @@ __device__ __forceinline__ int dp_lane_ordered(const uint8_t *rowb, int pitch, C
     r.cp2 = ~0ull;
     r.t0 = tab_at(tab, 1);
     r.t1 = tab_at(tab, 2);
-    const u32x4 *row = reinterpret_cast<const u32x4 *>(rowb);
+    GU32x4 *row = (GU32x4 *)reinterpret_cast<const u32x4 *>(rowb);
     const int64_t segs = pitch / 32;
     r.cur[0] = __builtin_nontemporal_load(row);
     r.cur[1] = __builtin_nontemporal_load(row + 1);

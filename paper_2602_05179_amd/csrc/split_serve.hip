@@ -92,11 +92,28 @@ __device__ __forceinline__ JobView read_job(const ServeJob *j)
 }
 
 // Lane 0 takes the next tile from the queue; returns false (uniformly) when
-// the wave should leave.
+// the wave should leave.  A wave caches the queue position it last read a
+// job from (`cur_h`, its slot and tile count): only when the head has moved
+// past it does the wave read the tail with acquire order (the publish
+// kernel's release makes the job's descriptor and tables visible) and the
+// new head job's slot, and `fresh` tells the caller to read the descriptor
+// again.  Tiles are claimed from the partition `home` (the workgroup index
+// modulo the partition count) first, then from the others in turn; a
+// partition whose claim counter has passed its tile count is skipped with
+// a load instead of an add.  When every partition of the head job is
+// claimed the head moves on.
+struct ClaimCache {
+    uint32_t h;  // queue position of the cached job (valid when s >= 0)
+    int s;       // its slot
+    int tiles;   // its tile count
+    int chunk;   // tiles per claim
+};
+
 __device__ bool claim(ServeQueue *q, ServeJob *jobs, long long start, long long &idle_since,
-                      const ServeCtl &ctl, int lane, int &slot, int &tile)
+                      const ServeCtl &ctl, int lane, int home, ClaimCache &cc, int &slot,
+                      int &tile, int &count, int &part, bool &fresh)
 {
-    int s_out = -1, t_out = -1, quit = 0;
+    int s_out = -1, t_out = -1, c_out = 0, p_out = -1, quit = 0, fr = 0;
     if (lane == 0) {
         for (;;) {
             const long long now = ticks();
@@ -104,26 +121,50 @@ __device__ bool claim(ServeQueue *q, ServeJob *jobs, long long start, long long 
                 quit = 1;
                 break;
             }
-            const uint32_t h = __hip_atomic_load(&q->head, __ATOMIC_ACQUIRE,
+            const uint32_t h = __hip_atomic_load(&q->head, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t t = __hip_atomic_load(&q->tail, __ATOMIC_ACQUIRE,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-            if (h == t) {
-                if (now - idle_since > ctl.idle_ticks) {
-                    quit = 1;
-                    break;
+            if (cc.s < 0 || h != cc.h) {
+                // relaxed: a job's descriptor and tables are written by
+                // kernels that completed (and wrote back) before the publish
+                // kernel stored the tail, and no cache of a running drain
+                // holds lines of reused memory (memory is reused only after
+                // every drain running at its retirement has ended), so the
+                // reads below see them without an acquire's cache
+                // invalidation
+                const uint32_t t = __hip_atomic_load(&q->tail, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+                if (h == t) {
+                    if (now - idle_since > ctl.idle_ticks) {
+                        quit = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(16);
+                    continue;
                 }
-                __builtin_amdgcn_s_sleep(16);
-                continue;
+                cc.h = h;
+                cc.s = ld_agent(&q->ring[h & (kServeQueueCap - 1)]);
+                cc.tiles = ld_agent(&jobs[cc.s].tiles);
+                cc.chunk = ld_agent(&jobs[cc.s].chunk);
+                fr = 1;
             }
-            const int s = ld_agent(&q->ring[h & (kServeQueueCap - 1)]);
-            const int k = atomicAdd(&jobs[s].next_tile, 1);
-            if (k < ld_agent(&jobs[s].tiles)) {
-                s_out = s;
-                t_out = k;
+            ServeJob *jb = jobs + cc.s;
+            for (int i = 0; i < kServeParts && s_out < 0; ++i) {
+                const int p = (home + i) & (kServeParts - 1);
+                const int lo = serve_part_lo(cc.tiles, p);
+                const int cnt = serve_part_lo(cc.tiles, p + 1) - lo;
+                if (cnt == 0 || ld_agent(&jb->part[p].next) >= cnt)
+                    continue;
+                const int k = atomicAdd(&jb->part[p].next, cc.chunk);
+                if (k < cnt) {
+                    s_out = cc.s;
+                    t_out = lo + k;
+                    c_out = min(cc.chunk, cnt - k);
+                    p_out = p;
+                }
+            }
+            if (s_out >= 0)
                 break;
-            }
-            // no tiles left in this job: move the head on (another wave may
+            // every partition claimed: move the head on (another wave may
             // already have)
             uint32_t expect = h;
             __hip_atomic_compare_exchange_strong(&q->head, &expect, h + 1, __ATOMIC_RELAXED,
@@ -133,6 +174,9 @@ __device__ bool claim(ServeQueue *q, ServeJob *jobs, long long start, long long 
     quit = uni(__shfl(quit, 0, kWave));
     slot = uni(__shfl(s_out, 0, kWave));
     tile = uni(__shfl(t_out, 0, kWave));
+    count = uni(__shfl(c_out, 0, kWave));
+    part = uni(__shfl(p_out, 0, kWave));
+    fresh = uni(__shfl(fr, 0, kWave)) != 0;
     return !quit;
 }
 
@@ -173,7 +217,7 @@ __device__ int exact_tile(const ServeCtl &ctl, const JobView &jv, int64_t s0, in
     return v;
 }
 
-template <bool ORDERED>
+template <bool ORDERED, bool WIDE>
 __device__ __forceinline__ int fast_tile(const JobView &jv, const uint8_t *lds, int64_t s0,
                                          int lane, int rows, bool &ovf)
 {
@@ -182,40 +226,37 @@ __device__ __forceinline__ int fast_tile(const JobView &jv, const uint8_t *lds, 
     if (lane < rows) {
         if (ORDERED) {
             const uint8_t *row = jv.perm + (s0 + lane) * jv.pitch;
-            switch (jv.variant) {
-            case SV_R32_6:
-                m = dp_lane_ordered<32, 6, 3, 3>(row, jv.pitch, tab, jv.n, jv.f0, jv.Q, ovf);
-                break;
-            case SV_R32_8:
-                m = dp_lane_ordered<32, 8, 3, 3>(row, jv.pitch, tab, jv.n, jv.f0, jv.Q, ovf);
-                break;
-            default:
+            if (WIDE)
                 m = dp_lane_ordered<64, 16, 4, 4>(row, jv.pitch, tab, jv.n, jv.f0, jv.Q, ovf);
-                break;
-            }
+            else if (jv.variant == SV_R32_6)
+                m = dp_lane_ordered<32, 6, 3, 3>(row, jv.pitch, tab, jv.n, jv.f0, jv.Q, ovf);
+            else
+                m = dp_lane_ordered<32, 8, 3, 3>(row, jv.pitch, tab, jv.n, jv.f0, jv.Q, ovf);
         } else {
             const uint8_t *row = lds + (int64_t)lane * jv.N;
-            switch (jv.variant) {
-            case SV_R32_6:
-                m = dp_lane<32, 6, 3, 3>(row, tab, jv.n, jv.f0, jv.Q, ovf);
-                break;
-            case SV_R32_8:
-                m = dp_lane<32, 8, 3, 3>(row, tab, jv.n, jv.f0, jv.Q, ovf);
-                break;
-            default:
+            if (WIDE)
                 m = dp_lane<64, 16, 4, 4>(row, tab, jv.n, jv.f0, jv.Q, ovf);
-                break;
-            }
+            else if (jv.variant == SV_R32_6)
+                m = dp_lane<32, 6, 3, 3>(row, tab, jv.n, jv.f0, jv.Q, ovf);
+            else
+                m = dp_lane<32, 8, 3, 3>(row, tab, jv.n, jv.f0, jv.Q, ovf);
         }
     }
     return m + jv.bn;
 }
 
-template <bool ORDERED>
-__device__ void run_tile(const ServeCtl &ctl, int slot, int tile, uint8_t *lds, int lane)
+// Partial results of the tiles a wave has run since its last claim.
+struct TileAcc {
+    long long sum; // exact sum of finite costs
+    int ninf;      // SPLIT_INF costs
+    bool neg;      // a negative demand was read
+    bool no_scratch; // an exact tile found no value history in time
+};
+
+template <bool ORDERED, bool WIDE>
+__device__ void run_tile(const ServeCtl &ctl, const JobView &jv, int tile, uint8_t *lds,
+                         int lane, TileAcc &acc)
 {
-    ServeJob *job = ctl.jobs + slot;
-    const JobView jv = read_job(job);
     const int64_t s0 = (int64_t)tile * kWave;
     const int rows = (int)min<int64_t>(kWave, jv.S - s0);
     bool negq = false, no_scratch = false;
@@ -232,7 +273,7 @@ __device__ void run_tile(const ServeCtl &ctl, int slot, int tile, uint8_t *lds, 
         }
         bool ovf = false;
         if (ok)
-            v = fast_tile<ORDERED>(jv, lds, s0, lane, rows, ovf);
+            v = fast_tile<ORDERED, WIDE>(jv, lds, s0, lane, rows, ovf);
         if (!ok || ballot(ovf) != 0)
             v = exact_tile(ctl, jv, s0, rows, lane, negq, no_scratch);
     }
@@ -240,102 +281,210 @@ __device__ void run_tile(const ServeCtl &ctl, int slot, int tile, uint8_t *lds, 
     const bool fin = lane < rows && !inf;
     if (lane < rows)
         jv.costs[s0 + lane] = inf ? SPLIT_INF : v;
-    const long long sm = wave_sum_i64(fin ? (long long)v : 0LL);
-    const int ni = wave_sum_i32(inf ? 1 : 0);
-    const bool flag_neg = ballot(negq) != 0;
-    if (lane == 0) {
-        if (sm)
-            atomicAdd(reinterpret_cast<unsigned long long *>(&job->sum), (unsigned long long)sm);
-        if (ni)
-            atomicAdd(reinterpret_cast<unsigned long long *>(&job->ninf), (unsigned long long)ni);
-        if (flag_neg)
-            atomicOr(&job->flags, 1);
-        if (no_scratch)
-            atomicOr(&job->flags, 2);
-        __threadfence(); // costs and partial sums before the tile counts as done
-        const int done = atomicAdd(&job->tiles_done, 1) + 1;
-        if (done == jv.tiles) {
-            __threadfence();
-            const long long sum = (long long)atomicAdd(
-                reinterpret_cast<unsigned long long *>(&job->sum), 0ull);
-            const long long ninf = (long long)atomicAdd(
-                reinterpret_cast<unsigned long long *>(&job->ninf), 0ull);
-            const int flags = atomicOr(&job->flags, 0);
-            ServeResult *r = ctl.results + slot;
-            if (flags) {
-                r->sum = SPLIT_SUM_INVALID;
-                r->mean = __builtin_nan("");
-            } else if (ninf) {
-                r->sum = INT64_MAX;
-                r->mean = __builtin_inf();
-            } else {
-                r->sum = sum;
-                r->mean = (double)sum / (double)jv.S;
-            }
-            r->flags = flags;
-            __threadfence_system();
-            __hip_atomic_store(&r->seq, ld_agent(&job->seq), __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_SYSTEM);
-        }
+    acc.sum += wave_sum_i64(fin ? (long long)v : 0LL);
+    acc.ninf += wave_sum_i32(inf ? 1 : 0);
+    acc.neg = acc.neg || ballot(negq) != 0;
+    acc.no_scratch = acc.no_scratch || no_scratch;
+}
+
+// The claimed tiles' partial sums into their partition, then the
+// partition's and the job's completion counts; the wave that completes the
+// job folds the partitions and writes the result to host-visible memory.
+__device__ void finish_chunk(const ServeCtl &ctl, const JobView &jv, int slot, int part,
+                             int count, const TileAcc &acc, int lane)
+{
+    if (lane != 0)
+        return;
+    ServeJob *job = ctl.jobs + slot;
+    ServePart &pt = job->part[part];
+    if (acc.sum)
+        atomicAdd(reinterpret_cast<unsigned long long *>(&pt.sum), (unsigned long long)acc.sum);
+    if (acc.ninf)
+        atomicAdd(reinterpret_cast<unsigned long long *>(&pt.ninf), (unsigned long long)acc.ninf);
+    if (acc.neg)
+        atomicOr(&job->flags, 1);
+    if (acc.no_scratch)
+        atomicOr(&job->flags, 2);
+    __threadfence(); // costs and partial sums before the tiles count as done
+    const int cnt = serve_part_lo(jv.tiles, part + 1) - serve_part_lo(jv.tiles, part);
+    if (atomicAdd(&pt.done, count) + count != cnt)
+        return;
+    __threadfence(); // the partition's sums before it counts as done
+    if (atomicAdd(&job->parts_done, 1) + 1 != kServeParts)
+        return;
+    __threadfence();
+    long long sum = 0, ninf = 0;
+    for (int p = 0; p < kServeParts; ++p) {
+        sum += (long long)atomicAdd(reinterpret_cast<unsigned long long *>(&job->part[p].sum),
+                                    0ull);
+        ninf += (long long)atomicAdd(reinterpret_cast<unsigned long long *>(&job->part[p].ninf),
+                                     0ull);
     }
+    const int flags = atomicOr(&job->flags, 0);
+    ServeResult *r = ctl.results + slot;
+    if (flags) {
+        r->sum = SPLIT_SUM_INVALID;
+        r->mean = __builtin_nan("");
+    } else if (ninf) {
+        r->sum = INT64_MAX;
+        r->mean = __builtin_inf();
+    } else {
+        r->sum = sum;
+        r->mean = (double)sum / (double)jv.S;
+    }
+    r->flags = flags;
+    __threadfence_system();
+    __hip_atomic_store(&r->seq, ld_agent(&job->seq), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 } // namespace
 
 // grid of one-wave workgroups; LDS: the fused drain's tile (kServeFusedMaxN
 // bytes per row) plus the staging flag
-template <bool ORDERED>
+template <bool ORDERED, bool WIDE>
 __global__ __launch_bounds__(kWave) void serve_drain_kernel(ServeCtl ctl, ServeQueue *q)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     const int lane = threadIdx.x;
     const long long start = ticks();
     long long idle_since = start;
-    int slot, tile;
-    while (claim(q, ctl.jobs, start, idle_since, ctl, lane, slot, tile)) {
-        run_tile<ORDERED>(ctl, slot, tile, lds, lane);
+    const int home = (int)(blockIdx.x & (kServeParts - 1));
+    ClaimCache cc{0u, -1, 0, 1};
+    JobView jv{};
+    int slot, tile, count, part;
+    bool fresh;
+    while (claim(q, ctl.jobs, start, idle_since, ctl, lane, home, cc, slot, tile, count, part,
+                 fresh)) {
+        if (fresh) // a job this wave has not run before: its descriptor
+            jv = read_job(ctl.jobs + slot);
+        TileAcc acc{0, 0, false, false};
+        for (int i = 0; i < count; ++i)
+            run_tile<ORDERED, WIDE>(ctl, jv, tile + i, lds, lane, acc);
+        finish_chunk(ctl, jv, slot, part, count, acc, lane);
         idle_since = ticks();
     }
 }
 
-// one wave: copy the batch's staged job descriptors (pinned host memory, at
-// the start of each slot's staging area) into their table slots, then
-// append the slots to their queues and publish the new tails with release
-// order
-__global__ __launch_bounds__(kWave) void serve_publish_kernel(ServeQueue *q0, ServeQueue *q1,
-                                                              ServeJob *jobs,
-                                                              const char *stage_base,
-                                                              size_t stage_bytes,
+// one workgroup per admitted job: its tables (tab, ab, rec, as laid out in
+// its arena block, which tab starts) and then its descriptor, both from the
+// job's pinned staging area (descriptor first, tables after it)
+constexpr int kAdmitThreads = 256;
+
+__global__ __launch_bounds__(kAdmitThreads) void serve_admit_kernel(ServeJob *jobs,
+                                                                    const char *stage_base,
+                                                                    size_t stage_bytes,
+                                                                    AdmitBatch batch)
+{
+    const int s = batch.slot[blockIdx.x];
+    const char *st = stage_base + (size_t)s * stage_bytes;
+    const ServeJob *src = reinterpret_cast<const ServeJob *>(st);
+    const int hb = src->head_bytes;
+    uint8_t *dst = reinterpret_cast<uint8_t *>(const_cast<int2 *>(src->tab));
+    const uint8_t *from = reinterpret_cast<const uint8_t *>(st) + kStageHead;
+    for (int w = threadIdx.x; w < hb / 16; w += kAdmitThreads)
+        reinterpret_cast<u32x4 *>(dst)[w] = reinterpret_cast<const u32x4 *>(from)[w];
+    for (int b = (hb & ~15) + threadIdx.x; b < hb; b += kAdmitThreads)
+        dst[b] = from[b];
+    constexpr int words = (int)(sizeof(ServeJob) / sizeof(uint32_t));
+    const uint32_t *js = reinterpret_cast<const uint32_t *>(src);
+    uint32_t *jd = reinterpret_cast<uint32_t *>(jobs + s);
+    for (int w = threadIdx.x; w < words; w += kAdmitThreads)
+        jd[w] = js[w];
+}
+
+// one workgroup per 64-scenario tile of the round's ordered jobs: the
+// tile's demands rewritten in tour order (one byte each, row pitch `pitch`)
+// for the ordered drain, and its flag (1: a demand outside 0..255, the
+// drain runs the exact recursion).  The tour's customer order sits in LDS;
+// each thread gathers 16 positions of one row straight from the row in
+// global memory (consecutive threads share a row, so its few cache lines
+// serve them all).  The kernel needs only a small LDS block and few
+// registers, so its workgroups find room beside running drain waves (the
+// drains leave one wave slot per SIMD free).
+constexpr int kServePermThreads = 256;
+
+__global__ __launch_bounds__(kServePermThreads) void serve_permute_kernel(const ServeJob *jobs,
+                                                                          PermuteBatch batch)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    const int k = blockIdx.x;
+    int lo = 0, hi = batch.count - 1; // the job: the last one whose first tile is <= k
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (batch.tile0[mid] <= k)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const ServeJob *jb = jobs + batch.slot[lo];
+    const int tile = k - batch.tile0[lo];
+    const int16_t *demands = jb->demands;
+    uint8_t *perm = const_cast<uint8_t *>(jb->perm);
+    uint8_t *tile_bad = const_cast<uint8_t *>(jb->tile_bad);
+    const int2 *tab = jb->tab;
+    const int64_t S = jb->S;
+    const int N = jb->N, n = jb->n, pitch = jb->pitch;
+    const int64_t s0 = (int64_t)tile * kWave;
+    const int rows = (int)min<int64_t>(kWave, S - s0);
+    const int chunks = pitch / 16;
+    uint8_t *dst = perm + s0 * pitch;
+    const int tid = threadIdx.x;
+    int &s_bad = *reinterpret_cast<int *>(lds);
+    uint16_t *cust = reinterpret_cast<uint16_t *>(lds + 16);
+    if (tid == 0)
+        s_bad = 0;
+    for (int j = tid; j < n; j += kServePermThreads)
+        cust[j] = (uint16_t)tab[j + 1].x;
+    __syncthreads();
+    uint32_t bad = 0;
+    for (int idx = tid; idx < rows * chunks; idx += kServePermThreads) {
+        const int r = idx / chunks;
+        const int c = idx - r * chunks;
+        const int16_t *row = demands + (s0 + r) * N;
+        uint32_t w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint32_t x = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int j = c * 16 + q * 4 + b;
+                const int v = j < n ? row[cust[j]] : 0;
+                bad |= (v < 0 || v > 255) ? 1u : 0u;
+                x |= ((uint32_t)v & 0xFFu) << (8 * b);
+            }
+            w[q] = x;
+        }
+        u32x4 o = {w[0], w[1], w[2], w[3]};
+        __builtin_nontemporal_store(o, reinterpret_cast<u32x4 *>(dst + (int64_t)r * pitch) + c);
+    }
+    if (ballot(bad != 0) != 0 && (tid & (kWave - 1)) == 0)
+        atomicOr(&s_bad, 1);
+    __syncthreads();
+    if (tid == 0)
+        tile_bad[tile] = s_bad ? 1 : 0;
+}
+
+// one wave: the batch's slots appended to their queues, the new tails
+// published with release order (the jobs' descriptors and tables were
+// written by the launches before it on the same stream)
+__global__ __launch_bounds__(kWave) void serve_publish_kernel(ServeQueues queues,
                                                               PublishBatch batch)
 {
-    const int lane = threadIdx.x;
-    constexpr int words = (int)(sizeof(ServeJob) / sizeof(uint32_t));
-    for (int i = 0; i < batch.count; ++i) {
-        const int s = batch.entry[i] & ((1 << 30) - 1);
-        const uint32_t *src =
-            reinterpret_cast<const uint32_t *>(stage_base + (size_t)s * stage_bytes);
-        uint32_t *dst = reinterpret_cast<uint32_t *>(jobs + s);
-        for (int w = lane; w < words; w += kWave)
-            __hip_atomic_store(dst + w, src[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __threadfence();
-    if (lane == 0) {
-        uint32_t t0 = __hip_atomic_load(&q0->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        uint32_t t1 = __hip_atomic_load(&q1->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t b0 = t0, b1 = t1;
+    if (threadIdx.x == 0) {
+        uint32_t t[kServeQueues], b[kServeQueues];
+        for (int k = 0; k < kServeQueues; ++k)
+            b[k] = t[k] = __hip_atomic_load(&queues.q[k]->tail, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
         for (int i = 0; i < batch.count; ++i) {
-            const int s = batch.entry[i] & ((1 << 30) - 1);
-            if (batch.entry[i] >> 30)
-                __hip_atomic_store(&q1->ring[t1++ & (kServeQueueCap - 1)], s, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            else
-                __hip_atomic_store(&q0->ring[t0++ & (kServeQueueCap - 1)], s, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+            const int s = batch.entry[i] & ((1 << 28) - 1);
+            const int k = (batch.entry[i] >> 28) & (kServeQueues - 1);
+            __hip_atomic_store(&queues.q[k]->ring[t[k]++ & (kServeQueueCap - 1)], s,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        if (t0 != b0)
-            __hip_atomic_store(&q0->tail, t0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        if (t1 != b1)
-            __hip_atomic_store(&q1->tail, t1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        for (int k = 0; k < kServeQueues; ++k)
+            if (t[k] != b[k])
+                __hip_atomic_store(&queues.q[k]->tail, t[k], __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -344,38 +493,97 @@ static size_t drain_lds(bool ordered)
     return ordered ? 0 : (((size_t)kWave * kServeFusedMaxN + 15) & ~(size_t)15) + 16;
 }
 
-int serve_drain_grid(bool ordered)
+template <bool ORDERED, bool WIDE> static const void *drain_fn()
+{
+    return reinterpret_cast<const void *>(&serve_drain_kernel<ORDERED, WIDE>);
+}
+
+static const void *drain_fn(int queue)
+{
+    switch (queue) {
+    case 0: return drain_fn<false, false>();
+    case 1: return drain_fn<false, true>();
+    case 2: return drain_fn<true, false>();
+    default: return drain_fn<true, true>();
+    }
+}
+
+int serve_drain_grid(int queue)
 {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
-    const void *fn = ordered ? reinterpret_cast<const void *>(&serve_drain_kernel<true>)
-                             : reinterpret_cast<const void *>(&serve_drain_kernel<false>);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kWave, drain_lds(ordered)) !=
-            hipSuccess ||
+    const bool ordered = serve_queue_ordered(queue);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, drain_fn(queue), kWave,
+                                                     drain_lds(ordered)) != hipSuccess ||
         per < 1)
         per = 1;
+    // leave one wave slot per SIMD (and the LDS and registers it needs) to
+    // the admission launches, so a round's permute is not held up until
+    // drain waves retire
+    if (per >= 8)
+        per -= 4;
+    else if (per >= 2)
+        per -= 1;
     return cus * per;
 }
 
-hipError_t serve_launch_drain(bool ordered, const ServeCtl &ctl, ServeQueue *q, int grid,
+hipError_t serve_launch_drain(int queue, const ServeCtl &ctl, ServeQueue *q, int grid,
                               hipStream_t stream)
 {
-    if (ordered)
-        hipLaunchKernelGGL(serve_drain_kernel<true>, dim3(grid), dim3(kWave), 0, stream, ctl, q);
-    else
-        hipLaunchKernelGGL(serve_drain_kernel<false>, dim3(grid), dim3(kWave), drain_lds(false),
+    const size_t lds = drain_lds(serve_queue_ordered(queue));
+    switch (queue) {
+    case 0:
+        hipLaunchKernelGGL((serve_drain_kernel<false, false>), dim3(grid), dim3(kWave), lds,
                            stream, ctl, q);
+        break;
+    case 1:
+        hipLaunchKernelGGL((serve_drain_kernel<false, true>), dim3(grid), dim3(kWave), lds,
+                           stream, ctl, q);
+        break;
+    case 2:
+        hipLaunchKernelGGL((serve_drain_kernel<true, false>), dim3(grid), dim3(kWave), lds,
+                           stream, ctl, q);
+        break;
+    default:
+        hipLaunchKernelGGL((serve_drain_kernel<true, true>), dim3(grid), dim3(kWave), lds,
+                           stream, ctl, q);
+        break;
+    }
     return hipGetLastError();
 }
 
-hipError_t serve_launch_publish(ServeQueue *q0, ServeQueue *q1, ServeJob *jobs,
-                                const char *stage_base, size_t stage_bytes,
-                                const PublishBatch &batch, hipStream_t stream)
+hipError_t serve_launch_admit(ServeJob *jobs, const char *stage_base, size_t stage_bytes,
+                              const AdmitBatch &batch, hipStream_t stream)
 {
-    hipLaunchKernelGGL(serve_publish_kernel, dim3(1), dim3(kWave), 0, stream, q0, q1, jobs,
-                       stage_base, stage_bytes, batch);
+    hipLaunchKernelGGL(serve_admit_kernel, dim3(batch.count), dim3(kAdmitThreads), 0, stream,
+                       jobs, stage_base, stage_bytes, batch);
+    return hipGetLastError();
+}
+
+hipError_t serve_launch_permute(const ServeJob *jobs, const PermuteBatch &batch,
+                                int32_t max_n, hipStream_t stream)
+{
+    static bool attr = false;
+    if (!attr) {
+        const hipError_t e =
+            hipFuncSetAttribute(reinterpret_cast<const void *>(&serve_permute_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kLdsLimit);
+        if (e != hipSuccess)
+            return e;
+        attr = true;
+    }
+    const int32_t tiles = batch.tile0[batch.count];
+    hipLaunchKernelGGL(serve_permute_kernel, dim3((unsigned)tiles), dim3(kServePermThreads),
+                       (size_t)16 + 2 * ((size_t)max_n + 1), stream, jobs, batch);
+    return hipGetLastError();
+}
+
+hipError_t serve_launch_publish(const ServeQueues &queues, const PublishBatch &batch,
+                                hipStream_t stream)
+{
+    hipLaunchKernelGGL(serve_publish_kernel, dim3(1), dim3(kWave), 0, stream, queues, batch);
     return hipGetLastError();
 }
 

@@ -151,6 +151,7 @@ struct Request {
     // host-computed tour constants
     std::vector<int2> tab, ab;
     int32_t f0 = 0, bn = 0, variant = 0, pitch = 0;
+    int32_t tiles = 0; // 64-scenario tiles
     bool ordered = false;
     // admission
     size_t off = 0, bytes = 0;
@@ -191,7 +192,7 @@ struct split_server {
     // device memory: fixed structures, then the arena
     char *dev_base = nullptr;
     splitk::ServeJob *d_jobs = nullptr;
-    splitk::ServeQueue *d_queue[2] = {nullptr, nullptr}; // 0 fused, 1 ordered
+    splitk::ServeQueue *d_queue[splitk::kServeQueues] = {}; // splitk::serve_queue order
     int *d_scratch = nullptr;
     uint32_t *d_scratch_mask = nullptr;
     char *arena_base = nullptr;
@@ -204,11 +205,11 @@ struct split_server {
     size_t stage_bytes = 0;
 
     hipStream_t copy_stream = nullptr, out_stream = nullptr;
-    hipStream_t drain_stream[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    hipStream_t drain_stream[splitk::kServeQueues][2] = {};
     std::vector<hipEvent_t> event_pool;
-    std::deque<Drain> drains[2];
-    int drain_rr[2] = {0, 0};
-    int drain_grid[2] = {0, 0};
+    std::deque<Drain> drains[splitk::kServeQueues];
+    int drain_rr[splitk::kServeQueues] = {};
+    int drain_grid[splitk::kServeQueues] = {};
     uint64_t next_drain_id = 1;
     int64_t drains_launched = 0;
     int64_t life_us = 1000;
@@ -221,7 +222,8 @@ struct split_server {
     std::vector<int> free_slots;
     std::vector<Request *> slot_req; // [kServeMaxJobs]
     int32_t seq_counter = 0;
-    int64_t outstanding[2] = {0, 0}; // published, not finished, per queue
+    int64_t outstanding[splitk::kServeQueues] = {}; // published, not finished, per queue
+    int64_t backlog_tiles = 0; // tiles of admitted, unfinished requests
     std::deque<Request *> pending;
     std::vector<Request *> running;
     std::vector<Deferred> deferred;
@@ -253,7 +255,7 @@ struct split_server {
     uint64_t min_running_drain() const
     {
         uint64_t m = next_drain_id;
-        for (int q = 0; q < 2; ++q)
+        for (int q = 0; q < splitk::kServeQueues; ++q)
             for (const Drain &d : drains[q])
                 m = std::min(m, d.id);
         return m;
@@ -273,7 +275,7 @@ struct split_server {
     {
         if (free_slots.empty())
             return false;
-        const int qi = r->ordered ? 1 : 0;
+        const int qi = splitk::serve_queue(r->ordered, r->variant);
         if (outstanding[qi] >= splitk::kServeQueueCap - 2)
             return false;
         const size_t bytes = footprint(*r);
@@ -325,9 +327,10 @@ struct split_server {
             d_dem = reinterpret_cast<const int16_t *>(arena_base + in->off);
         }
 
-        // pinned staging of this slot: the job descriptor (read by the
-        // publish kernel), then tab, ab, rec laid out as in the arena block
-        char *st = h_stage + (size_t)r->slot * stage_bytes + a256(sizeof(splitk::ServeJob));
+        // pinned staging of this slot: the job descriptor, then tab, ab, rec
+        // laid out as in the arena block (the round's admit launch copies
+        // them; the permute launch writes the tour-ordered copy)
+        char *st = h_stage + (size_t)r->slot * stage_bytes + splitk::kStageHead;
         const size_t tab_b = ((size_t)r->n + splitk::kTabPad) * sizeof(int2);
         const size_t ab_b = (size_t)r->n * sizeof(int2);
         memcpy(st, r->tab.data(), tab_b);
@@ -342,24 +345,7 @@ struct split_server {
                sizeof(rec));
         const size_t head_b = a256(tab_b) + a256((size_t)std::max(r->n, 1) * sizeof(int2)) +
                               sizeof(splitk::TourRec);
-        hipError_t e = hipMemcpyAsync(d_tab, st, head_b, hipMemcpyHostToDevice, copy_stream);
-        if (e != hipSuccess) {
-            fail_all("copy tables", e);
-            return true;
-        }
-        if (r->ordered) {
-            splitk::Workspace ws{};
-            ws.tab = d_tab;
-            ws.rec = d_rec;
-            ws.tile_bad = d_bad;
-            ws.perm = d_perm;
-            ws.max_len = r->n;
-            e = splitk::launch_permute(d_dem, in->N, S, 1, r->n, ws, copy_stream);
-            if (e != hipSuccess) {
-                fail_all("permute launch", e);
-                return true;
-            }
-        }
+        (void)d_rec;
         splitk::ServeJob j{};
         j.demands = d_dem;
         j.perm = d_perm;
@@ -374,29 +360,83 @@ struct split_server {
         j.f0 = r->f0;
         j.bn = r->bn;
         j.tiles = (int32_t)splitk::num_tiles(S);
+        j.parts_done = splitk::kServeParts - std::min<int32_t>(splitk::kServeParts, j.tiles);
+        // tiles per claim: one while the device is not saturated (every
+        // tile of a lone request runs in parallel), up to kServeChunkMax
+        // when the backlog holds several tiles per drain wave (fewer claims
+        // and completion updates per tile)
+        r->tiles = j.tiles;
+        backlog_tiles += j.tiles;
+        j.chunk = (int32_t)std::min<int64_t>(
+            splitk::kServeChunkMax,
+            std::max<int64_t>(1, backlog_tiles / (2 * (int64_t)drain_grid[qi])));
         j.variant = r->variant;
         j.pitch = r->pitch;
         j.seq = r->seq;
+        j.head_bytes = (int32_t)head_b;
         memcpy(h_stage + (size_t)r->slot * stage_bytes, &j, sizeof(j));
         batch.push_back(r);
         return true;
     }
 
-    // Publish launches for the requests admitted this round (at most
-    // kPublishMax per launch), on the copy stream after their tables.
+    // The round's launches on the copy stream, after any demand copies of
+    // its requests: admit (tables and descriptors), permute (tour-ordered
+    // copies of the jobs on large pools), publish (queue append), at most
+    // kPublishMax jobs per group.
     void publish(std::vector<Request *> &batch)
     {
         if (batch.empty() || failed)
             return;
         for (size_t i = 0; i < batch.size(); i += splitk::kPublishMax) {
+            const int cnt = (int)std::min(batch.size() - i, (size_t)splitk::kPublishMax);
+            splitk::AdmitBatch ab{};
             splitk::PublishBatch pb{};
-            pb.count = (int32_t)std::min(batch.size() - i, (size_t)splitk::kPublishMax);
-            for (int k = 0; k < pb.count; ++k) {
+            splitk::PermuteBatch mb{};
+            ab.count = cnt;
+            pb.count = cnt;
+            int32_t max_n = 1;
+            for (int k = 0; k < cnt; ++k) {
                 const Request *r = batch[i + k];
-                pb.entry[k] = r->slot | ((r->ordered ? 1 : 0) << 30);
+                ab.slot[k] = r->slot;
+                pb.entry[k] = r->slot | (splitk::serve_queue(r->ordered, r->variant) << 28);
+                if (r->ordered)
+                    max_n = std::max(max_n, r->n);
             }
-            hipError_t e = splitk::serve_launch_publish(d_queue[0], d_queue[1], d_jobs, h_stage,
-                                                        stage_bytes, pb, copy_stream);
+            hipError_t e = splitk::serve_launch_admit(d_jobs, h_stage, stage_bytes, ab, copy_stream);
+            if (e != hipSuccess) {
+                fail_all("admit launch", e);
+                return;
+            }
+            auto flush_permute = [&]() -> bool {
+                if (mb.count == 0)
+                    return true;
+                const hipError_t pe = splitk::serve_launch_permute(d_jobs, mb, max_n, copy_stream);
+                if (pe != hipSuccess) {
+                    fail_all("permute launch", pe);
+                    return false;
+                }
+                mb.count = 0;
+                mb.tile0[0] = 0;
+                return true;
+            };
+            mb.tile0[0] = 0;
+            for (int k = 0; k < cnt; ++k) {
+                const Request *r = batch[i + k];
+                if (!r->ordered || r->n == 0)
+                    continue;
+                const int64_t tiles = splitk::num_tiles(r->inst->S);
+                if (mb.count > 0 && (int64_t)mb.tile0[mb.count] + tiles > (1 << 30) && !flush_permute())
+                    return;
+                mb.slot[mb.count] = r->slot;
+                mb.tile0[mb.count + 1] = (int32_t)(mb.tile0[mb.count] + tiles);
+                mb.count++;
+            }
+            if (!flush_permute())
+                return;
+            splitk::ServeQueues qs{};
+            for (int q = 0; q < splitk::kServeQueues; ++q)
+                qs.q[q] = d_queue[q];
+            e = splitk::serve_launch_publish(qs, pb, copy_stream);
             if (e != hipSuccess) {
                 fail_all("publish launch", e);
                 return;
@@ -409,7 +449,7 @@ struct split_server {
         }
         pub_recorded = true;
         for (Request *r : batch) {
-            outstanding[r->ordered ? 1 : 0]++;
+            outstanding[splitk::serve_queue(r->ordered, r->variant)]++;
             r->state = RUNNING;
             running.push_back(r);
         }
@@ -428,7 +468,7 @@ struct split_server {
     void manage_drains(Clock::time_point now)
     {
         const auto life = std::chrono::microseconds(life_us);
-        for (int qi = 0; qi < 2; ++qi) {
+        for (int qi = 0; qi < splitk::kServeQueues; ++qi) {
             // retire finished drains
             while (!drains[qi].empty()) {
                 Drain &d = drains[qi].front();
@@ -443,7 +483,12 @@ struct split_server {
             if (failed || outstanding[qi] == 0)
                 continue;
             const bool none = drains[qi].empty();
-            const bool aging = drains[qi].size() == 1 && now - drains[qi].back().launched > life / 2;
+            // the next drain is launched once the running one has stopped
+            // taking tiles (its life is over), so its workgroups take the
+            // slots the old one's waves free as they finish; before that a
+            // second drain would fill the wave slots each drain leaves free
+            // for the admission launches
+            const bool aging = drains[qi].size() == 1 && now - drains[qi].back().launched > life;
             if (!none && !aging)
                 continue;
             hipEvent_t ev = get_event();
@@ -454,7 +499,7 @@ struct split_server {
             // the drain starts after the latest publication has landed
             hipError_t e = pub_recorded ? hipStreamWaitEvent(st, pub_event, 0) : hipSuccess;
             if (e == hipSuccess)
-                e = splitk::serve_launch_drain(qi == 1, ctl, d_queue[qi], drain_grid[qi], st);
+                e = splitk::serve_launch_drain(qi, ctl, d_queue[qi], drain_grid[qi], st);
             if (e == hipSuccess)
                 e = hipEventRecord(ev, st);
             if (e != hipSuccess) {
@@ -500,7 +545,8 @@ struct split_server {
                 }
             }
             r->t_done = Clock::now();
-            outstanding[r->ordered ? 1 : 0]--;
+            outstanding[splitk::serve_queue(r->ordered, r->variant)]--;
+            backlog_tiles -= r->tiles;
             done.push_back(r);
             running[i] = running.back();
             running.pop_back();
@@ -607,8 +653,9 @@ struct split_server {
                 break;
             if (!progress) {
                 if (running.empty() && pending.empty()) {
-                    bool drains_left = !drains[0].empty() || !drains[1].empty() ||
-                                       !deferred.empty();
+                    bool drains_left = !deferred.empty();
+                    for (int q = 0; q < splitk::kServeQueues; ++q)
+                        drains_left = drains_left || !drains[q].empty();
                     if (drains_left)
                         cv_work.wait_for(lk, std::chrono::microseconds(200));
                     else
@@ -621,13 +668,13 @@ struct split_server {
             }
         }
         // wait for the drains to end before memory is released
-        for (int qi = 0; qi < 2; ++qi)
+        for (int qi = 0; qi < splitk::kServeQueues; ++qi)
             for (Drain &d : drains[qi]) {
                 (void)hipEventSynchronize(d.done);
                 event_pool.push_back(d.done);
             }
-        drains[0].clear();
-        drains[1].clear();
+        for (int qi = 0; qi < splitk::kServeQueues; ++qi)
+            drains[qi].clear();
     }
 };
 
@@ -722,10 +769,13 @@ int split_server_create(split_server **out, size_t budget_bytes, int32_t max_len
             (void)hipEventDestroy(ev);
         if (s->pub_event)
             (void)hipEventDestroy(s->pub_event);
-        for (hipStream_t st : {s->copy_stream, s->out_stream, s->drain_stream[0][0],
-                               s->drain_stream[0][1], s->drain_stream[1][0], s->drain_stream[1][1]})
+        for (hipStream_t st : {s->copy_stream, s->out_stream})
             if (st)
                 (void)hipStreamDestroy(st);
+        for (int q = 0; q < splitk::kServeQueues; ++q)
+            for (hipStream_t st : s->drain_stream[q])
+                if (st)
+                    (void)hipStreamDestroy(st);
         delete s;
         return sfail(code, "%s: %s", what, hipGetErrorString(e));
     };
@@ -738,7 +788,7 @@ int split_server_create(split_server **out, size_t budget_bytes, int32_t max_len
     const size_t queue_b = a256(sizeof(splitk::ServeQueue));
     const size_t scratch_b =
         a256((size_t)splitk::kServeScratchSlots * splitk::kTile * ((size_t)max_len + 1) * 4);
-    const size_t fixed = jobs_b + 2 * queue_b + scratch_b + 256;
+    const size_t fixed = jobs_b + splitk::kServeQueues * queue_b + scratch_b + 256;
     size_t budget = budget_bytes;
     if (budget == 0) { // a share of free device memory (adaptive batch size)
         size_t fr = 0, tot = 0;
@@ -763,10 +813,10 @@ int split_server_create(split_server **out, size_t budget_bytes, int32_t max_len
     char *p = s->dev_base;
     s->d_jobs = reinterpret_cast<splitk::ServeJob *>(p);
     p += jobs_b;
-    s->d_queue[0] = reinterpret_cast<splitk::ServeQueue *>(p);
-    p += queue_b;
-    s->d_queue[1] = reinterpret_cast<splitk::ServeQueue *>(p);
-    p += queue_b;
+    for (int q = 0; q < splitk::kServeQueues; ++q) {
+        s->d_queue[q] = reinterpret_cast<splitk::ServeQueue *>(p);
+        p += queue_b;
+    }
     s->d_scratch = reinterpret_cast<int *>(p);
     p += scratch_b;
     s->d_scratch_mask = reinterpret_cast<uint32_t *>(p);
@@ -795,12 +845,12 @@ int split_server_create(split_server **out, size_t budget_bytes, int32_t max_len
     e = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking);
     if (e == hipSuccess)
         e = hipStreamCreateWithFlags(&s->out_stream, hipStreamNonBlocking);
-    for (int q = 0; q < 2 && e == hipSuccess; ++q)
+    for (int q = 0; q < splitk::kServeQueues && e == hipSuccess; ++q)
         for (int k = 0; k < 2 && e == hipSuccess; ++k)
             e = hipStreamCreateWithFlags(&s->drain_stream[q][k], hipStreamNonBlocking);
     if (e != hipSuccess)
         return bail(SPLIT_EDEVICE, "stream creation", e);
-    for (int k = 0; k < 8 && e == hipSuccess; ++k) {
+    for (int k = 0; k < 4 * splitk::kServeQueues && e == hipSuccess; ++k) {
         hipEvent_t ev = nullptr;
         e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
         if (e == hipSuccess)
@@ -808,10 +858,11 @@ int split_server_create(split_server **out, size_t budget_bytes, int32_t max_len
     }
     if (e != hipSuccess)
         return bail(SPLIT_EDEVICE, "event creation", e);
-    s->drain_grid[0] = splitk::serve_drain_grid(false);
-    s->drain_grid[1] = splitk::serve_drain_grid(true);
-    if (s->drain_grid[0] < 1 || s->drain_grid[1] < 1)
-        return bail(SPLIT_EDEVICE, "drain occupancy", hipGetLastError());
+    for (int q = 0; q < splitk::kServeQueues; ++q) {
+        s->drain_grid[q] = splitk::serve_drain_grid(q);
+        if (s->drain_grid[q] < 1)
+            return bail(SPLIT_EDEVICE, "drain occupancy", hipGetLastError());
+    }
     s->ctl.jobs = s->d_jobs;
     s->ctl.results = s->h_results;
     s->ctl.scratch = s->d_scratch;
@@ -1076,10 +1127,13 @@ int split_server_destroy(split_server *s)
         (void)hipEventDestroy(ev);
     if (s->pub_event)
         (void)hipEventDestroy(s->pub_event);
-    for (hipStream_t st : {s->copy_stream, s->out_stream, s->drain_stream[0][0],
-                           s->drain_stream[0][1], s->drain_stream[1][0], s->drain_stream[1][1]})
+    for (hipStream_t st : {s->copy_stream, s->out_stream})
         if (st)
             (void)hipStreamDestroy(st);
+    for (int q = 0; q < splitk::kServeQueues; ++q)
+        for (hipStream_t st : s->drain_stream[q])
+            if (st)
+                (void)hipStreamDestroy(st);
     (void)hipFree(s->dev_base);
     (void)hipHostFree(s->pin_base);
     delete s;
