@@ -154,7 +154,8 @@ def emit_wrapper(R: int, first: int, every: int) -> str:
         ""])
 
 
-def main():
+def render() -> str:
+    """The generated file's text."""
     text = ["// window_argmin_asm.inc -- GENERATED by gen_argmin_asm.py; do not edit.",
             "// Masked window minimum and smallest minimising predecessor of one tour",
             "// position (see gen_argmin_asm.py).",
@@ -172,9 +173,13 @@ def main():
     for k, (R, f, e) in enumerate(combos):
         text.append("    X(%d, %d, %d)%s" % (R, f, e, " \\" if k + 1 < len(combos) else ""))
     text.append("")
+    return "\n".join(text)
+
+
+def main():
     path = os.path.join(HERE, "window_argmin_asm.inc")
-    with open(path, "w") as f:
-        f.write("\n".join(text))
+    with open(path, "w") as fh:
+        fh.write(render())
     print(path)
 
 

@@ -128,7 +128,8 @@ def emit_wrapper(R, first, group, every, L):
     return "\n".join(lines)
 
 
-def main():
+def render() -> str:
+    """The generated file's text."""
     text = ["// window_min_multi_asm.inc -- GENERATED by gen_multiring_asm.py; do not edit.",
             "// Masked window minimum of one tour position over L rings sharing one window",
             "// (see gen_multiring_asm.py).",
@@ -140,9 +141,13 @@ def main():
         for L in RING_COUNTS:
             text.append(emit(R, first, group, every, L))
             text.append(emit_wrapper(R, first, group, every, L))
+    return "\n".join(text)
+
+
+def main():
     path = os.path.join(HERE, "window_min_multi_asm.inc")
     with open(path, "w") as fh:
-        fh.write("\n".join(text))
+        fh.write(render())
     print(path)
 
 

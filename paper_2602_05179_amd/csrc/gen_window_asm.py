@@ -172,7 +172,8 @@ def emit_wrapper(R: int, first: int, group: int, every: int) -> str:
         ""])
 
 
-def main():
+def render() -> str:
+    """The generated file's text."""
     text = ["// window_min_asm.inc -- GENERATED by gen_window_asm.py; do not edit.",
             "// Masked window minimum of one tour position (see gen_window_asm.py).",
             "// WindowMin<R, F, G, E>::run<U>(f, lq, L, Ln, j, cp1, cp2, cn1, cn2, ov) returns m.",
@@ -189,9 +190,13 @@ def main():
     for k, (R, f, g, e) in enumerate(combos):
         text.append("    X(%d, %d, %d, %d)%s" % (R, f, g, e, " \\" if k + 1 < len(combos) else ""))
     text.append("")
+    return "\n".join(text)
+
+
+def main():
     path = os.path.join(HERE, "window_min_asm.inc")
-    with open(path, "w") as f:
-        f.write("\n".join(text))
+    with open(path, "w") as fh:
+        fh.write(render())
     print(path)
 
 

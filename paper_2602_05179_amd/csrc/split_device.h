@@ -50,7 +50,25 @@ __device__ __forceinline__ int wave_sum_i32(int v)
 // tile staging: int16 rows [rows x N] (contiguous) -> LDS bytes [rows x N]
 // returns false (uniformly) when some value is outside [0, 255]
 // s_bad: an LDS word outside the staged bytes (the block-wide "bad" flag)
+//
+// The 16-byte chunks of a thread are fetched kStageBatch at a time, all in
+// flight together before any is narrowed: a one-wave block stages a
+// 64 x 200 tile (25 chunks per lane) in two memory round trips instead of
+// one per four chunks.  The ring registers of the recursion are not live
+// yet, so the batch costs no occupancy.
 // ---------------------------------------------------------------------------
+constexpr int kStageBatch = 16;
+
+__device__ __forceinline__ uint2 narrow_chunk(const u32x4 v, uint32_t &bad)
+{
+    const uint32_t x0 = v.x, x1 = v.y, x2 = v.z, x3 = v.w;
+    bad |= (x0 | x1 | x2 | x3) & 0xFF00FF00u;
+    uint2 o;
+    o.x = __builtin_amdgcn_perm(x1, x0, 0x06040200u);
+    o.y = __builtin_amdgcn_perm(x3, x2, 0x06040200u);
+    return o;
+}
+
 __device__ __forceinline__ bool stage_tile_u8(const int16_t *__restrict__ src, uint8_t *lds,
                                               int64_t elems, int tid, int nthreads, int &s_bad)
 {
@@ -62,30 +80,16 @@ __device__ __forceinline__ bool stage_tile_u8(const int16_t *__restrict__ src, u
     GU32x4 *src4 = (GU32x4 *)reinterpret_cast<const u32x4 *>(src);
     GI16 *gsrc = (GI16 *)src;
     uint2 *dst8 = reinterpret_cast<uint2 *>(lds);
-    int64_t i = tid;
-    for (; i + 3 * nthreads < chunks; i += 4 * nthreads) {
-        u32x4 v[4];
+    for (int64_t i = tid; i < chunks; i += (int64_t)kStageBatch * nthreads) {
+        u32x4 v[kStageBatch];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            v[r] = __builtin_nontemporal_load(&src4[i + r * nthreads]);
+        for (int r = 0; r < kStageBatch; ++r)
+            if (i + (int64_t)r * nthreads < chunks)
+                v[r] = __builtin_nontemporal_load(&src4[i + (int64_t)r * nthreads]);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const uint32_t x0 = v[r].x, x1 = v[r].y, x2 = v[r].z, x3 = v[r].w;
-            bad |= (x0 | x1 | x2 | x3) & 0xFF00FF00u;
-            uint2 o;
-            o.x = __builtin_amdgcn_perm(x1, x0, 0x06040200u);
-            o.y = __builtin_amdgcn_perm(x3, x2, 0x06040200u);
-            dst8[i + r * nthreads] = o;
-        }
-    }
-    for (; i < chunks; i += nthreads) {
-        const u32x4 v = __builtin_nontemporal_load(&src4[i]);
-        const uint32_t x0 = v.x, x1 = v.y, x2 = v.z, x3 = v.w;
-        bad |= (x0 | x1 | x2 | x3) & 0xFF00FF00u;
-        uint2 o;
-        o.x = __builtin_amdgcn_perm(x1, x0, 0x06040200u);
-        o.y = __builtin_amdgcn_perm(x3, x2, 0x06040200u);
-        dst8[i] = o;
+        for (int r = 0; r < kStageBatch; ++r)
+            if (i + (int64_t)r * nthreads < chunks)
+                dst8[i + (int64_t)r * nthreads] = narrow_chunk(v[r], bad);
     }
     for (int64_t e = (chunks << 3) + tid; e < elems; e += nthreads) {
         const int v = gsrc[e];

@@ -130,7 +130,11 @@ struct DpRegsO {
     uint64_t cp2; // lanes rejecting d = F + G at position j (computed at j-1)
     int mres;     // m of the last position relaxed (m_n after the loop)
     int ovf;      // 1 when a window reached past the ring
-    u32x4 cur[2], nxt[2]; // demand bytes of the current / next 32 positions
+    // demand bytes of the lane's row, 32 positions per pair of registers:
+    // a holds bytes [j0, j0 + 32) and b bytes [j0 + 32, j0 + 64) of the
+    // current 64-position block; each is refilled with the bytes 64
+    // further on once its last byte has been read
+    u32x4 a[2], b[2];
 };
 
 __device__ __forceinline__ int byte_at(const u32x4 (&seg)[2], int b)
@@ -141,18 +145,24 @@ __device__ __forceinline__ int byte_at(const u32x4 (&seg)[2], int b)
     return (int)((x >> (8 * (b & 3))) & 0xFFu);
 }
 
-// position j = j0 + 1 + U of a block of R positions (j0 a multiple of R)
-template <int R, int F, int G, int E, int U, bool CHK> struct DpStateO {
-    __device__ __forceinline__ static bool run(int (&f)[R], int (&lq)[R], DpRegsO &r,
-                                               GU32x4 *row, int64_t segs, CInt *tab,
-                                               int j0, int n, int Q)
+// Position j = j0 + 1 + U of a 64-position block (j0 a multiple of 64).
+// The two 32-byte halves a and b stay in fixed registers: a is refilled
+// at U = 31, 32 positions before its next use, and b at U = 63, so no
+// register ever copies a load in flight (a rotation cur <- nxt would, and
+// would make the wave wait for the load at every block).
+template <int R, int F, int G, int E, int U> struct DpStateO {
+    __device__ __forceinline__ static void run(int (&f)[R], int (&lq)[R], DpRegsO &r,
+                                               GU32x4 *row, int64_t segs, CInt *tab, int j0,
+                                               int Q)
     {
         constexpr int SL = (U + 1) & (R - 1);
-        constexpr int B = U & 31; // byte of position j in the current segment
+        constexpr int B = U & 31;
         const int j = j0 + 1 + U;
-        if (CHK && j > n)
-            return false;
-        const int qn = B == 31 ? byte_at(r.nxt, 0) : byte_at(r.cur, B + 1);
+        // demand of position j + 1: byte U + 1 of the block
+        const int qn = U == 31 ? byte_at(r.b, 0)
+                       : U == 63 ? byte_at(r.a, 0)
+                       : U < 32  ? byte_at(r.a, B + 1)
+                                 : byte_at(r.b, B + 1);
         const int cj = r.t0.y;
         const int Ln = r.L + qn;
         r.t0 = r.t1;
@@ -166,25 +176,32 @@ template <int R, int F, int G, int E, int U, bool CHK> struct DpStateO {
         r.L = Ln;
         r.cp1 = cn1;
         r.cp2 = cn2;
-        if (B == 31) { // next 32 positions: rotate and prefetch the one after
-            r.cur[0] = r.nxt[0];
-            r.cur[1] = r.nxt[1];
-            const int64_t seg = (j + 32) >> 5; // segment holding positions j+33..j+64
+        if (U == 31 || U == 63) {
+            const int64_t seg = (j0 >> 5) + (U == 31 ? 2 : 3);
+            u32x4(&dst)[2] = U == 31 ? r.a : r.b;
             if (seg < segs) {
-                r.nxt[0] = __builtin_nontemporal_load(row + 2 * seg);
-                r.nxt[1] = __builtin_nontemporal_load(row + 2 * seg + 1);
+                dst[0] = __builtin_nontemporal_load(row + 2 * seg);
+                dst[1] = __builtin_nontemporal_load(row + 2 * seg + 1);
             }
         }
-        return true;
     }
 };
 
-template <int R, int F, int G, int E, bool CHK, int... Us>
-__device__ __forceinline__ bool dp_block_o(int (&f)[R], int (&lq)[R], DpRegsO &r, GU32x4 *row,
-                                           int64_t segs, CInt *tab, int j0, int n, int Q,
+template <int R, int F, int G, int E, int... Us>
+__device__ __forceinline__ void dp_block_o(int (&f)[R], int (&lq)[R], DpRegsO &r, GU32x4 *row,
+                                           int64_t segs, CInt *tab, int j0, int Q,
                                            std::integer_sequence<int, Us...>)
 {
-    return (DpStateO<R, F, G, E, Us, CHK>::run(f, lq, r, row, segs, tab, j0, n, Q) && ...);
+    (DpStateO<R, F, G, E, Us>::run(f, lq, r, row, segs, tab, j0, Q), ...);
+}
+
+// the tour's last block, positions j0 + 1 .. j0 + cnt (cnt < 64)
+template <int R, int F, int G, int E, int... Us>
+__device__ __forceinline__ void dp_partial_o(int (&f)[R], int (&lq)[R], DpRegsO &r, GU32x4 *row,
+                                             int64_t segs, CInt *tab, int j0, int cnt, int Q,
+                                             std::integer_sequence<int, Us...>)
+{
+    ((Us < cnt ? (DpStateO<R, F, G, E, Us>::run(f, lq, r, row, segs, tab, j0, Q), 0) : 0), ...);
 }
 
 template <int R, int F, int G, int E>
@@ -208,23 +225,23 @@ __device__ __forceinline__ int dp_lane_ordered(const uint8_t *rowb, int pitch, C
     r.t1 = tab_at(tab, 2);
     GU32x4 *row = (GU32x4 *)reinterpret_cast<const u32x4 *>(rowb);
     const int64_t segs = pitch / 32;
-    r.cur[0] = __builtin_nontemporal_load(row);
-    r.cur[1] = __builtin_nontemporal_load(row + 1);
+    r.a[0] = __builtin_nontemporal_load(row);
+    r.a[1] = __builtin_nontemporal_load(row + 1);
     if (segs > 1) {
-        r.nxt[0] = __builtin_nontemporal_load(row + 2);
-        r.nxt[1] = __builtin_nontemporal_load(row + 3);
+        r.b[0] = __builtin_nontemporal_load(row + 2);
+        r.b[1] = __builtin_nontemporal_load(row + 3);
     } else {
-        r.nxt[0] = r.cur[0];
-        r.nxt[1] = r.cur[1];
+        r.b[0] = u32x4{0u, 0u, 0u, 0u};
+        r.b[1] = r.b[0];
     }
-    r.L = byte_at(r.cur, 0);
+    r.L = byte_at(r.a, 0);
     int j0 = 0;
-    for (; j0 + R <= n; j0 += R) // blocks whose positions all exist
-        dp_block_o<R, F, G, E, false>(f, lq, r, row, segs, tab, j0, n, Q,
-                                      std::make_integer_sequence<int, R>{});
+    for (; j0 + 64 <= n; j0 += 64) // blocks whose positions all exist
+        dp_block_o<R, F, G, E>(f, lq, r, row, segs, tab, j0, Q,
+                               std::make_integer_sequence<int, 64>{});
     if (j0 < n) // the last, partial block
-        dp_block_o<R, F, G, E, true>(f, lq, r, row, segs, tab, j0, n, Q,
-                                     std::make_integer_sequence<int, R>{});
+        dp_partial_o<R, F, G, E>(f, lq, r, row, segs, tab, j0, n - j0, Q,
+                                 std::make_integer_sequence<int, 64>{});
     ovf = r.ovf != 0;
     return r.mres;
 }
