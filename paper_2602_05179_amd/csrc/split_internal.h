@@ -31,6 +31,7 @@ struct Workspace {
     int *vscratch;         // [fallback blocks * 64 * (max_len + 1)] value history
     uint8_t *tile_bad;     // [tiles] ordered path: tile needs the exact fallback (or null)
     uint8_t *perm;         // [T * S * pitch] ordered path: demands in tour order (or null)
+    int *order;            // [T] tour indices by decreasing length (batched fused path)
     int max_len;
 };
 

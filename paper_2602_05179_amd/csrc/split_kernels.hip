@@ -248,19 +248,32 @@ constexpr int kMaxWavesPerGroup = 8;
 template <int R, int F, int G, int E>
 __global__ __launch_bounds__(kWave *kMaxWavesPerGroup) void split_tile_kernel(
     const int16_t *__restrict__ demands, int32_t N, int64_t S, int32_t Q, int32_t T,
-    int32_t *__restrict__ costs, Workspace ws, int32_t use_lds)
+    int32_t *__restrict__ costs, Workspace ws, int32_t use_lds, int32_t by_length)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     const int W = blockDim.x / kWave;
     const int NG = (T + W - 1) / W;
     const int64_t b = blockIdx.x;
-    const int64_t k = b / NG;
-    const int g = (int)(b - k * NG);
+    // by_length: tours taken in decreasing length (groups of similar
+    // length finish together), group-major so the longest work starts
+    // first; otherwise tile-major, so the groups sharing a tile run close
+    // together and the tile is read from HBM about once
+    int64_t k;
+    int g;
+    if (by_length) {
+        const int64_t tiles = (S + kWave - 1) / kWave;
+        g = (int)(b / tiles);
+        k = b - (int64_t)g * tiles;
+    } else {
+        k = b / NG;
+        g = (int)(b - k * NG);
+    }
     const int lane = threadIdx.x & (kWave - 1);
     // uniform within the wave; readfirstlane lets the compiler keep the
     // tour's scalars (length, table pointer) in SGPRs
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int t = g * W + wave;
+    const int slot = g * W + wave;
+    const int t = by_length && slot < T ? __builtin_amdgcn_readfirstlane(ws.order[slot]) : slot;
     const int64_t s0 = k * kWave;
     const int rows = (int)min<int64_t>(kWave, S - s0);
 
@@ -584,6 +597,29 @@ __global__ void zero_i64_kernel(int64_t *p, int32_t n)
 
 int64_t num_tiles(int64_t S) { return (S + kTile - 1) / kTile; }
 
+// order[r] = the tour of rank r by decreasing length (ties by index); an
+// invalid length ranks as 0 (its waves return at once).  One block; the
+// rank of a tour is a count over all tours, O(T^2 / threads) per launch.
+constexpr int kOrderThreads = 1024;
+constexpr int32_t kOrderMaxTours = 4096;
+
+__global__ __launch_bounds__(kOrderThreads) void order_kernel(const int32_t *__restrict__ lens,
+                                                              int32_t T, int32_t max_len,
+                                                              int *__restrict__ order)
+{
+    for (int i = threadIdx.x; i < T; i += kOrderThreads) {
+        const int li = lens[i];
+        const int ni = li < 0 || li > max_len ? 0 : li;
+        int rank = 0;
+        for (int j = 0; j < T; ++j) {
+            const int lj = lens[j];
+            const int nj = lj < 0 || lj > max_len ? 0 : lj;
+            rank += (nj > ni || (nj == ni && j < i)) ? 1 : 0;
+        }
+        order[rank] = i;
+    }
+}
+
 hipError_t launch_prep(const int32_t *tours, const int32_t *lens, int32_t T, int32_t max_len,
                        const int32_t *dist, int32_t N, const Workspace &ws, hipStream_t stream)
 {
@@ -637,6 +673,7 @@ size_t workspace_bytes(int32_t T, int32_t max_len, int32_t N, int64_t S, bool or
     b += align256(units * sizeof(int));
     b += align256(2 * sizeof(int));
     b += align256((size_t)kFallbackBlocks * kWave * ((size_t)max_len + 1) * sizeof(int));
+    b += align256((size_t)T * sizeof(int));
     if (ordered) {
         b += align256((size_t)num_tiles(S));
         b += align256((size_t)T * (size_t)S * (size_t)ordered_pitch(max_len));
@@ -666,6 +703,8 @@ Workspace carve_workspace(void *base, int32_t T, int32_t max_len, int32_t N, int
     p += align256(2 * sizeof(int));
     ws.vscratch = reinterpret_cast<int *>(p);
     p += align256((size_t)kFallbackBlocks * kWave * ((size_t)max_len + 1) * sizeof(int));
+    ws.order = reinterpret_cast<int *>(p);
+    p += align256((size_t)T * sizeof(int));
     ws.tile_bad = nullptr;
     ws.perm = nullptr;
     if (ordered) {
@@ -731,9 +770,12 @@ hipError_t launch_permute(const int16_t *demands, int32_t N, int64_t S, int32_t 
     return hipGetLastError();
 }
 
+constexpr int64_t kOrderMaxDemandBytes = 64ll << 20;
+
 template <int R, int F, int G, int E>
 static hipError_t launch_tiles(const int16_t *demands, int32_t N, int64_t S, int32_t Q, int32_t T,
-                               int32_t *costs, const Workspace &ws, hipStream_t stream, int W)
+                               const int32_t *lens, int32_t *costs, const Workspace &ws,
+                               hipStream_t stream, int W)
 {
     const int NG = (T + W - 1) / W;
     const int64_t groups = (int64_t)NG * num_tiles(S);
@@ -756,9 +798,23 @@ static hipError_t launch_tiles(const int16_t *demands, int32_t N, int64_t S, int
     }
     const int use_lds = lds <= (size_t)lds_limit ? 1 : 0;
     const size_t lds_bytes = use_lds ? lds : 0;
+    // Ragged tours in decreasing length when there are several groups and
+    // the demand matrix is small enough to stay in the last-level cache
+    // while every group stages its copy of a tile.
+    const int by_length = lens && NG > 1 && T <= kOrderMaxTours &&
+                                  (int64_t)S * N * (int64_t)sizeof(int16_t) <= kOrderMaxDemandBytes
+                              ? 1
+                              : 0;
+    if (by_length) {
+        hipLaunchKernelGGL(order_kernel, dim3(1), dim3(kOrderThreads), 0, stream, lens, T,
+                           ws.max_len, ws.order);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
     hipLaunchKernelGGL((split_tile_kernel<R, F, G, E>), dim3((unsigned)groups),
                        dim3(kWave * W), lds_bytes, stream, demands, N, S, Q, T, costs, ws,
-                       use_lds);
+                       use_lds, by_length);
     return hipGetLastError();
 }
 
@@ -794,7 +850,7 @@ hipError_t launch_eval(const int32_t *tours, const int32_t *lens, int32_t T, int
     } else {
 #define SPLIT_LAUNCH(R_, F_, G_, E_)                                                             \
     if (sched.ring == R_ && sched.first == F_ && sched.group == G_ && sched.every == E_)          \
-        e = launch_tiles<R_, F_, G_, E_>(demands, N, S, Q, T, costs, ws, stream,                  \
+        e = launch_tiles<R_, F_, G_, E_>(demands, N, S, Q, T, lens, costs, ws, stream,            \
                                          sched.waves ? sched.waves : waves_per_group(T, N));
         SPLIT_WINDOW_VARIANTS(SPLIT_LAUNCH)
 #undef SPLIT_LAUNCH

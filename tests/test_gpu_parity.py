@@ -106,6 +106,31 @@ def test_batched_ragged_and_equal_to_plain(binding):
         assert one["sums"][0] == got["sums"][t]
 
 
+def test_batched_by_length_ties_empty_and_invalid(binding):
+    """Ragged batch taken in decreasing length: equal lengths, empty tours
+    and an invalid tour in the batch; every valid tour equals the oracle."""
+    rng = np.random.default_rng(21)
+    N, S, Q = 60, 700, 40
+    dist = W.dist_round(W.coords(rng, N))
+    dem = W.demands_poisson(rng, S, rng.uniform(2.0, 9.0, size=N))
+    sizes = [30, 30, 0, 50, 30, 50, 10, 60, 0, 30, 45, 45, 7, 60, 30, 12, 50, 1, 30, 25]
+    tours_list = [W.random_tour(rng, N)[:k] if k else np.zeros(0, np.int32) for k in sizes]
+    lens = np.array(sizes, np.int32)
+    tours = np.concatenate(tours_list).astype(np.int32)
+    bad = int(lens[:5].sum()) + 3  # tour 5 gets an invalid customer id
+    tours_bad = tours.copy()
+    tours_bad[bad] = N + 1
+    got = _device_eval(binding, tours_bad, lens, dist, dem, Q)
+    ref = oracle.split_eval(tours, lens, dist, dem, Q, nthreads=THREADS)
+    for t in range(len(sizes)):
+        if t == 5:
+            assert got["sums"][t] == binding.SPLIT_SUM_INVALID
+            assert (got["costs"][t] == binding.SPLIT_INF).all()
+        else:
+            assert np.array_equal(got["costs"][t], ref["costs"][t]), t
+            assert got["sums"][t] == ref["sums"][t], t
+
+
 # ----------------------------------------------------------------------------
 # edge cases
 # ----------------------------------------------------------------------------
