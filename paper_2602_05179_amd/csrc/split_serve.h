@@ -49,8 +49,8 @@ struct alignas(128) ServePart {
 // claiming one of its tiles.
 struct alignas(128) ServeJob {
     const int16_t *demands; // [S][N] scenario-major
-    const uint8_t *perm;    // ordered path: [S][pitch] tour-ordered bytes (else null)
-    const uint8_t *tile_bad; // ordered path: [tiles] tile needs the exact path (else null)
+    const uint8_t *perm;    // ordered path: [S][pitch] tour-ordered bytes, written by the
+                            // drain wave that runs each tile (else null)
     const int2 *tab;        // [n + kTabPad] {customer index, c_j}, entry 0 and pads zero
     const int2 *ab;         // [n] {a_j, b_j}
     int32_t *costs;         // [S] per-scenario V(n) or SPLIT_INF
@@ -100,15 +100,12 @@ struct ServeCtl {
 // launchers (split_serve.hip)
 hipError_t serve_launch_drain(int queue, const ServeCtl &ctl, ServeQueue *q, int grid,
                               hipStream_t stream);
-int serve_drain_grid(int queue); // workgroups that fill the device
-// One admission round, three launches on the scheduler's copy stream:
+int serve_drain_grid(int queue, int32_t max_len); // workgroups that fill the device
+// One admission round, two launches on the scheduler's copy stream:
 //   admit   -- one workgroup per job: its tables (tab, ab, rec) from its
 //              pinned staging area into its arena block, its descriptor into
 //              the job table (each slot's staging area holds the descriptor,
 //              then the tables as laid out in the arena block);
-//   permute -- one workgroup per 64-scenario tile of the round's jobs on
-//              large pools: the tile's demands in tour order (the tour-ordered
-//              copy the ordered drain streams) and its exact-path flag;
 //   publish -- one wave: the slots appended to their queues (entry = slot |
 //              queue << 28), new tails published with release order.
 constexpr int kPublishMax = 255;
@@ -117,20 +114,12 @@ struct AdmitBatch {
     int32_t count;
     int32_t slot[kPublishMax];
 };
-struct PermuteBatch {
-    int32_t count;                   // jobs on the ordered path
-    int32_t slot[kPublishMax];
-    int32_t tile0[kPublishMax + 1]; // prefix sums of the jobs' tile counts
-};
 struct PublishBatch {
     int32_t count;
     int32_t entry[kPublishMax];
 };
 hipError_t serve_launch_admit(ServeJob *jobs, const char *stage_base, size_t stage_bytes,
                               const AdmitBatch &batch, hipStream_t stream);
-// max_n: the longest tour in the batch
-hipError_t serve_launch_permute(const ServeJob *jobs, const PermuteBatch &batch,
-                                int32_t max_n, hipStream_t stream);
 struct ServeQueues {
     ServeQueue *q[kServeQueues];
 };

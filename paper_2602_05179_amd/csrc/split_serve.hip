@@ -21,8 +21,9 @@
 // value history from a small scratch pool.
 //
 // Two drains exist: the fused one stages the tile's rows in LDS (pools of
-// at most kServeFusedMaxN customers); the ordered one streams each lane's
-// row of the tour-ordered copy that a permute launch wrote at admission.
+// at most kServeFusedMaxN customers); the ordered one first writes the
+// tile's rows in tour order into the job's copy (gathered from the demand
+// rows by the same wave) and then streams each lane's row of that copy.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -62,7 +63,6 @@ template <typename T> __device__ __forceinline__ T *uptr(T *p)
 struct JobView {
     const int16_t *demands;
     const uint8_t *perm;
-    const uint8_t *tile_bad;
     const int2 *tab;
     const int2 *ab;
     int32_t *costs;
@@ -75,7 +75,6 @@ __device__ __forceinline__ JobView read_job(const ServeJob *j)
     JobView v;
     v.demands = uptr(ld_agent(&j->demands));
     v.perm = uptr(ld_agent(&j->perm));
-    v.tile_bad = uptr(ld_agent(&j->tile_bad));
     v.tab = uptr(ld_agent(&j->tab));
     v.ab = uptr(ld_agent(&j->ab));
     v.costs = uptr(ld_agent(&j->costs));
@@ -217,6 +216,64 @@ __device__ int exact_tile(const ServeCtl &ctl, const JobView &jv, int64_t s0, in
     return v;
 }
 
+// The tile's rows in tour order into the job's copy: byte j - 1 of row s is
+// the demand of position j (zero from n to the pitch).  Consecutive lanes
+// take consecutive 16-position chunks of one row, so a load instruction
+// touches a few lines of that row; two chunks per lane are in flight at
+// once.  cust: the tour's customer indices (LDS).  Returns false
+// (uniformly) when a demand lies outside [0, 255].
+constexpr int kGatherChunks = 2;
+
+__device__ bool gather_tile(const JobView &jv, int64_t s0, int rows, const uint16_t *cust,
+                            int lane)
+{
+    const int chunks = jv.pitch / 16;
+    const int total = rows * chunks;
+    uint8_t *dst = const_cast<uint8_t *>(jv.perm) + s0 * jv.pitch;
+    uint32_t bad = 0;
+    for (int base = 0; base < total; base += kGatherChunks * kWave) {
+        int v[kGatherChunks][16];
+#pragma unroll
+        for (int u = 0; u < kGatherChunks; ++u) {
+            const int idx = base + u * kWave + lane;
+            const int r = idx / chunks;
+            const int c = idx - r * chunks;
+            const int16_t *row = jv.demands + (s0 + r) * jv.N;
+#pragma unroll
+            for (int b = 0; b < 16; ++b) {
+                const int j = c * 16 + b;
+                v[u][b] = idx < total && j < jv.n ? row[cust[j]] : 0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kGatherChunks; ++u) {
+            const int idx = base + u * kWave + lane;
+            if (idx >= total)
+                continue;
+            const int r = idx / chunks;
+            const int c = idx - r * chunks;
+            uint32_t w[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint32_t x = 0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int val = v[u][q * 4 + b];
+                    bad |= (uint32_t)val & 0xFFFFFF00u; // outside [0, 255]
+                    x |= ((uint32_t)val & 0xFFu) << (8 * b);
+                }
+                w[q] = x;
+            }
+            const u32x4 o = {w[0], w[1], w[2], w[3]};
+            reinterpret_cast<u32x4 *>(dst + (int64_t)r * jv.pitch)[c] = o;
+        }
+    }
+    // the stores complete before the recursion of this wave reads them back
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
+    return ballot(bad != 0) == 0;
+}
+
 template <bool ORDERED, bool WIDE>
 __device__ __forceinline__ int fast_tile(const JobView &jv, const uint8_t *lds, int64_t s0,
                                          int lane, int rows, bool &ovf)
@@ -256,6 +313,7 @@ struct TileAcc {
 template <bool ORDERED, bool WIDE>
 __device__ void run_tile(const ServeCtl &ctl, const JobView &jv, int tile, uint8_t *lds,
                          int lane, TileAcc &acc)
+// (ordered drain: lds holds the tour's customer indices)
 {
     const int64_t s0 = (int64_t)tile * kWave;
     const int rows = (int)min<int64_t>(kWave, jv.S - s0);
@@ -264,7 +322,7 @@ __device__ void run_tile(const ServeCtl &ctl, const JobView &jv, int tile, uint8
     if (jv.n > 0) {
         bool ok;
         if (ORDERED) {
-            ok = jv.tile_bad[tile] == 0;
+            ok = gather_tile(jv, s0, rows, reinterpret_cast<const uint16_t *>(lds), lane);
         } else {
             int &s_bad = *reinterpret_cast<int *>(lds + (((size_t)kWave * kServeFusedMaxN + 15) &
                                                           ~(size_t)15));
@@ -340,9 +398,9 @@ __device__ void finish_chunk(const ServeCtl &ctl, const JobView &jv, int slot, i
 } // namespace
 
 // grid of one-wave workgroups; LDS: the fused drain's tile (kServeFusedMaxN
-// bytes per row) plus the staging flag
+// bytes per row) plus the staging flag, or the ordered drain's tour
 template <bool ORDERED, bool WIDE>
-__global__ __launch_bounds__(kWave) void serve_drain_kernel(ServeCtl ctl, ServeQueue *q)
+__device__ __forceinline__ void drain(ServeCtl ctl, ServeQueue *q)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     const int lane = threadIdx.x;
@@ -355,14 +413,39 @@ __global__ __launch_bounds__(kWave) void serve_drain_kernel(ServeCtl ctl, ServeQ
     bool fresh;
     while (claim(q, ctl.jobs, start, idle_since, ctl, lane, home, cc, slot, tile, count, part,
                  fresh)) {
-        if (fresh) // a job this wave has not run before: its descriptor
+        if (fresh) { // a job this wave has not run before: its descriptor
             jv = read_job(ctl.jobs + slot);
+            if (ORDERED) { // and its tour's customer order for the gather
+                uint16_t *cust = reinterpret_cast<uint16_t *>(lds);
+                for (int j = lane; j < jv.n; j += kWave)
+                    cust[j] = (uint16_t)jv.tab[j + 1].x;
+                __syncthreads();
+            }
+        }
         TileAcc acc{0, 0, false, false};
         for (int i = 0; i < count; ++i)
             run_tile<ORDERED, WIDE>(ctl, jv, tile + i, lds, lane, acc);
         finish_chunk(ctl, jv, slot, part, count, acc, lane);
         idle_since = ticks();
     }
+}
+
+// one kernel per queue
+__global__ __launch_bounds__(kWave) void serve_drain_fused32(ServeCtl ctl, ServeQueue *q)
+{
+    drain<false, false>(ctl, q);
+}
+__global__ __launch_bounds__(kWave) void serve_drain_fused64(ServeCtl ctl, ServeQueue *q)
+{
+    drain<false, true>(ctl, q);
+}
+__global__ __launch_bounds__(kWave) void serve_drain_ordered32(ServeCtl ctl, ServeQueue *q)
+{
+    drain<true, false>(ctl, q);
+}
+__global__ __launch_bounds__(kWave) void serve_drain_ordered64(ServeCtl ctl, ServeQueue *q)
+{
+    drain<true, true>(ctl, q);
 }
 
 // one workgroup per admitted job: its tables (tab, ab, rec, as laid out in
@@ -392,78 +475,6 @@ __global__ __launch_bounds__(kAdmitThreads) void serve_admit_kernel(ServeJob *jo
         jd[w] = js[w];
 }
 
-// one workgroup per 64-scenario tile of the round's ordered jobs: the
-// tile's demands rewritten in tour order (one byte each, row pitch `pitch`)
-// for the ordered drain, and its flag (1: a demand outside 0..255, the
-// drain runs the exact recursion).  The tour's customer order sits in LDS;
-// each thread gathers 16 positions of one row straight from the row in
-// global memory (consecutive threads share a row, so its few cache lines
-// serve them all).  The kernel needs only a small LDS block and few
-// registers, so its workgroups find room beside running drain waves (the
-// drains leave one wave slot per SIMD free).
-constexpr int kServePermThreads = 256;
-
-__global__ __launch_bounds__(kServePermThreads) void serve_permute_kernel(const ServeJob *jobs,
-                                                                          PermuteBatch batch)
-{
-    extern __shared__ __align__(16) uint8_t lds[];
-    const int k = blockIdx.x;
-    int lo = 0, hi = batch.count - 1; // the job: the last one whose first tile is <= k
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (batch.tile0[mid] <= k)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    const ServeJob *jb = jobs + batch.slot[lo];
-    const int tile = k - batch.tile0[lo];
-    const int16_t *demands = jb->demands;
-    uint8_t *perm = const_cast<uint8_t *>(jb->perm);
-    uint8_t *tile_bad = const_cast<uint8_t *>(jb->tile_bad);
-    const int2 *tab = jb->tab;
-    const int64_t S = jb->S;
-    const int N = jb->N, n = jb->n, pitch = jb->pitch;
-    const int64_t s0 = (int64_t)tile * kWave;
-    const int rows = (int)min<int64_t>(kWave, S - s0);
-    const int chunks = pitch / 16;
-    uint8_t *dst = perm + s0 * pitch;
-    const int tid = threadIdx.x;
-    int &s_bad = *reinterpret_cast<int *>(lds);
-    uint16_t *cust = reinterpret_cast<uint16_t *>(lds + 16);
-    if (tid == 0)
-        s_bad = 0;
-    for (int j = tid; j < n; j += kServePermThreads)
-        cust[j] = (uint16_t)tab[j + 1].x;
-    __syncthreads();
-    uint32_t bad = 0;
-    for (int idx = tid; idx < rows * chunks; idx += kServePermThreads) {
-        const int r = idx / chunks;
-        const int c = idx - r * chunks;
-        const int16_t *row = demands + (s0 + r) * N;
-        uint32_t w[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            uint32_t x = 0;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int j = c * 16 + q * 4 + b;
-                const int v = j < n ? row[cust[j]] : 0;
-                bad |= (v < 0 || v > 255) ? 1u : 0u;
-                x |= ((uint32_t)v & 0xFFu) << (8 * b);
-            }
-            w[q] = x;
-        }
-        u32x4 o = {w[0], w[1], w[2], w[3]};
-        __builtin_nontemporal_store(o, reinterpret_cast<u32x4 *>(dst + (int64_t)r * pitch) + c);
-    }
-    if (ballot(bad != 0) != 0 && (tid & (kWave - 1)) == 0)
-        atomicOr(&s_bad, 1);
-    __syncthreads();
-    if (tid == 0)
-        tile_bad[tile] = s_bad ? 1 : 0;
-}
-
 // one wave: the batch's slots appended to their queues, the new tails
 // published with release order (the jobs' descriptors and tables were
 // written by the launches before it on the same stream)
@@ -488,27 +499,29 @@ __global__ __launch_bounds__(kWave) void serve_publish_kernel(ServeQueues queues
     }
 }
 
-static size_t drain_lds(bool ordered)
+// LDS of a drain wave: the fused drain's tile (kServeFusedMaxN bytes per
+// row) and staging flag; the ordered drain's tour (u16 per position)
+static size_t drain_lds(bool ordered, int32_t max_len)
 {
-    return ordered ? 0 : (((size_t)kWave * kServeFusedMaxN + 15) & ~(size_t)15) + 16;
+    return ordered ? (2 * (size_t)max_len + 15) & ~(size_t)15
+                   : (((size_t)kWave * kServeFusedMaxN + 15) & ~(size_t)15) + 16;
 }
 
-template <bool ORDERED, bool WIDE> static const void *drain_fn()
-{
-    return reinterpret_cast<const void *>(&serve_drain_kernel<ORDERED, WIDE>);
-}
+typedef void (*DrainKernel)(ServeCtl, ServeQueue *);
 
-static const void *drain_fn(int queue)
+static DrainKernel drain_kernel(int queue)
 {
     switch (queue) {
-    case 0: return drain_fn<false, false>();
-    case 1: return drain_fn<false, true>();
-    case 2: return drain_fn<true, false>();
-    default: return drain_fn<true, true>();
+    case 0: return serve_drain_fused32;
+    case 1: return serve_drain_fused64;
+    case 2: return serve_drain_ordered32;
+    default: return serve_drain_ordered64;
     }
 }
 
-int serve_drain_grid(int queue)
+static const void *drain_fn(int queue) { return reinterpret_cast<const void *>(drain_kernel(queue)); }
+
+int serve_drain_grid(int queue, int32_t max_len)
 {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -516,12 +529,12 @@ int serve_drain_grid(int queue)
         return 0;
     const bool ordered = serve_queue_ordered(queue);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, drain_fn(queue), kWave,
-                                                     drain_lds(ordered)) != hipSuccess ||
+                                                     drain_lds(ordered, max_len)) != hipSuccess ||
         per < 1)
         per = 1;
     // leave one wave slot per SIMD (and the LDS and registers it needs) to
-    // the admission launches, so a round's permute is not held up until
-    // drain waves retire
+    // the admission launches, so a round is not held up until drain waves
+    // retire
     if (per >= 8)
         per -= 4;
     else if (per >= 2)
@@ -532,25 +545,8 @@ int serve_drain_grid(int queue)
 hipError_t serve_launch_drain(int queue, const ServeCtl &ctl, ServeQueue *q, int grid,
                               hipStream_t stream)
 {
-    const size_t lds = drain_lds(serve_queue_ordered(queue));
-    switch (queue) {
-    case 0:
-        hipLaunchKernelGGL((serve_drain_kernel<false, false>), dim3(grid), dim3(kWave), lds,
-                           stream, ctl, q);
-        break;
-    case 1:
-        hipLaunchKernelGGL((serve_drain_kernel<false, true>), dim3(grid), dim3(kWave), lds,
-                           stream, ctl, q);
-        break;
-    case 2:
-        hipLaunchKernelGGL((serve_drain_kernel<true, false>), dim3(grid), dim3(kWave), lds,
-                           stream, ctl, q);
-        break;
-    default:
-        hipLaunchKernelGGL((serve_drain_kernel<true, true>), dim3(grid), dim3(kWave), lds,
-                           stream, ctl, q);
-        break;
-    }
+    const size_t lds = drain_lds(serve_queue_ordered(queue), ctl.max_len);
+    hipLaunchKernelGGL(drain_kernel(queue), dim3(grid), dim3(kWave), lds, stream, ctl, q);
     return hipGetLastError();
 }
 
@@ -559,24 +555,6 @@ hipError_t serve_launch_admit(ServeJob *jobs, const char *stage_base, size_t sta
 {
     hipLaunchKernelGGL(serve_admit_kernel, dim3(batch.count), dim3(kAdmitThreads), 0, stream,
                        jobs, stage_base, stage_bytes, batch);
-    return hipGetLastError();
-}
-
-hipError_t serve_launch_permute(const ServeJob *jobs, const PermuteBatch &batch,
-                                int32_t max_n, hipStream_t stream)
-{
-    static bool attr = false;
-    if (!attr) {
-        const hipError_t e =
-            hipFuncSetAttribute(reinterpret_cast<const void *>(&serve_permute_kernel),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, kLdsLimit);
-        if (e != hipSuccess)
-            return e;
-        attr = true;
-    }
-    const int32_t tiles = batch.tile0[batch.count];
-    hipLaunchKernelGGL(serve_permute_kernel, dim3((unsigned)tiles), dim3(kServePermThreads),
-                       (size_t)16 + 2 * ((size_t)max_n + 1), stream, jobs, batch);
     return hipGetLastError();
 }
 

@@ -13,8 +13,8 @@
 // its batches from free GPU memory, App. B; here admission against the
 // arena plays that role and nothing is allocated per request).  Admission
 // copies the request's tables into its arena block on the copy stream
-// (from per-slot pinned staging), runs the permute launch for large pools,
-// and a one-wave publish kernel appends the jobs to a device work queue.
+// (from per-slot pinned staging), and a one-wave publish kernel appends the
+// jobs to a device work queue.
 // Drain kernels (split_serve.hip) take tiles from the queue; the scheduler
 // keeps at most two drains per queue in flight and launches the next one
 // while work remains.  The wave that finishes a job's last tile writes its
@@ -241,12 +241,10 @@ struct split_server {
         size_t b = 0;
         b += a256(((size_t)r.n + splitk::kTabPad) * sizeof(int2)); // tab
         b += a256((size_t)std::max(r.n, 1) * sizeof(int2));        // ab
-        b += a256(sizeof(splitk::TourRec));                         // rec (permute)
+        b += a256(sizeof(splitk::TourRec));                         // rec
         b += a256((size_t)S * 4);                                   // costs
-        if (r.ordered) {
-            b += a256((size_t)splitk::num_tiles(S));              // tile_bad
+        if (r.ordered)
             b += a256((size_t)S * (size_t)r.pitch);               // tour-ordered copy
-        }
         if (r.inst->transient)
             b += a256((size_t)S * r.inst->N * 2);                 // own demands
         return b;
@@ -269,7 +267,7 @@ struct split_server {
         }
     }
 
-    // Admits one request: staging, copies, permute.  Returns false when
+    // Admits one request: staging and copies.  Returns false when
     // resources are short (the request stays pending).
     bool admit(Request *r, std::vector<Request *> &batch)
     {
@@ -303,10 +301,8 @@ struct split_server {
         o += a256(sizeof(splitk::TourRec));
         int32_t *d_costs = reinterpret_cast<int32_t *>(blk + o);
         o += a256((size_t)S * 4);
-        uint8_t *d_bad = nullptr, *d_perm = nullptr;
+        uint8_t *d_perm = nullptr;
         if (r->ordered) {
-            d_bad = reinterpret_cast<uint8_t *>(blk + o);
-            o += a256((size_t)splitk::num_tiles(S));
             d_perm = reinterpret_cast<uint8_t *>(blk + o);
             o += a256((size_t)S * (size_t)r->pitch);
         }
@@ -329,7 +325,7 @@ struct split_server {
 
         // pinned staging of this slot: the job descriptor, then tab, ab, rec
         // laid out as in the arena block (the round's admit launch copies
-        // them; the permute launch writes the tour-ordered copy)
+        // them; the drain wave that runs a tile writes its tour-ordered rows)
         char *st = h_stage + (size_t)r->slot * stage_bytes + splitk::kStageHead;
         const size_t tab_b = ((size_t)r->n + splitk::kTabPad) * sizeof(int2);
         const size_t ab_b = (size_t)r->n * sizeof(int2);
@@ -349,7 +345,6 @@ struct split_server {
         splitk::ServeJob j{};
         j.demands = d_dem;
         j.perm = d_perm;
-        j.tile_bad = d_bad;
         j.tab = d_tab;
         j.ab = d_ab;
         j.costs = d_costs;
@@ -380,9 +375,8 @@ struct split_server {
     }
 
     // The round's launches on the copy stream, after any demand copies of
-    // its requests: admit (tables and descriptors), permute (tour-ordered
-    // copies of the jobs on large pools), publish (queue append), at most
-    // kPublishMax jobs per group.
+    // its requests: admit (tables and descriptors), then publish (queue
+    // append), at most kPublishMax jobs per group.
     void publish(std::vector<Request *> &batch)
     {
         if (batch.empty() || failed)
@@ -391,48 +385,18 @@ struct split_server {
             const int cnt = (int)std::min(batch.size() - i, (size_t)splitk::kPublishMax);
             splitk::AdmitBatch ab{};
             splitk::PublishBatch pb{};
-            splitk::PermuteBatch mb{};
             ab.count = cnt;
             pb.count = cnt;
-            int32_t max_n = 1;
             for (int k = 0; k < cnt; ++k) {
                 const Request *r = batch[i + k];
                 ab.slot[k] = r->slot;
                 pb.entry[k] = r->slot | (splitk::serve_queue(r->ordered, r->variant) << 28);
-                if (r->ordered)
-                    max_n = std::max(max_n, r->n);
             }
             hipError_t e = splitk::serve_launch_admit(d_jobs, h_stage, stage_bytes, ab, copy_stream);
             if (e != hipSuccess) {
                 fail_all("admit launch", e);
                 return;
             }
-            auto flush_permute = [&]() -> bool {
-                if (mb.count == 0)
-                    return true;
-                const hipError_t pe = splitk::serve_launch_permute(d_jobs, mb, max_n, copy_stream);
-                if (pe != hipSuccess) {
-                    fail_all("permute launch", pe);
-                    return false;
-                }
-                mb.count = 0;
-                mb.tile0[0] = 0;
-                return true;
-            };
-            mb.tile0[0] = 0;
-            for (int k = 0; k < cnt; ++k) {
-                const Request *r = batch[i + k];
-                if (!r->ordered || r->n == 0)
-                    continue;
-                const int64_t tiles = splitk::num_tiles(r->inst->S);
-                if (mb.count > 0 && (int64_t)mb.tile0[mb.count] + tiles > (1 << 30) && !flush_permute())
-                    return;
-                mb.slot[mb.count] = r->slot;
-                mb.tile0[mb.count + 1] = (int32_t)(mb.tile0[mb.count] + tiles);
-                mb.count++;
-            }
-            if (!flush_permute())
-                return;
             splitk::ServeQueues qs{};
             for (int q = 0; q < splitk::kServeQueues; ++q)
                 qs.q[q] = d_queue[q];
@@ -859,7 +823,7 @@ int split_server_create(split_server **out, size_t budget_bytes, int32_t max_len
     if (e != hipSuccess)
         return bail(SPLIT_EDEVICE, "event creation", e);
     for (int q = 0; q < splitk::kServeQueues; ++q) {
-        s->drain_grid[q] = splitk::serve_drain_grid(q);
+        s->drain_grid[q] = splitk::serve_drain_grid(q, s->max_len);
         if (s->drain_grid[q] < 1)
             return bail(SPLIT_EDEVICE, "drain occupancy", hipGetLastError());
     }
