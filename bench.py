@@ -596,7 +596,7 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-requests", type=int, default=10_000)
     ap.add_argument("--served-pool", type=int, default=32)
-    ap.add_argument("--budget-gb", type=float, default=2.0)
+    ap.add_argument("--budget-gb", type=float, default=8.0)
     ap.add_argument("--calibration-copy", action="store_true",
                     help="also run a plain device copy of the demand tensor (HBM counter scale)")
     args = ap.parse_args()

@@ -21,10 +21,15 @@
 // result to pinned host memory, which the scheduler polls: no event or
 // allocation per request.
 //
-// Reuse of device memory: a retired job's arena block and table slot are
-// released only once every drain that was running when it retired has
-// ended, so no running drain can hold cached lines of memory that a later
-// job reuses.
+// Reuse of device memory: a job has two arena blocks.  Its tables (and the
+// demands of a request that brought its own instance), which drains read
+// through the scalar and vector caches, are released with its table slot
+// only once every drain that was running when it retired has ended, so no
+// running drain can hold cached lines of memory that a later job reuses.
+// Its costs and tour-ordered copy are released at retirement: drains never
+// read the costs, and a drain wave reads only the tour-ordered rows it has
+// just written itself (its own stores, made visible to the wave by a
+// workgroup-scope fence), so stale lines of that memory are never read.
 //
 // The server's own reservation follows the paper's adaptive batching
 // (App. B, Alg. "GPU-Based DP with Adaptive Batching"): the budget defaults
@@ -153,8 +158,11 @@ struct Request {
     int32_t f0 = 0, bn = 0, variant = 0, pitch = 0;
     int32_t tiles = 0; // 64-scenario tiles
     bool ordered = false;
-    // admission
+    // admission: tables block (released after the drains running at
+    // retirement end) and outputs block (costs, tour-ordered copy: released
+    // at retirement)
     size_t off = 0, bytes = 0;
+    size_t off2 = 0, bytes2 = 0;
     int slot = -1;
     int32_t seq = 0;
     ReqState state = PENDING;
@@ -177,6 +185,7 @@ struct Drain {
     int stream;
     hipEvent_t done;
     Clock::time_point launched;
+    std::chrono::microseconds life; // how long its waves take tiles
 };
 
 } // namespace
@@ -212,7 +221,7 @@ struct split_server {
     int drain_grid[splitk::kServeQueues] = {};
     uint64_t next_drain_id = 1;
     int64_t drains_launched = 0;
-    int64_t life_us = 1000;
+    int rate_khz = 100000; // device wall clock (ticks per ms) the drain waves read
     int64_t blocked = 0;        // scheduler rounds whose next request did not fit
     size_t deferred_bytes = 0;  // retired memory waiting for running drains to end
     hipEvent_t pub_event = nullptr; // recorded after the latest publish launch
@@ -235,18 +244,29 @@ struct split_server {
     char fail_text[256] = "";
 
     // ----- helpers (scheduler thread unless noted) -----
-    size_t footprint(const Request &r) const
+    size_t footprint_tables(const Request &r) const
     {
         const int64_t S = r.inst->S;
         size_t b = 0;
         b += a256(((size_t)r.n + splitk::kTabPad) * sizeof(int2)); // tab
         b += a256((size_t)std::max(r.n, 1) * sizeof(int2));        // ab
         b += a256(sizeof(splitk::TourRec));                         // rec
-        b += a256((size_t)S * 4);                                   // costs
-        if (r.ordered)
-            b += a256((size_t)S * (size_t)r.pitch);               // tour-ordered copy
         if (r.inst->transient)
             b += a256((size_t)S * r.inst->N * 2);                 // own demands
+        return b;
+    }
+
+    size_t footprint(const Request &r) const
+    {
+        return Arena::round(footprint_tables(r)) + Arena::round(footprint_outputs(r));
+    }
+
+    size_t footprint_outputs(const Request &r) const
+    {
+        const int64_t S = r.inst->S;
+        size_t b = a256((size_t)S * 4);                             // costs
+        if (r.ordered)
+            b += a256((size_t)S * (size_t)r.pitch);               // tour-ordered copy
         return b;
     }
 
@@ -276,12 +296,18 @@ struct split_server {
         const int qi = splitk::serve_queue(r->ordered, r->variant);
         if (outstanding[qi] >= splitk::kServeQueueCap - 2)
             return false;
-        const size_t bytes = footprint(*r);
-        size_t off = 0;
+        const size_t bytes = footprint_tables(*r), bytes2 = footprint_outputs(*r);
+        size_t off = 0, off2 = 0;
         if (!arena.alloc(bytes, &off))
             return false;
+        if (!arena.alloc(bytes2, &off2)) {
+            arena.release(off, bytes);
+            return false;
+        }
         r->off = off;
         r->bytes = bytes;
+        r->off2 = off2;
+        r->bytes2 = bytes2;
         r->slot = free_slots.back();
         free_slots.pop_back();
         slot_req[r->slot] = r;
@@ -299,13 +325,10 @@ struct split_server {
         o += a256((size_t)std::max(r->n, 1) * sizeof(int2));
         splitk::TourRec *d_rec = reinterpret_cast<splitk::TourRec *>(blk + o);
         o += a256(sizeof(splitk::TourRec));
-        int32_t *d_costs = reinterpret_cast<int32_t *>(blk + o);
-        o += a256((size_t)S * 4);
-        uint8_t *d_perm = nullptr;
-        if (r->ordered) {
-            d_perm = reinterpret_cast<uint8_t *>(blk + o);
-            o += a256((size_t)S * (size_t)r->pitch);
-        }
+        char *blk2 = arena_base + off2;
+        int32_t *d_costs = reinterpret_cast<int32_t *>(blk2);
+        uint8_t *d_perm = r->ordered ? reinterpret_cast<uint8_t *>(blk2 + a256((size_t)S * 4))
+                                     : nullptr;
         const int16_t *d_dem = nullptr;
         if (in->transient) {
             int16_t *dd = reinterpret_cast<int16_t *>(blk + o);
@@ -431,7 +454,6 @@ struct split_server {
 
     void manage_drains(Clock::time_point now)
     {
-        const auto life = std::chrono::microseconds(life_us);
         for (int qi = 0; qi < splitk::kServeQueues; ++qi) {
             // retire finished drains
             while (!drains[qi].empty()) {
@@ -449,10 +471,9 @@ struct split_server {
             const bool none = drains[qi].empty();
             // the next drain is launched once the running one has stopped
             // taking tiles (its life is over), so its workgroups take the
-            // slots the old one's waves free as they finish; before that a
-            // second drain would fill the wave slots each drain leaves free
-            // for the admission launches
-            const bool aging = drains[qi].size() == 1 && now - drains[qi].back().launched > life;
+            // slots the old one's waves free as they finish
+            const bool aging =
+                drains[qi].size() == 1 && now - drains[qi].back().launched > drains[qi].back().life;
             if (!none && !aging)
                 continue;
             hipEvent_t ev = get_event();
@@ -462,8 +483,20 @@ struct split_server {
             hipStream_t st = drain_stream[qi][si];
             // the drain starts after the latest publication has landed
             hipError_t e = pub_recorded ? hipStreamWaitEvent(st, pub_event, 0) : hipSuccess;
+            // Drain life by backlog: with several tiles per drain wave queued
+            // (saturation) a drain takes tiles for 32 ms and waits 200 us for
+            // more, since each change of drain costs the device the tail of
+            // the old drain's last tiles and a drain's stream keeps later
+            // launches that share its hardware queue waiting until it ends;
+            // otherwise 1 ms and 20 us, so a light stream's launches and
+            // retired memory do not wait long.
+            const bool busy = backlog_tiles > 4 * (int64_t)drain_grid[qi];
+            const auto life = std::chrono::microseconds(busy ? 32000 : 1000);
+            splitk::ServeCtl c = ctl;
+            c.life_ticks = (long long)rate_khz * (busy ? 32 : 1);
+            c.idle_ticks = (long long)rate_khz / (busy ? 5 : 50);
             if (e == hipSuccess)
-                e = splitk::serve_launch_drain(qi, ctl, d_queue[qi], drain_grid[qi], st);
+                e = splitk::serve_launch_drain(qi, c, d_queue[qi], drain_grid[qi], st);
             if (e == hipSuccess)
                 e = hipEventRecord(ev, st);
             if (e != hipSuccess) {
@@ -471,7 +504,7 @@ struct split_server {
                 fail_all("drain launch", e);
                 continue;
             }
-            drains[qi].push_back(Drain{next_drain_id++, si, ev, now});
+            drains[qi].push_back(Drain{next_drain_id++, si, ev, now, life});
             drains_launched++;
         }
     }
@@ -495,10 +528,7 @@ struct split_server {
             else if (res->flags)
                 r->error = SPLIT_EDEVICE;
             if (r->costs_out && r->error == SPLIT_OK) {
-                const char *d_costs = arena_base + r->off +
-                                      a256(((size_t)r->n + splitk::kTabPad) * sizeof(int2)) +
-                                      a256((size_t)std::max(r->n, 1) * sizeof(int2)) +
-                                      a256(sizeof(splitk::TourRec));
+                const char *d_costs = arena_base + r->off2;
                 hipError_t e = hipMemcpyAsync(r->costs_out, d_costs, (size_t)r->inst->S * 4,
                                               hipMemcpyDeviceToHost, out_stream);
                 if (e == hipSuccess)
@@ -540,7 +570,11 @@ struct split_server {
 
     void retire(Request *r)
     {
-        // every drain launched so far may have touched the job's memory
+        // outputs: no drain reads them any more (every tile is done)
+        if (r->bytes2)
+            arena.release(r->off2, r->bytes2);
+        r->bytes2 = 0;
+        // tables: every drain launched so far may have touched them
         deferred.push_back(Deferred{next_drain_id, r->off, r->bytes, r->slot});
         deferred_bytes += Arena::round(r->bytes);
         Instance *in = r->inst;
@@ -836,11 +870,11 @@ int split_server_create(split_server **out, size_t budget_bytes, int32_t max_len
     e = hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, s->device);
     if (e != hipSuccess || rate_khz <= 0)
         rate_khz = 100000;
-    // a drain wave leaves after 20 us on an empty queue and takes no new
-    // tile after 1 ms, so retired memory comes back within a few ms
+    s->rate_khz = rate_khz;
+    // per launch the scheduler sets a drain's life and idle time by the
+    // backlog (manage_drains); these are the light-load values
     s->ctl.idle_ticks = (long long)rate_khz / 50; // 20 us
     s->ctl.life_ticks = (long long)rate_khz;      // 1 ms
-    s->life_us = 1000;
     e = hipEventCreateWithFlags(&s->pub_event, hipEventDisableTiming);
     if (e != hipSuccess)
         return bail(SPLIT_EDEVICE, "event creation", e);
