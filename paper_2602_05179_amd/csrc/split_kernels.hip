@@ -599,7 +599,8 @@ int64_t num_tiles(int64_t S) { return (S + kTile - 1) / kTile; }
 
 // order[r] = the tour of rank r by decreasing length (ties by index); an
 // invalid length ranks as 0 (its waves return at once).  One block; the
-// rank of a tour is a count over all tours, O(T^2 / threads) per launch.
+// lengths are staged in LDS and the rank of a tour is a count over all
+// tours, O(T^2 / threads) LDS reads per launch.
 constexpr int kOrderThreads = 1024;
 constexpr int32_t kOrderMaxTours = 4096;
 
@@ -607,13 +608,17 @@ __global__ __launch_bounds__(kOrderThreads) void order_kernel(const int32_t *__r
                                                               int32_t T, int32_t max_len,
                                                               int *__restrict__ order)
 {
+    __shared__ int s_len[kOrderMaxTours];
     for (int i = threadIdx.x; i < T; i += kOrderThreads) {
         const int li = lens[i];
-        const int ni = li < 0 || li > max_len ? 0 : li;
+        s_len[i] = li < 0 || li > max_len ? 0 : li;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < T; i += kOrderThreads) {
+        const int ni = s_len[i];
         int rank = 0;
         for (int j = 0; j < T; ++j) {
-            const int lj = lens[j];
-            const int nj = lj < 0 || lj > max_len ? 0 : lj;
+            const int nj = s_len[j]; // the same address across the wave: a broadcast
             rank += (nj > ni || (nj == ni && j < i)) ? 1 : 0;
         }
         order[rank] = i;
