@@ -195,6 +195,39 @@ int split_routes_list_variants(int32_t *out, int32_t cap);
 int split_routes_set_path(int32_t path);
 
 /*
+ * Full value table (Sec. 2.3 recursion; the batched DP of App. A returns
+ * the value array over every tour position and scenario, of which the
+ * evaluation entry points keep only V_s(n)).  For ONE giant tour over
+ * every scenario s:
+ *   V_s(j) = min over admissible p < j of V_s(p) + W(p,j), V_s(0) = 0,
+ *   for j = 1..n, SPLIT_INF where no split of the first j customers exists.
+ *
+ * split_values_device -- DEVICE pointers, enqueued on `stream` (nothing is
+ * allocated):
+ *   d_tour, n, d_dist, N, d_demands, S, Q   as in split_routes_device
+ *   d_V       out int32 [n*S]  POSITION-MAJOR: d_V[(j-1)*S + s] = V_s(j)
+ *   d_status  out int32 [1]    0, or 1 when a negative demand was read (the
+ *                              entries of such a scenario are SPLIT_INF)
+ *   d_workspace, ws_bytes      caller-owned device scratch of at least
+ *                              split_values_workspace_bytes(n, N, S) bytes,
+ *                              256-byte aligned
+ * d_tour and d_V may be NULL when n = 0.  Host-checkable arguments are
+ * validated before anything is enqueued (SPLIT_EINVAL).  The tour's ids,
+ * costs and the int32 guard are checked on the device: on failure every
+ * entry is SPLIT_INF.  The recursion runs exactly from its definition (one
+ * read of V_s(p) and of one demand per admissible predecessor), reading
+ * back the rows it has written: an inspection output, slower than the
+ * evaluation kernels, which never materialise the table.  The library
+ * touches the buffers only until the enqueued work completes; two calls
+ * sharing a workspace must be ordered on one stream.
+ */
+size_t split_values_workspace_bytes(int32_t n, int32_t N, int64_t S);
+int split_values_device(const int32_t *d_tour, int32_t n, const int32_t *d_dist, int32_t N,
+                        const int16_t *d_demands, int64_t S, int32_t Q, int32_t *d_V,
+                        int32_t *d_status, void *d_workspace, size_t ws_bytes,
+                        split_stream_t stream);
+
+/*
  * Split variants (App. A, the extensive form: its objective charges every
  * vehicle's overload l_k at rate beta, and its fleet-size constraint allows
  * at most K vehicles).  For ONE giant tour over every scenario s, with

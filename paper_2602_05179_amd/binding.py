@@ -56,6 +56,8 @@ EXPORTED = (
     "split_tune_load",
     "split_tune_clear",
     "split_routes_workspace_bytes",
+    "split_values_workspace_bytes",
+    "split_values_device",
     "split_routes_device",
     "split_routes_set_variant",
     "split_routes_list_variants",
@@ -163,6 +165,10 @@ def _load():
     lib.split_tune_clear.argtypes = []
     lib.split_routes_workspace_bytes.restype = sz
     lib.split_routes_workspace_bytes.argtypes = [i32, i32, i64]
+    lib.split_values_workspace_bytes.restype = sz
+    lib.split_values_workspace_bytes.argtypes = [i32, i32, i64]
+    lib.split_values_device.restype = ctypes.c_int
+    lib.split_values_device.argtypes = [P, i32, P, i32, P, i64, i32, P, P, P, sz, P]
     lib.split_routes_device.restype = ctypes.c_int
     lib.split_routes_device.argtypes = [P, i32, P, i32, P, i64, i32, P, P, P, P, P, sz, P]
     lib.split_routes_set_variant.restype = ctypes.c_int
@@ -443,6 +449,37 @@ def split_routes_device(tour, dist, demands, Q, *, out=None, workspace=None, str
                                    _dptr(workspace), int(workspace.numel()), _stream_handle(stream)))
     out.workspace = workspace
     return out
+
+
+def values_workspace_bytes(n: int, N: int, S: int) -> int:
+    return int(lib.split_values_workspace_bytes(int(n), int(N), int(S)))
+
+
+def split_values_device(tour, dist, demands, Q, *, V=None, status=None, workspace=None, stream=None):
+    """Enqueue the full value table of one giant tour: V int32 [n, S] with
+    V[j-1, s] = V_s(j) (SPLIT_INF where infeasible).  Returns (V, status)
+    with status an int32 [1] device tensor (1: a negative demand was read)."""
+    torch = _torch()
+    n = int(tour.numel())
+    N = int(dist.shape[0] - 1)
+    S = int(demands.shape[0])
+    for name, t, dt in (("tour", tour, torch.int32), ("dist", dist, torch.int32),
+                        ("demands", demands, torch.int16)):
+        if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+            raise SplitError(SPLIT_EINVAL, "%s must be a contiguous %s CUDA tensor" % (name, dt))
+    if V is None:
+        V = torch.empty((n, S), dtype=torch.int32, device=demands.device)
+    elif tuple(V.shape) != (n, S) or V.dtype != torch.int32 or not V.is_contiguous():
+        raise SplitError(SPLIT_EINVAL, "V must be a contiguous int32 tensor of shape (%d, %d)" % (n, S))
+    if status is None:
+        status = torch.empty(1, dtype=torch.int32, device=demands.device)
+    need = values_workspace_bytes(n, N, S)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=demands.device)
+    _check(lib.split_values_device(_dptr(tour), n, _dptr(dist), N, _dptr(demands), S, int(Q),
+                                   _dptr(V) if n else None, _dptr(status), _dptr(workspace),
+                                   int(workspace.numel()), _stream_handle(stream)))
+    return V, status
 
 
 # ---------------------------------------------------------------------------

@@ -15,6 +15,7 @@
 #include "split_check.h"
 #include "split_eval.h"
 #include "split_internal.h"
+#include "split_values.h"
 #include "split_minplus.h"
 #include "split_variant.h"
 
@@ -294,6 +295,36 @@ int split_routes_device(const int32_t *d_tour, int32_t n, const int32_t *d_dist,
                                   splitk::routes_position_table(d_workspace, n, N, S),
                                   static_cast<hipStream_t>(stream),
                                   splitk::choose_route_variant(Q), use_ev ? &ev : nullptr),
+            "launch");
+    return SPLIT_OK;
+}
+
+size_t split_values_workspace_bytes(int32_t n, int32_t N, int64_t S)
+{
+    if (n < 0 || n > splitk::kMaxLen || S < 1 || N < 1)
+        return 0;
+    return splitk::workspace_bytes(1, n, N, S, false);
+}
+
+int split_values_device(const int32_t *d_tour, int32_t n, const int32_t *d_dist, int32_t N,
+                        const int16_t *d_demands, int64_t S, int32_t Q, int32_t *d_V,
+                        int32_t *d_status, void *d_workspace, size_t ws_bytes,
+                        split_stream_t stream)
+{
+    splitk::clear_error();
+    int rc = check_scalars(1, N, S, Q, n);
+    if (rc)
+        return rc;
+    if (!d_dist || !d_demands || !d_status || !d_workspace || (n > 0 && (!d_tour || !d_V)))
+        return fail(SPLIT_EINVAL, "null pointer argument");
+    if (reinterpret_cast<uintptr_t>(d_workspace) % 256)
+        return fail(SPLIT_EINVAL, "workspace must be 256-byte aligned");
+    const size_t need = splitk::workspace_bytes(1, n, N, S, false);
+    if (ws_bytes < need)
+        return fail(SPLIT_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+    const splitk::Workspace ws = splitk::carve_workspace(d_workspace, 1, n, N, S, false);
+    HIP_TRY(splitk::launch_values(d_tour, n, d_dist, N, d_demands, S, Q, d_V, d_status, ws,
+                                  static_cast<hipStream_t>(stream)),
             "launch");
     return SPLIT_OK;
 }

@@ -235,6 +235,25 @@ def test_routes_device_form_rejects_bad_arguments_before_device_work():
     assert rc == binding.SPLIT_EINVAL and "aligned" in binding.last_error()
 
 
+def test_values_device_form_rejects_bad_arguments_before_device_work():
+    P = ctypes.c_void_p
+    fake = P(256)
+    f = binding.lib.split_values_device
+    for n, N, S, Q in ((5, 0, 10, 3), (5, 5, 0, 3), (5, 5, 10, -2), (70000, 5, 10, 3), (-1, 5, 10, 3)):
+        rc = f(fake, n, fake, N, fake, S, Q, fake, fake, fake, 1 << 20, None)
+        assert rc == binding.SPLIT_EINVAL, (n, N, S, Q)
+    rc = f(fake, 5, fake, 5, fake, 10, 3, fake, fake, fake, 16, None)
+    assert rc == binding.SPLIT_EINVAL and "workspace" in binding.last_error()
+    rc = f(fake, 5, fake, 5, fake, 10, 3, None, fake, fake, 1 << 20, None)
+    assert rc == binding.SPLIT_EINVAL and "null" in binding.last_error()
+    rc = f(fake, 5, fake, 5, fake, 10, 3, fake, None, fake, 1 << 20, None)
+    assert rc == binding.SPLIT_EINVAL and "null" in binding.last_error()
+    rc = f(fake, 5, fake, 5, fake, 10, 3, fake, fake, P(300), 1 << 20, None)
+    assert rc == binding.SPLIT_EINVAL and "aligned" in binding.last_error()
+    assert binding.lib.split_values_workspace_bytes(-1, 5, 10) == 0
+    assert binding.lib.split_values_workspace_bytes(5, 5, 10) >= 256
+
+
 def test_minplus_and_variant_entry_points_reject_bad_arguments_before_device_work():
     P = ctypes.c_void_p
     fake = P(256)
