@@ -94,6 +94,24 @@ def test_alone_equals_mix_equals_oracle(binding):
         assert mix[k]["latency_s"] > 0
 
 
+def test_large_pools_at_the_served_scenario_counts(binding):
+    """Requests at the top of the served stream's range (S = 10^5 scenarios,
+    pools of 300..1000 customers, all three capacities), submitted together
+    so both drains and all four queues run at once; every cost, sum and
+    mean equals the oracle's."""
+    rng = np.random.default_rng(91)
+    insts = [W.plain_normal(int(rng.integers(0, 2**31 - 1)), n, 100_000, Q)
+             for n, Q in ((1000, 300), (640, 150), (300, 80), (200, 150), (257, 300))]
+    srv = binding.Server(8 << 30, max_len=1024)
+    ids = [srv.add_instance(i.dist, i.demands) for i in insts]
+    rids = [srv.submit(iid, inst.tours, inst.Q, inst.S, want_costs=True) for inst, iid in zip(insts, ids)]
+    res = [srv.wait(r) for r in rids]
+    srv.close()
+    for inst, r in zip(insts, res):
+        _say("large " + inst.name)
+        _same(r, _ref(inst), "large " + inst.name)
+
+
 def test_requests_with_their_own_instance(binding):
     insts = _instances(41, 10, n_hi=600, S_hi=8000)
     srv = binding.Server(2 << 30, max_len=1024)
