@@ -112,6 +112,35 @@ def test_large_pools_at_the_served_scenario_counts(binding):
         _same(r, _ref(inst), "large " + inst.name)
 
 
+def test_memory_reuse_under_a_deep_backlog(binding):
+    """Sixty requests on pools above the LDS path (their tour-ordered copies
+    written by the drain waves), submitted at once under a budget that holds
+    a few of them: outputs and copies are reused while long-lived drains
+    run, and every result still equals the oracle's."""
+    rng = np.random.default_rng(93)
+    insts = [W.plain_normal(int(rng.integers(0, 2**31 - 1)), int(rng.integers(300, 600)),
+                            int(rng.integers(10_000, 30_000)), int(rng.choice([80, 150, 300])))
+             for _ in range(6)]
+    probe = binding.Server(2 << 30, max_len=1024)
+    pids = [probe.add_instance(i.dist, i.demands) for i in insts]
+    resident = probe.stats()["bytes_in_use"]
+    probe.close()
+    srv = binding.Server(resident + (160 << 20), max_len=1024)
+    ids = [srv.add_instance(i.dist, i.demands) for i in insts]
+    work = []
+    for k in range(60):
+        j = k % len(insts)
+        tour = rng.permutation(insts[j].N).astype(np.int32) + 1
+        work.append((j, tour))
+    rids = [srv.submit(ids[j], tour, insts[j].Q, insts[j].S, want_costs=True) for j, tour in work]
+    res = [srv.wait(r) for r in rids]
+    st = srv.stats()
+    srv.close()
+    assert st["blocked_rounds"] > 0, "the budget should make admission wait"
+    for (j, tour), r in zip(work, res):
+        _same(r, _ref(insts[j], tour), "reuse " + insts[j].name)
+
+
 def test_requests_with_their_own_instance(binding):
     insts = _instances(41, 10, n_hi=600, S_hi=8000)
     srv = binding.Server(2 << 30, max_len=1024)
