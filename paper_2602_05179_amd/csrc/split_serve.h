@@ -13,6 +13,8 @@ constexpr int kServeQueueCap = 1 << 14;  // ring entries per queue (power of two
 constexpr int kServeMaxJobs = 4096;      // job-table slots
 constexpr int kServeScratchSlots = 16;   // exact-fallback value histories
 constexpr int kServeFusedMaxN = 256;     // pools staged whole in LDS by the fused drain
+constexpr int kServeStageMaxN = 1024;    // pools the ordered drain stages in LDS by row batches
+constexpr int kServeStageRows = 8;       // rows per batch (a multiple of 8: batches start 16-byte aligned)
 
 // Window variants a served job can take (chosen by capacity on the host).
 enum ServeVariant : int32_t { SV_R32_6 = 0, SV_R32_8 = 1, SV_R64_16 = 2 };

@@ -217,61 +217,93 @@ __device__ int exact_tile(const ServeCtl &ctl, const JobView &jv, int64_t s0, in
 }
 
 // The tile's rows in tour order into the job's copy: byte j - 1 of row s is
-// the demand of position j (zero from n to the pitch).  Consecutive lanes
-// take consecutive 16-position chunks of one row, so a load instruction
-// touches a few lines of that row; two chunks per lane are in flight at
-// once.  cust: the tour's customer indices (LDS).  Returns false
+// the demand of position j (zero from n to the pitch).  Returns false
 // (uniformly) when a demand lies outside [0, 255].
+//
+// Pools of at most kServeStageMaxN customers: eight rows at a time are
+// staged in LDS as bytes with 16-byte coalesced loads (all of a lane's
+// chunks in flight together) and rewritten in tour order from there, so
+// the gather runs on LDS.  Larger pools: consecutive lanes take consecutive
+// 16-position chunks of one row straight from global memory (a load
+// instruction touches a few lines of that row), two chunks per lane in
+// flight.  cust: the tour's customer indices (LDS).
 constexpr int kGatherChunks = 2;
 
+__device__ __forceinline__ u32x4 pack16(const int (&v)[16], uint32_t &bad)
+{
+    uint32_t w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        uint32_t x = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int val = v[q * 4 + b];
+            bad |= (uint32_t)val & 0xFFFFFF00u; // outside [0, 255]
+            x |= ((uint32_t)val & 0xFFu) << (8 * b);
+        }
+        w[q] = x;
+    }
+    return u32x4{w[0], w[1], w[2], w[3]};
+}
+
 __device__ bool gather_tile(const JobView &jv, int64_t s0, int rows, const uint16_t *cust,
-                            int lane)
+                            uint8_t *rowbuf, int &s_bad, int lane)
 {
     const int chunks = jv.pitch / 16;
-    const int total = rows * chunks;
     uint8_t *dst = const_cast<uint8_t *>(jv.perm) + s0 * jv.pitch;
     uint32_t bad = 0;
-    for (int base = 0; base < total; base += kGatherChunks * kWave) {
-        int v[kGatherChunks][16];
+    bool ok = true;
+    if (jv.N <= kServeStageMaxN) {
+        for (int rb0 = 0; rb0 < rows; rb0 += kServeStageRows) {
+            const int rb = min(kServeStageRows, rows - rb0);
+            // rows s0+rb0 .. start 16-byte aligned: s0 + rb0 is a multiple of 8
+            ok = stage_tile_u8(jv.demands + (s0 + rb0) * jv.N, rowbuf, (int64_t)rb * jv.N, lane,
+                               kWave, s_bad) && ok;
+            for (int idx = lane; idx < rb * chunks; idx += kWave) {
+                const int r = idx / chunks;
+                const int c = idx - r * chunks;
+                const uint8_t *row = rowbuf + r * jv.N;
+                int w[16];
 #pragma unroll
-        for (int u = 0; u < kGatherChunks; ++u) {
-            const int idx = base + u * kWave + lane;
-            const int r = idx / chunks;
-            const int c = idx - r * chunks;
-            const int16_t *row = jv.demands + (s0 + r) * jv.N;
-#pragma unroll
-            for (int b = 0; b < 16; ++b) {
-                const int j = c * 16 + b;
-                v[u][b] = idx < total && j < jv.n ? row[cust[j]] : 0;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kGatherChunks; ++u) {
-            const int idx = base + u * kWave + lane;
-            if (idx >= total)
-                continue;
-            const int r = idx / chunks;
-            const int c = idx - r * chunks;
-            uint32_t w[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                uint32_t x = 0;
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const int val = v[u][q * 4 + b];
-                    bad |= (uint32_t)val & 0xFFFFFF00u; // outside [0, 255]
-                    x |= ((uint32_t)val & 0xFFu) << (8 * b);
+                for (int b = 0; b < 16; ++b) {
+                    const int j = c * 16 + b;
+                    w[b] = j < jv.n ? row[cust[j]] : 0;
                 }
-                w[q] = x;
+                reinterpret_cast<u32x4 *>(dst + (int64_t)(rb0 + r) * jv.pitch)[c] = pack16(w, bad);
             }
-            const u32x4 o = {w[0], w[1], w[2], w[3]};
-            reinterpret_cast<u32x4 *>(dst + (int64_t)r * jv.pitch)[c] = o;
+            __syncthreads(); // the next batch overwrites the staged rows
+        }
+    } else {
+        const int total = rows * chunks;
+        for (int base = 0; base < total; base += kGatherChunks * kWave) {
+            int v[kGatherChunks][16];
+#pragma unroll
+            for (int u = 0; u < kGatherChunks; ++u) {
+                const int idx = base + u * kWave + lane;
+                const int r = idx / chunks;
+                const int c = idx - r * chunks;
+                const int16_t *row = jv.demands + (s0 + r) * jv.N;
+#pragma unroll
+                for (int b = 0; b < 16; ++b) {
+                    const int j = c * 16 + b;
+                    v[u][b] = idx < total && j < jv.n ? row[cust[j]] : 0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kGatherChunks; ++u) {
+                const int idx = base + u * kWave + lane;
+                if (idx >= total)
+                    continue;
+                const int r = idx / chunks;
+                const int c = idx - r * chunks;
+                reinterpret_cast<u32x4 *>(dst + (int64_t)r * jv.pitch)[c] = pack16(v[u], bad);
+            }
         }
     }
     // the stores complete before the recursion of this wave reads them back
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_s_waitcnt(0);
-    return ballot(bad != 0) == 0;
+    return ok && ballot(bad != 0) == 0;
 }
 
 template <bool ORDERED, bool WIDE>
@@ -322,7 +354,11 @@ __device__ void run_tile(const ServeCtl &ctl, const JobView &jv, int tile, uint8
     if (jv.n > 0) {
         bool ok;
         if (ORDERED) {
-            ok = gather_tile(jv, s0, rows, reinterpret_cast<const uint16_t *>(lds), lane);
+            const size_t cust_bytes = ((size_t)2 * ctl.max_len + 15) & ~(size_t)15;
+            uint8_t *rowbuf = lds + cust_bytes;
+            int &s_bad = *reinterpret_cast<int *>(rowbuf + kServeStageRows * kServeStageMaxN);
+            ok = gather_tile(jv, s0, rows, reinterpret_cast<const uint16_t *>(lds), rowbuf, s_bad,
+                             lane);
         } else {
             int &s_bad = *reinterpret_cast<int *>(lds + (((size_t)kWave * kServeFusedMaxN + 15) &
                                                           ~(size_t)15));
@@ -500,10 +536,12 @@ __global__ __launch_bounds__(kWave) void serve_publish_kernel(ServeQueues queues
 }
 
 // LDS of a drain wave: the fused drain's tile (kServeFusedMaxN bytes per
-// row) and staging flag; the ordered drain's tour (u16 per position)
+// row) and staging flag; the ordered drain's tour (u16 per position), its
+// staged rows (kServeStageRows x kServeStageMaxN bytes) and staging flag
 static size_t drain_lds(bool ordered, int32_t max_len)
 {
-    return ordered ? (2 * (size_t)max_len + 15) & ~(size_t)15
+    return ordered ? ((2 * (size_t)max_len + 15) & ~(size_t)15) +
+                         (size_t)kServeStageRows * kServeStageMaxN + 16
                    : (((size_t)kWave * kServeFusedMaxN + 15) & ~(size_t)15) + 16;
 }
 
@@ -532,12 +570,10 @@ int serve_drain_grid(int queue, int32_t max_len)
                                                      drain_lds(ordered, max_len)) != hipSuccess ||
         per < 1)
         per = 1;
-    // leave one wave slot per SIMD (and the LDS and registers it needs) to
-    // the admission launches, so a round is not held up until drain waves
-    // retire
-    if (per >= 8)
-        per -= 4;
-    else if (per >= 2)
+    // leave one workgroup slot per CU (and the LDS and registers it needs)
+    // to the admission launches, so a round is not held up until drain
+    // waves retire; one drain may otherwise fill the device
+    if (per >= 2)
         per -= 1;
     return cus * per;
 }
