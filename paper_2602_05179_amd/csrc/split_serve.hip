@@ -264,10 +264,21 @@ __device__ bool gather_tile(const JobView &jv, int64_t s0, int rows, const uint1
                 const int c = idx - r * chunks;
                 const uint8_t *row = rowbuf + r * jv.N;
                 int w[16];
+                if (c * 16 < jv.n) {
+                    // the chunk's 16 customer indices in two 16-byte LDS reads
+                    // (the tour array is zero-padded to a multiple of 16)
+                    const u32x4 *cp = reinterpret_cast<const u32x4 *>(cust) + 2 * c;
+                    const u32x4 c0 = cp[0], c1 = cp[1];
+                    const uint32_t cw[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
 #pragma unroll
-                for (int b = 0; b < 16; ++b) {
-                    const int j = c * 16 + b;
-                    w[b] = j < jv.n ? row[cust[j]] : 0;
+                    for (int b = 0; b < 16; ++b) {
+                        const int cu = (int)((cw[b >> 1] >> (16 * (b & 1))) & 0xFFFFu);
+                        w[b] = c * 16 + b < jv.n ? row[cu] : 0;
+                    }
+                } else {
+#pragma unroll
+                    for (int b = 0; b < 16; ++b)
+                        w[b] = 0; // past the tour: the row's zero padding
                 }
                 reinterpret_cast<u32x4 *>(dst + (int64_t)(rb0 + r) * jv.pitch)[c] = pack16(w, bad);
             }
@@ -354,7 +365,7 @@ __device__ void run_tile(const ServeCtl &ctl, const JobView &jv, int tile, uint8
     if (jv.n > 0) {
         bool ok;
         if (ORDERED) {
-            const size_t cust_bytes = ((size_t)2 * ctl.max_len + 15) & ~(size_t)15;
+            const size_t cust_bytes = 2 * (((size_t)ctl.max_len + 15) & ~(size_t)15);
             uint8_t *rowbuf = lds + cust_bytes;
             int &s_bad = *reinterpret_cast<int *>(rowbuf + kServeStageRows * kServeStageMaxN);
             ok = gather_tile(jv, s0, rows, reinterpret_cast<const uint16_t *>(lds), rowbuf, s_bad,
@@ -453,8 +464,10 @@ __device__ __forceinline__ void drain(ServeCtl ctl, ServeQueue *q)
             jv = read_job(ctl.jobs + slot);
             if (ORDERED) { // and its tour's customer order for the gather
                 uint16_t *cust = reinterpret_cast<uint16_t *>(lds);
-                for (int j = lane; j < jv.n; j += kWave)
-                    cust[j] = (uint16_t)jv.tab[j + 1].x;
+                const int padded = (jv.n + 15) & ~15; // within the array: its length is
+                                                      // max_len rounded up to 16
+                for (int j = lane; j < padded; j += kWave)
+                    cust[j] = j < jv.n ? (uint16_t)jv.tab[j + 1].x : (uint16_t)0;
                 __syncthreads();
             }
         }
@@ -536,11 +549,12 @@ __global__ __launch_bounds__(kWave) void serve_publish_kernel(ServeQueues queues
 }
 
 // LDS of a drain wave: the fused drain's tile (kServeFusedMaxN bytes per
-// row) and staging flag; the ordered drain's tour (u16 per position), its
-// staged rows (kServeStageRows x kServeStageMaxN bytes) and staging flag
+// row) and staging flag; the ordered drain's tour (u16 per position, the
+// length rounded up to 16), its staged rows (kServeStageRows x
+// kServeStageMaxN bytes) and staging flag
 static size_t drain_lds(bool ordered, int32_t max_len)
 {
-    return ordered ? ((2 * (size_t)max_len + 15) & ~(size_t)15) +
+    return ordered ? 2 * (((size_t)max_len + 15) & ~(size_t)15) +
                          (size_t)kServeStageRows * kServeStageMaxN + 16
                    : (((size_t)kWave * kServeFusedMaxN + 15) & ~(size_t)15) + 16;
 }
