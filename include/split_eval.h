@@ -118,6 +118,31 @@ int split_eval_device(const int32_t *d_tours, const int32_t *d_lens, int32_t num
                       split_stream_t stream);
 
 /*
+ * split_eval_path -- which kernels split_eval / split_eval_device run for a
+ * call of this shape under the schedule in force (measurement and tests;
+ * results never depend on it):
+ *   SPLIT_PATH_ONE_LAUNCH  tables, recursion, exact fallback and the fold
+ *                          in a single launch of one 8-wave workgroup, for
+ *                          ONE tour with at most 256 recursion steps per
+ *                          wave (ceil(ceil(S/64)/8) x max_len <= 256) and
+ *                          N <= 256 (larger pools take the tour-ordered
+ *                          path); automatic path choice only (a
+ *                          path forced by split_set_schedule, a tuned entry
+ *                          or split_profile_enable takes the general kernels)
+ *   SPLIT_PATH_TILES       per-tour tables, one workgroup per 64-scenario
+ *                          tile staged in LDS, exact fallback and fold
+ *   SPLIT_PATH_ORDERED     as TILES, after the demands are rewritten in tour
+ *                          order into the workspace
+ * Returns the path (>= 0), or SPLIT_EINVAL for sizes split_eval_device
+ * would reject.
+ */
+#define SPLIT_PATH_ONE_LAUNCH 0
+#define SPLIT_PATH_TILES 1
+#define SPLIT_PATH_ORDERED 2
+
+int split_eval_path(int32_t num_tours, int32_t max_len, int32_t N, int64_t S, int32_t Q);
+
+/*
  * Route recovery (App. A: the giant tour is cut into routes by the split
  * operator; App. B: a batched DP that records each minimiser and is then
  * backtracked recovers the decisions).  For ONE giant tour over every

@@ -31,6 +31,7 @@ EXPORTED = (
     "split_eval",
     "split_workspace_bytes",
     "split_eval_device",
+    "split_eval_path",
     "split_count_cells_device",
     "split_plan_create",
     "split_plan_launch",
@@ -126,6 +127,8 @@ def _load():
     lib.split_set_schedule.argtypes = [i32, i32, i32, i32, i32, i32]
     lib.split_probe_valu_peak.restype = ctypes.c_int
     lib.split_probe_valu_peak.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]
+    lib.split_eval_path.restype = ctypes.c_int
+    lib.split_eval_path.argtypes = [i32, i32, i32, ctypes.c_int64, i32]
     lib.split_list_variants.restype = ctypes.c_int
     lib.split_list_variants.argtypes = [ctypes.POINTER(i32), i32]
     lib.split_profile_enable.restype = ctypes.c_int
@@ -225,6 +228,16 @@ SCHEDULES = list_variants()
 
 
 PATH_AUTO, PATH_FUSED, PATH_ORDERED = 0, 1, 2
+
+PATH_ONE_LAUNCH, PATH_TILES = 0, 1
+
+
+def eval_path(num_tours: int, max_len: int, N: int, S: int, Q: int) -> int:
+    """Kernels an evaluation of this shape runs under the schedule in force:
+    PATH_ONE_LAUNCH, PATH_TILES or PATH_ORDERED (the same value as PATH_ORDERED)."""
+    rc = lib.split_eval_path(int(num_tours), int(max_len), int(N), int(S), int(Q))
+    _check(rc if rc < 0 else 0)
+    return rc
 
 
 def set_schedule(ring: int, first: int = 8, group: int = 0, every: int = 4, waves: int = 0,

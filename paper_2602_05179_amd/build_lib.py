@@ -16,14 +16,14 @@ SOURCES = [os.path.join(CSRC, "split_kernels.hip"), os.path.join(CSRC, "split_ap
            os.path.join(CSRC, "split_variant.hip"), os.path.join(CSRC, "split_minplus.hip"),
            os.path.join(CSRC, "split_search.cpp"), os.path.join(CSRC, "split_check.cpp"),
            os.path.join(CSRC, "split_serve.hip"), os.path.join(CSRC, "split_noalloc.hip"),
-           os.path.join(CSRC, "split_ou.hip"), os.path.join(CSRC, "split_values.hip")]
+           os.path.join(CSRC, "split_ou.hip"), os.path.join(CSRC, "split_values.hip"), os.path.join(CSRC, "split_small.hip")]
 HEADERS = [os.path.join(INCLUDE, "split_eval.h"), os.path.join(CSRC, "split_internal.h"),
            os.path.join(CSRC, "split_device.h"), os.path.join(CSRC, "window_min_asm.inc"),
            os.path.join(CSRC, "window_argmin_asm.inc"), os.path.join(CSRC, "split_variant.h"),
            os.path.join(CSRC, "split_minplus.h"),
            os.path.join(CSRC, "window_min_multi_asm.inc"), os.path.join(CSRC, "split_check.h"),
            os.path.join(CSRC, "split_serve.h"), os.path.join(CSRC, "split_dp.h"),
-           os.path.join(CSRC, "split_values.h")]
+           os.path.join(CSRC, "split_values.h"), os.path.join(CSRC, "split_small.h")]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are disabled for every GPU object this library

@@ -17,6 +17,7 @@
 #include "split_internal.h"
 #include "split_values.h"
 #include "split_minplus.h"
+#include "split_small.h"
 #include "split_variant.h"
 
 namespace {
@@ -96,6 +97,12 @@ hipError_t profile_events(splitk::LaunchEvents *out, bool *use)
     return hipSuccess;
 }
 
+bool profiling()
+{
+    std::lock_guard<std::mutex> lock(g_prof.mu);
+    return g_prof.on;
+}
+
 hipError_t ensure(HostCtx::Buf &b, size_t bytes)
 {
     if (bytes == 0)
@@ -134,6 +141,22 @@ Schedule choose_schedule(int32_t T, int32_t max_len, int32_t N, int64_t S, int32
         ord = false;
     *ordered = ord;
     return s;
+}
+
+// One evaluation: the one-launch form for one short tour when it fits and
+// profiling is off (its events bracket the general tile kernel), else the
+// general launches.
+static hipError_t run_eval(const int32_t *tours, const int32_t *lens, int32_t T, int32_t max_len,
+                           const int32_t *dist, int32_t N, const int16_t *demands, int64_t S,
+                           int32_t Q, int32_t *costs, int64_t *sums, double *means,
+                           const Workspace &ws, hipStream_t stream, const Schedule &sched,
+                           bool ordered, const LaunchEvents *ev)
+{
+    if (!profiling() && small_path_fits(T, max_len, N, S, sched, ordered))
+        return launch_small(tours, lens, max_len, dist, N, demands, S, Q, costs, sums, means, ws,
+                            stream, sched);
+    return launch_eval(tours, lens, T, max_len, dist, N, demands, S, Q, costs, sums, means, ws,
+                       stream, sched, ev);
 }
 
 } // namespace splitk
@@ -185,6 +208,19 @@ size_t split_workspace_bytes(int32_t num_tours, int32_t max_len, int32_t N, int6
     return splitk::workspace_bytes(num_tours, max_len, N, S, ordered);
 }
 
+int split_eval_path(int32_t num_tours, int32_t max_len, int32_t N, int64_t S, int32_t Q)
+{
+    splitk::clear_error();
+    const int rc = check_scalars(num_tours, N, S, Q, max_len);
+    if (rc)
+        return rc;
+    bool ordered = false;
+    const splitk::Schedule sched = splitk::choose_schedule(num_tours, max_len, N, S, Q, &ordered);
+    if (!profiling() && splitk::small_path_fits(num_tours, max_len, N, S, sched, ordered))
+        return SPLIT_PATH_ONE_LAUNCH;
+    return ordered ? SPLIT_PATH_ORDERED : SPLIT_PATH_TILES;
+}
+
 int split_eval_device(const int32_t *d_tours, const int32_t *d_lens, int32_t num_tours,
                       int32_t max_len, const int32_t *d_dist, int32_t N,
                       const int16_t *d_demands, int64_t S, int32_t Q, int32_t *d_costs,
@@ -212,9 +248,9 @@ int split_eval_device(const int32_t *d_tours, const int32_t *d_lens, int32_t num
     splitk::LaunchEvents ev;
     bool use_ev = false;
     HIP_TRY(profile_events(&ev, &use_ev), "profile events");
-    HIP_TRY(splitk::launch_eval(d_tours, d_lens, num_tours, max_len, d_dist, N, d_demands, S, Q,
-                                d_costs, d_sums, d_means, ws, static_cast<hipStream_t>(stream),
-                                sched, use_ev ? &ev : nullptr),
+    HIP_TRY(splitk::run_eval(d_tours, d_lens, num_tours, max_len, d_dist, N, d_demands, S, Q,
+                             d_costs, d_sums, d_means, ws, static_cast<hipStream_t>(stream),
+                             sched, ordered, use_ev ? &ev : nullptr),
             "launch");
     return SPLIT_OK;
 }
@@ -522,13 +558,14 @@ int split_eval(const int32_t *tours, const int32_t *lens, int32_t num_tours, con
             "copy demands");
     const splitk::Workspace ws =
         splitk::carve_workspace(g_ctx.ws.p, num_tours, max_len, N, S, ordered);
-    HIP_TRY(splitk::launch_eval(static_cast<int32_t *>(g_ctx.tours.p),
-                                static_cast<int32_t *>(g_ctx.lens.p), num_tours, max_len,
-                                static_cast<int32_t *>(g_ctx.dist.p), N,
-                                static_cast<int16_t *>(g_ctx.demands.p), S, Q,
-                                static_cast<int32_t *>(g_ctx.costs.p),
-                                static_cast<int64_t *>(g_ctx.sums.p),
-                                static_cast<double *>(g_ctx.means.p), ws, st, sched),
+    HIP_TRY(splitk::run_eval(static_cast<int32_t *>(g_ctx.tours.p),
+                             static_cast<int32_t *>(g_ctx.lens.p), num_tours, max_len,
+                             static_cast<int32_t *>(g_ctx.dist.p), N,
+                             static_cast<int16_t *>(g_ctx.demands.p), S, Q,
+                             static_cast<int32_t *>(g_ctx.costs.p),
+                             static_cast<int64_t *>(g_ctx.sums.p),
+                             static_cast<double *>(g_ctx.means.p), ws, st, sched, ordered,
+                             nullptr),
             "launch");
     std::vector<int64_t> hs(num_tours);
     std::vector<double> hm(num_tours);

@@ -280,3 +280,33 @@ def test_minplus_and_variant_entry_points_reject_bad_arguments_before_device_wor
     assert f(fake, 5, fake, 5, fake, 10, 3, 2, 0, fake, None, fake, 1 << 20, None) == binding.SPLIT_EINVAL
     assert f(fake, 5, fake, 5, fake, 10, 3, 2, 0, fake, fake, fake, 16, None) == binding.SPLIT_EINVAL
     assert binding.variant_workspace_bytes(200, 200, 10 ** 6, 4) > binding.variant_workspace_bytes(200, 200, 10 ** 6, 0)
+
+
+def test_path_choice_of_the_one_launch_form():
+    """split_eval_path (host logic only): one tour, at most 256 recursion
+    steps per wave of the 8-wave workgroup, pools of at most 256 customers,
+    automatic path choice; anything else takes the general kernels."""
+    P = binding.eval_path
+    assert P(1, 20, 20, 1000, 30) == binding.PATH_ONE_LAUNCH       # n=20, S=1000
+    assert P(1, 128, 200, 1024, 100) == binding.PATH_ONE_LAUNCH    # 2 tiles per wave x 128
+    assert P(1, 128, 200, 1025, 100) == binding.PATH_TILES         # 3 tiles per wave
+    assert P(1, 256, 256, 512, 100) == binding.PATH_ONE_LAUNCH
+    assert P(1, 257, 256, 512, 100) == binding.PATH_TILES
+    assert P(1, 20, 256, 1000, 30) == binding.PATH_ONE_LAUNCH
+    assert P(1, 20, 257, 1000, 30) == binding.PATH_ORDERED        # large pools: tour-ordered copy
+    assert P(2, 20, 100, 1000, 30) == binding.PATH_TILES
+    assert P(1, 0, 100, 1000, 30) == binding.PATH_TILES
+    assert P(1, 100, 200, 100_000, 100) == binding.PATH_TILES
+    for bad in ((0, 20, 100, 1000, 30), (1, 20, 100, 0, 30), (1, 20, 0, 1000, 30)):
+        with pytest.raises(binding.SplitError):
+            P(*bad)
+    try:
+        binding.set_schedule(32, 8, 3, 3, waves=0, path=1)
+        assert P(1, 20, 20, 1000, 30) == binding.PATH_TILES
+        binding.set_schedule(32, 8, 3, 3, waves=0, path=0)
+        assert P(1, 20, 20, 1000, 30) == binding.PATH_ONE_LAUNCH
+        binding.profile_enable(True)
+        assert P(1, 20, 20, 1000, 30) == binding.PATH_TILES
+    finally:
+        binding.profile_enable(False)
+        binding.set_schedule(0)
