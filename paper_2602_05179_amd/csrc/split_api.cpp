@@ -58,8 +58,16 @@ struct HostCtx {
         size_t cap = 0;
     };
     Buf tours, lens, dist, demands, costs, sums, means, ws;
+    Buf in, out;        // packed inputs / outputs of a small call (one copy each way)
+    Buf pin;            // pinned host staging of a small call (hipHostMalloc)
     ~HostCtx() = default; // buffers live until process exit
 };
+
+// Calls whose inputs plus outputs fit in this many bytes are staged through
+// one pinned host buffer: one host-to-device copy of every input, one
+// device-to-host copy of every output, instead of one pageable copy per
+// array (each a separate staged transfer).
+constexpr size_t kPackedMax = 8u << 20;
 
 HostCtx g_ctx;
 
@@ -121,6 +129,25 @@ hipError_t ensure(HostCtx::Buf &b, size_t bytes)
         b.cap = bytes;
     return e;
 }
+
+hipError_t ensure_pinned(HostCtx::Buf &b, size_t bytes)
+{
+    if (b.cap >= bytes)
+        return hipSuccess;
+    if (b.p) {
+        hipError_t e = hipHostFree(b.p);
+        if (e != hipSuccess)
+            return e;
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    hipError_t e = hipHostMalloc(&b.p, bytes, hipHostMallocDefault);
+    if (e == hipSuccess)
+        b.cap = bytes;
+    return e;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 } // namespace
 
@@ -539,6 +566,59 @@ int split_eval(const int32_t *tours, const int32_t *lens, int32_t num_tours, con
     bool ordered = false;
     const splitk::Schedule sched = splitk::choose_schedule(num_tours, max_len, N, S, Q, &ordered);
     const size_t ws_bytes = splitk::workspace_bytes(num_tours, max_len, N, S, ordered);
+    HIP_TRY(ensure(g_ctx.ws, ws_bytes), "alloc workspace");
+    const splitk::Workspace ws =
+        splitk::carve_workspace(g_ctx.ws.p, num_tours, max_len, N, S, ordered);
+
+    // small calls: inputs packed at 256-byte offsets {tours, lens, dist,
+    // demands}, outputs {sums, means, costs}, each side one copy
+    const size_t b_tours = (size_t)total * 4, b_lens = (size_t)num_tours * 4,
+                 b_dist = n1sq * 4, b_dem = (size_t)S * N * 2, b_costs = (size_t)num_tours * S * 4,
+                 b_sm = (size_t)num_tours * 8;
+    const size_t i_lens = align256(b_tours), i_dist = i_lens + align256(b_lens),
+                 i_dem = i_dist + align256(b_dist), in_bytes = i_dem + b_dem;
+    const size_t o_means = align256(b_sm), o_costs = o_means + align256(b_sm),
+                 out_bytes = o_costs + b_costs;
+    if (in_bytes + out_bytes <= kPackedMax) {
+        HIP_TRY(ensure(g_ctx.in, in_bytes), "alloc inputs");
+        HIP_TRY(ensure(g_ctx.out, out_bytes), "alloc outputs");
+        HIP_TRY(ensure_pinned(g_ctx.pin, in_bytes > out_bytes ? in_bytes : out_bytes),
+                "alloc pinned staging");
+        char *h = static_cast<char *>(g_ctx.pin.p);
+        char *din = static_cast<char *>(g_ctx.in.p);
+        char *dout = static_cast<char *>(g_ctx.out.p);
+        if (b_tours)
+            memcpy(h, tours, b_tours);
+        memcpy(h + i_lens, lens, b_lens);
+        memcpy(h + i_dist, dist, b_dist);
+        memcpy(h + i_dem, demands, b_dem);
+        HIP_TRY(hipMemcpyAsync(din, h, in_bytes, hipMemcpyHostToDevice, st), "copy inputs");
+        HIP_TRY(splitk::run_eval(reinterpret_cast<int32_t *>(din),
+                                 reinterpret_cast<int32_t *>(din + i_lens), num_tours, max_len,
+                                 reinterpret_cast<int32_t *>(din + i_dist), N,
+                                 reinterpret_cast<int16_t *>(din + i_dem), S, Q,
+                                 reinterpret_cast<int32_t *>(dout + o_costs),
+                                 reinterpret_cast<int64_t *>(dout),
+                                 reinterpret_cast<double *>(dout + o_means), ws, st, sched, ordered,
+                                 nullptr),
+                "launch");
+        // the staging buffer is reused for the outputs: the copy above has
+        // completed by the time this one (same stream) starts
+        HIP_TRY(hipMemcpyAsync(h, dout, out_bytes, hipMemcpyDeviceToHost, st), "copy outputs");
+        HIP_TRY(hipStreamSynchronize(st), "synchronize");
+        const int64_t *hs = reinterpret_cast<const int64_t *>(h);
+        for (int32_t t = 0; t < num_tours; ++t)
+            if (hs[t] == SPLIT_SUM_INVALID)
+                return fail(SPLIT_EINVAL, "tour %d: invalid input found on the device "
+                                          "(negative demand)", t);
+        memcpy(costs, h + o_costs, b_costs);
+        if (sums)
+            memcpy(sums, h, b_sm);
+        if (means)
+            memcpy(means, h + o_means, b_sm);
+        return SPLIT_OK;
+    }
+
     HIP_TRY(ensure(g_ctx.tours, (size_t)total * 4), "alloc tours");
     HIP_TRY(ensure(g_ctx.lens, (size_t)num_tours * 4), "alloc lens");
     HIP_TRY(ensure(g_ctx.dist, n1sq * 4), "alloc dist");
@@ -546,7 +626,6 @@ int split_eval(const int32_t *tours, const int32_t *lens, int32_t num_tours, con
     HIP_TRY(ensure(g_ctx.costs, (size_t)num_tours * S * 4), "alloc costs");
     HIP_TRY(ensure(g_ctx.sums, (size_t)num_tours * 8), "alloc sums");
     HIP_TRY(ensure(g_ctx.means, (size_t)num_tours * 8), "alloc means");
-    HIP_TRY(ensure(g_ctx.ws, ws_bytes), "alloc workspace");
 
     if (total)
         HIP_TRY(hipMemcpyAsync(g_ctx.tours.p, tours, (size_t)total * 4, hipMemcpyHostToDevice, st),
@@ -556,8 +635,6 @@ int split_eval(const int32_t *tours, const int32_t *lens, int32_t num_tours, con
     HIP_TRY(hipMemcpyAsync(g_ctx.dist.p, dist, n1sq * 4, hipMemcpyHostToDevice, st), "copy dist");
     HIP_TRY(hipMemcpyAsync(g_ctx.demands.p, demands, (size_t)S * N * 2, hipMemcpyHostToDevice, st),
             "copy demands");
-    const splitk::Workspace ws =
-        splitk::carve_workspace(g_ctx.ws.p, num_tours, max_len, N, S, ordered);
     HIP_TRY(splitk::run_eval(static_cast<int32_t *>(g_ctx.tours.p),
                              static_cast<int32_t *>(g_ctx.lens.p), num_tours, max_len,
                              static_cast<int32_t *>(g_ctx.dist.p), N,
