@@ -127,8 +127,10 @@ int split_eval_device(const int32_t *d_tours, const int32_t *d_lens, int32_t num
  *                          wave (ceil(ceil(S/64)/8) x max_len <= 256) and
  *                          N <= 256 (larger pools take the tour-ordered
  *                          path); automatic path choice only (a
- *                          path forced by split_set_schedule, a tuned entry
- *                          or split_profile_enable takes the general kernels)
+ *                          path forced by split_set_schedule or a tuned
+ *                          entry, or split_profile_enable, takes the general
+ *                          kernels; the tuner records the one-launch form
+ *                          as path 0 when it is the fastest)
  *   SPLIT_PATH_TILES       per-tour tables, one workgroup per 64-scenario
  *                          tile staged in LDS, exact fallback and fold
  *   SPLIT_PATH_ORDERED     as TILES, after the demands are rewritten in tour
@@ -486,7 +488,8 @@ int split_list_variants(int32_t *out, int32_t cap);
 
 /*
  * Autotuning.  split_tune_device times every compiled schedule (ring length,
- * head/tail structure, tours per workgroup, fused or ordered path) on the
+ * head/tail structure, tours per workgroup, fused or ordered path, and the
+ * one-launch form where the shape allows it, recorded as path 0) on the
  * given device inputs, `reps` timed launches each after two warm-ups, on
  * `stream` (synchronising it), and records the fastest for the call's shape
  * bucket (tour count, length, pool size, scenario count and capacity, each

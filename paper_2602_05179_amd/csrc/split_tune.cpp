@@ -2,7 +2,8 @@
 //
 // A schedule fixes how the main kernel runs: register-ring length, head and
 // tail structure of the window minimum, tours per workgroup sharing a staged
-// tile, and fused vs ordered path.  Every candidate gives the same results
+// tile, and fused vs ordered path, and for one short tour the one-launch
+// form (recorded as path 0, the automatic choice that takes it).  Every candidate gives the same results
 // by construction (anything the fast path cannot take goes to the exact
 // fallback); the tuner still parity-gates each one against the reference
 // schedule on the device (bit-exact costs and sums) before timing counts.
@@ -19,6 +20,7 @@
 
 #include "split_eval.h"
 #include "split_internal.h"
+#include "split_small.h"
 
 namespace splitk {
 
@@ -118,6 +120,14 @@ int split_tune_device(const int32_t *d_tours, const int32_t *d_lens, int32_t num
             }
         }
     }
+    // the one-launch form (path 0) for every variant, where the shape allows it
+    for (int i = 0; i < nt; ++i) {
+        Schedule s = triples[i];
+        s.waves = 0;
+        s.path = 0;
+        if (small_path_fits(num_tours, max_len, N, S, s, false))
+            cand.push_back(s);
+    }
     // reference: the automatic schedule, placed first
     Schedule ref = default_schedule(N, S, Q);
     ref.path = use_ordered_path(num_tours, N, max_len) ? 2 : 1;
@@ -152,15 +162,20 @@ int split_tune_device(const int32_t *d_tours, const int32_t *d_lens, int32_t num
             int32_t *out = static_cast<int32_t *>(c == 0 ? costs_ref : costs);
             int64_t *so = c == 0 ? sums_ref : sums;
             double *mo = c == 0 ? means_ref : means;
+            auto launch = [&]() {
+                if (s.path == 0)
+                    return launch_small(d_tours, d_lens, max_len, d_dist, N, d_demands, S, Q, out,
+                                        so, mo, w, st, s);
+                return launch_eval(d_tours, d_lens, num_tours, max_len, d_dist, N, d_demands, S,
+                                   Q, out, so, mo, w, st, s);
+            };
             hipError_t e = hipSuccess;
             for (int r = 0; r < 2 && e == hipSuccess; ++r) // warm-up
-                e = launch_eval(d_tours, d_lens, num_tours, max_len, d_dist, N, d_demands, S, Q,
-                                out, so, mo, w, st, s);
+                e = launch();
             if (e == hipSuccess)
                 e = hipEventRecord(e0, st);
             for (int r = 0; r < reps && e == hipSuccess; ++r)
-                e = launch_eval(d_tours, d_lens, num_tours, max_len, d_dist, N, d_demands, S, Q,
-                                out, so, mo, w, st, s);
+                e = launch();
             if (e == hipSuccess)
                 e = hipEventRecord(e1, st);
             if (e == hipSuccess && c > 0)
@@ -268,7 +283,7 @@ int split_tune_load(const char *path)
         splitk::Schedule s;
         if (sscanf(line, "%d %d %d %d %d %d %d %d %d %d %d", &k.tours, &k.len, &k.pool, &k.scen,
                    &k.cap, &s.ring, &s.first, &s.group, &s.every, &s.waves, &s.path) == 11 &&
-            splitk::schedule_supported(s) && s.path >= 1 && s.path <= 2 && s.waves >= 0 &&
+            splitk::schedule_supported(s) && s.path >= 0 && s.path <= 2 && s.waves >= 0 &&
             s.waves <= 8) {
             splitk::g_table[k] = s;
             ++loaded;

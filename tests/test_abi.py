@@ -310,3 +310,20 @@ def test_path_choice_of_the_one_launch_form():
     finally:
         binding.profile_enable(False)
         binding.set_schedule(0)
+
+
+def test_tuned_entry_with_path_zero_selects_the_one_launch_form(tmp_path):
+    """A recorded path 0 (the tuner's record of the one-launch form) keeps
+    the automatic choice; a recorded path 1 forces the general kernels."""
+    binding.tune_clear()
+    key = (0, 4, 4, 4, 4)  # one tour, n~20, N~20, S~1000, Q~30
+    try:
+        for path, want in ((0, binding.PATH_ONE_LAUNCH), (1, binding.PATH_TILES)):
+            f = tmp_path / ("tune%d.txt" % path)
+            f.write_text("%d %d %d %d %d 32 8 3 3 0 %d\n" % (key + (path,)))
+            binding.tune_load(f)
+            assert binding.tune_lookup(1, 20, 20, 1000, 30) == (32, 8, 3, 3, 0, path)
+            assert binding.eval_path(1, 20, 20, 1000, 30) == want
+            binding.tune_clear()
+    finally:
+        binding.tune_clear()

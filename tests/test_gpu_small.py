@@ -282,3 +282,24 @@ def test_repeated_calls_reuse_the_workspace(binding):
                    means=out.means.cpu().numpy())
         ref = oracle.split_eval(tour[:n].astype(np.int32), np.array([n], np.int32), dist, dem[:S], 40)
         _same(got, ref, "n=%d S=%d" % (n, S))
+
+
+def test_tuner_times_the_one_launch_form(binding):
+    """The tuner's candidates include the one-launch form (recorded as path
+    0); whichever wins, the next evaluation of the shape takes the recorded
+    path and equals the oracle."""
+    binding.tune_clear()
+    try:
+        inst = W.plain_small(9, S=1000)
+        tours, lens, dist, dem = W.as_arrays(inst)
+        t, l, d, q = _dev(tours, lens, dist, dem)
+        ms = binding.tune_device(t, l, d, q, inst.Q, reps=5)
+        rec = binding.tune_lookup(1, 20, inst.N, inst.S, inst.Q)
+        _say("tuned n=20 S=1000 -> %s (%.4f ms)" % (rec, ms))
+        assert ms > 0 and rec is not None and rec[5] in (0, 1)
+        want = binding.PATH_ONE_LAUNCH if rec[5] == 0 else binding.PATH_TILES
+        assert binding.eval_path(1, 20, inst.N, inst.S, inst.Q) == want
+        got = _eval(binding, (t, l, d, q), inst.Q, 20)
+        _same(got, oracle.split_eval(tours, lens, dist, dem, inst.Q), "after tuning")
+    finally:
+        binding.tune_clear()
