@@ -203,8 +203,10 @@ def batched_vs_plain(torch, binding, W, reps):
 def latency_small(torch, binding, W, reps=400):
     """Config n=20, S=1000, Q=30: latency of one evaluation (launch to
     result on the host), p50/p99 over repeated calls, for the captured graph
-    (inputs resident), the eager device form and the host form (host
-    buffers in and out, copies included)."""
+    (inputs resident), the same plan launched eagerly (one library call,
+    ordinary kernel launches), the eager device form (arguments checked
+    and marshalled per call) and the host form (host buffers in and out,
+    copies included)."""
     import numpy as np
     inst = W.plain_small(1, S=1000)
     tours, lens, dist, dem = W.as_arrays(inst)
@@ -233,6 +235,7 @@ def latency_small(torch, binding, W, reps=400):
     res = {"workload": inst.name + ", uniform demands U{1..10}, int32 rounded Euclidean costs",
            "cells": cells, "reps": reps}
     res["graph"] = lat(plan.launch)
+    res["plan_eager"] = lat(plan.launch_eager)
     res["eager"] = lat(lambda: binding.split_eval_device(t, l, d, q, inst.Q, max_len=n, out=out, workspace=ws))
     res["host_form"] = lat(lambda: binding.split_eval(tours, lens, dist, dem, inst.Q))
     res["graph_cells_per_s"] = cells / (res["graph"]["p50_us"] * 1e-6)

@@ -540,13 +540,20 @@ int split_profile_read(double *kernel_ms, int64_t *launches);
  * sizes, owns its workspace, and captures the evaluation into a HIP graph
  * once; split_plan_launch replays it.  Rewriting the contents of d_tours,
  * d_lens (within max_len), d_demands between launches is allowed (the GA
- * pattern: new candidate tours, same shapes).
+ * pattern: new candidate tours, same shapes).  split_plan_launch_eager
+ * enqueues the same evaluation (same buffers, schedule and workspace) as
+ * ordinary kernel launches on `stream` instead of a graph launch: the same
+ * results, with the host-side cost of one library call and no graph
+ * launch, which is the lower latency for evaluations of a few kernels'
+ * length.  Launches of one plan on different streams must not overlap
+ * (they share the workspace and outputs).
  */
 int split_plan_create(split_plan **plan, const int32_t *d_tours, const int32_t *d_lens,
                       int32_t num_tours, int32_t max_len, const int32_t *d_dist, int32_t N,
                       const int16_t *d_demands, int64_t S, int32_t Q, int32_t *d_costs,
                       int64_t *d_sums, double *d_means, split_stream_t stream);
 int split_plan_launch(split_plan *plan, split_stream_t stream);
+int split_plan_launch_eager(split_plan *plan, split_stream_t stream);
 int split_plan_destroy(split_plan *plan);
 
 /*

@@ -35,6 +35,7 @@ EXPORTED = (
     "split_count_cells_device",
     "split_plan_create",
     "split_plan_launch",
+    "split_plan_launch_eager",
     "split_plan_destroy",
     "split_set_schedule",
     "split_list_variants",
@@ -121,6 +122,8 @@ def _load():
     lib.split_plan_create.argtypes = [ctypes.POINTER(P), P, P, i32, i32, P, i32, P, i64, i32, P, P, P, P]
     lib.split_plan_launch.restype = ctypes.c_int
     lib.split_plan_launch.argtypes = [P, P]
+    lib.split_plan_launch_eager.restype = ctypes.c_int
+    lib.split_plan_launch_eager.argtypes = [P, P]
     lib.split_plan_destroy.restype = ctypes.c_int
     lib.split_plan_destroy.argtypes = [P]
     lib.split_set_schedule.restype = ctypes.c_int
@@ -728,6 +731,11 @@ class Plan:
 
     def launch(self, stream=None):
         _check(lib.split_plan_launch(self._h, _stream_handle(stream)))
+        return self.out
+
+    def launch_eager(self, stream=None):
+        """The same evaluation as ordinary kernel launches (no graph launch)."""
+        _check(lib.split_plan_launch_eager(self._h, _stream_handle(stream)))
         return self.out
 
     def close(self):

@@ -689,6 +689,17 @@ struct split_plan {
     void *ws = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // the captured call, for eager replays (split_plan_launch_eager)
+    const int32_t *tours = nullptr, *lens = nullptr, *dist = nullptr;
+    const int16_t *demands = nullptr;
+    int32_t *costs = nullptr;
+    int64_t *sums = nullptr;
+    double *means = nullptr;
+    int32_t T = 0, max_len = 0, N = 0, Q = 0;
+    int64_t S = 0;
+    splitk::Schedule sched{};
+    bool ordered = false;
+    splitk::Workspace wsv{};
 };
 
 int split_plan_create(split_plan **plan, const int32_t *d_tours, const int32_t *d_lens,
@@ -732,6 +743,24 @@ int split_plan_create(split_plan **plan, const int32_t *d_tours, const int32_t *
         if (e != hipSuccess)
             rc = hip_fail(e, "graph instantiate");
     }
+    if (rc == SPLIT_OK) {
+        // the same call as the captured one: the schedule and workspace
+        // layout in force at creation
+        p->tours = d_tours;
+        p->lens = d_lens;
+        p->dist = d_dist;
+        p->demands = d_demands;
+        p->costs = d_costs;
+        p->sums = d_sums;
+        p->means = d_means;
+        p->T = num_tours;
+        p->max_len = max_len;
+        p->N = N;
+        p->Q = Q;
+        p->S = S;
+        p->sched = splitk::choose_schedule(num_tours, max_len, N, S, Q, &p->ordered);
+        p->wsv = splitk::carve_workspace(p->ws, num_tours, max_len, N, S, p->ordered);
+    }
     (void)hipStreamDestroy(cap);
     if (rc != SPLIT_OK) {
         if (p->exec)
@@ -752,6 +781,19 @@ int split_plan_launch(split_plan *plan, split_stream_t stream)
     if (!plan || !plan->exec)
         return fail(SPLIT_EINVAL, "null plan");
     HIP_TRY(hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream)), "graph launch");
+    return SPLIT_OK;
+}
+
+int split_plan_launch_eager(split_plan *plan, split_stream_t stream)
+{
+    splitk::clear_error();
+    if (!plan || !plan->exec)
+        return fail(SPLIT_EINVAL, "null plan");
+    HIP_TRY(splitk::run_eval(plan->tours, plan->lens, plan->T, plan->max_len, plan->dist, plan->N,
+                             plan->demands, plan->S, plan->Q, plan->costs, plan->sums,
+                             plan->means, plan->wsv, static_cast<hipStream_t>(stream),
+                             plan->sched, plan->ordered, nullptr),
+            "launch");
     return SPLIT_OK;
 }
 

@@ -290,7 +290,7 @@ def test_plan_graph_replays_match_eager(binding):
     t, l, d, q = _to_dev(tours, lens, dist, dem)
     plan = binding.Plan(t, l, d, q, inst.Q, max_len=400)
     rng = np.random.default_rng(8)
-    for rep in range(4):
+    for rep in range(6):
         _say("plan replay %d" % rep)
         if rep:
             # new candidate tours of the same lengths (the search pattern)
@@ -299,7 +299,8 @@ def test_plan_graph_replays_match_eager(binding):
                 new.append(W.two_opt_perturb(rng, inst.tour(k), 5))
             tours = np.concatenate(new).astype(np.int32)
             t.copy_(torch.from_numpy(tours))
-        plan.launch()
+        # graph replays and eager replays of the plan in turn
+        plan.launch() if rep % 2 == 0 else plan.launch_eager()
         torch.cuda.synchronize()
         got = dict(costs=plan.out.costs.cpu().numpy(), sums=plan.out.sums.cpu().numpy(),
                    means=plan.out.means.cpu().numpy())

@@ -242,15 +242,16 @@ def test_inputs_rejected_on_the_device(binding):
 
 
 def test_plan_graph_replays(binding):
-    """A captured plan of a one-launch shape replays to the eager result."""
+    """A captured plan of a one-launch shape, replayed as a graph and as
+    eager launches in turn, gives the oracle's result every time."""
     inst = W.plain_small(7, S=1000)
     tours, lens, dist, dem = W.as_arrays(inst)
     ref = oracle.split_eval(tours, lens, dist, dem, inst.Q)
     t, l, d, q = _dev(tours, lens, dist, dem)
     plan = binding.Plan(t, l, d, q, inst.Q, int(lens.max()))
     try:
-        for r in range(4):
-            out = plan.launch()
+        for r in range(6):
+            out = plan.launch() if r % 2 == 0 else plan.launch_eager()
             torch.cuda.synchronize()
             got = dict(costs=out.costs.cpu().numpy(), sums=out.sums.cpu().numpy(),
                        means=out.means.cpu().numpy())
