@@ -728,6 +728,13 @@ int split_plan_create(split_plan **plan, const int32_t *d_tours, const int32_t *
         return hip_fail(e, "capture stream");
     }
     (void)stream;
+    e = splitk::small_prepare(); // one-time kernel set-up outside the capture
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cap);
+        (void)hipFree(p->ws);
+        delete p;
+        return hip_fail(e, "kernel set-up");
+    }
     e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         rc = split_eval_device(d_tours, d_lens, num_tours, max_len, d_dist, N, d_demands, S, Q,

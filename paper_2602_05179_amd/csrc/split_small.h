@@ -24,6 +24,11 @@ constexpr int32_t kSmallMaxN = 256;
 bool small_path_fits(int32_t num_tours, int32_t max_len, int32_t N, int64_t S,
                      const Schedule &s, bool ordered);
 
+// one-time set-up of the one-launch kernels (their LDS limit), done by the
+// first launch; a caller about to capture a graph calls it first, so that
+// no such set-up falls inside the capture
+hipError_t small_prepare();
+
 // tables, recursion, exact fallback and the fold in one launch; the same
 // workspace layout, costs, sums and means as launch_eval for one tour
 hipError_t launch_small(const int32_t *tours, const int32_t *lens, int32_t max_len,

@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "split_device.h"
 #include "split_dp.h"
 #include "split_eval.h"
@@ -245,22 +247,28 @@ hipError_t launch_small_t(const int32_t *tours, const int32_t *lens, int32_t max
 {
     constexpr int THREADS = small_threads<R>();
     const size_t lds = (size_t)(THREADS / kWave) * small_row_bytes(N);
-    static bool attr = false;
-    if (!attr) {
-        const hipError_t e = hipFuncSetAttribute(
-            reinterpret_cast<const void *>(&small_kernel<R, F, G, E>),
-            hipFuncAttributeMaxDynamicSharedMemorySize,
-            (int)((size_t)(THREADS / kWave) * small_row_bytes(kSmallMaxN)));
-        if (e != hipSuccess)
-            return e;
-        attr = true;
-    }
     hipLaunchKernelGGL((small_kernel<R, F, G, E>), dim3(1), dim3(THREADS), lds, stream, tours,
                        lens, max_len, dist, N, demands, S, Q, costs, sums, means, ws);
     return hipGetLastError();
 }
 
 } // namespace
+
+hipError_t small_prepare()
+{
+    static std::once_flag once;
+    static hipError_t err = hipSuccess;
+    std::call_once(once, [] {
+        const int bytes = (int)((size_t)(small_threads<32>() / kWave) * small_row_bytes(kSmallMaxN));
+#define SPLIT_SMALL_ATTR(R_, F_, G_, E_)                                                         \
+    if (err == hipSuccess)                                                                       \
+        err = hipFuncSetAttribute(reinterpret_cast<const void *>(&small_kernel<R_, F_, G_, E_>),   \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        SPLIT_WINDOW_VARIANTS(SPLIT_SMALL_ATTR)
+#undef SPLIT_SMALL_ATTR
+    });
+    return err;
+}
 
 bool small_path_fits(int32_t num_tours, int32_t max_len, int32_t N, int64_t S,
                      const Schedule &s, bool ordered)
@@ -280,6 +288,9 @@ hipError_t launch_small(const int32_t *tours, const int32_t *lens, int32_t max_l
                         int32_t Q, int32_t *costs, int64_t *sums, double *means,
                         const Workspace &ws, hipStream_t stream, const Schedule &s)
 {
+    const hipError_t e = small_prepare();
+    if (e != hipSuccess)
+        return e;
 #define SPLIT_SMALL(R_, F_, G_, E_)                                                              \
     if (s.ring == R_ && s.first == F_ && s.group == G_ && s.every == E_)                         \
         return launch_small_t<R_, F_, G_, E_>(tours, lens, max_len, dist, N, demands, S, Q, costs, \

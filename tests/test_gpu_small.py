@@ -304,3 +304,38 @@ def test_tuner_times_the_one_launch_form(binding):
         _same(got, oracle.split_eval(tours, lens, dist, dem, inst.Q), "after tuning")
     finally:
         binding.tune_clear()
+
+
+_PLAN_FIRST = r'''
+import sys
+import numpy as np
+import torch
+sys.path.insert(0, sys.argv[1])
+import oracle
+from paper_2602_05179_amd import binding, workloads as W
+inst = W.plain_small(11, S=1000)
+tours, lens, dist, dem = W.as_arrays(inst)
+t, l, d, q = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (tours, lens, dist, dem))
+assert binding.eval_path(1, 20, inst.N, inst.S, inst.Q) == binding.PATH_ONE_LAUNCH
+plan = binding.Plan(t, l, d, q, inst.Q, 20)   # the process's first evaluation
+ref = oracle.split_eval(tours, lens, dist, dem, inst.Q)
+for r in range(3):
+    out = plan.launch() if r != 1 else plan.launch_eager()
+    torch.cuda.synchronize()
+    assert np.array_equal(out.costs.cpu().numpy(), ref["costs"]), r
+    assert np.array_equal(out.sums.cpu().numpy(), ref["sums"]), r
+plan.close()
+print("plan-first ok")
+'''
+
+
+def test_plan_as_the_first_evaluation_of_a_process(binding):
+    """A fresh process whose first evaluation is a captured plan of a
+    one-launch shape: the kernels' one-time set-up happens before the
+    capture, and the graph and eager replays equal the oracle."""
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    _say("plan-first subprocess")
+    r = subprocess.run([sys.executable, "-c", _PLAN_FIRST, root], capture_output=True, text=True,
+                       timeout=300, cwd=root)
+    assert r.returncode == 0 and "plan-first ok" in r.stdout, r.stdout[-2000:] + r.stderr[-2000:]
