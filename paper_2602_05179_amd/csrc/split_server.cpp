@@ -484,16 +484,18 @@ struct split_server {
             // the drain starts after the latest publication has landed
             hipError_t e = pub_recorded ? hipStreamWaitEvent(st, pub_event, 0) : hipSuccess;
             // Drain life by backlog: with several tiles per drain wave queued
-            // (saturation) a drain takes tiles for 32 ms and waits 200 us for
+            // (saturation) a drain takes tiles for 24 ms and waits 200 us for
             // more, since each change of drain costs the device the tail of
             // the old drain's last tiles and a drain's stream keeps later
             // launches that share its hardware queue waiting until it ends;
-            // otherwise 1 ms and 20 us, so a light stream's launches and
+            // longer lives hold retired jobs' tables (released only after the
+            // drains running at retirement end) and with them admission.
+            // Otherwise 1 ms and 20 us, so a light stream's launches and
             // retired memory do not wait long.
             const bool busy = backlog_tiles > 4 * (int64_t)drain_grid[qi];
-            const auto life = std::chrono::microseconds(busy ? 32000 : 1000);
+            const auto life = std::chrono::microseconds(busy ? 24000 : 1000);
             splitk::ServeCtl c = ctl;
-            c.life_ticks = (long long)rate_khz * (busy ? 32 : 1);
+            c.life_ticks = (long long)rate_khz * (busy ? 24 : 1);
             c.idle_ticks = (long long)rate_khz / (busy ? 5 : 50);
             if (e == hipSuccess)
                 e = splitk::serve_launch_drain(qi, c, d_queue[qi], drain_grid[qi], st);
