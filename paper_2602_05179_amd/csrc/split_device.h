@@ -51,11 +51,13 @@ __device__ __forceinline__ int wave_sum_i32(int v)
 // returns false (uniformly) when some value is outside [0, 255]
 // s_bad: an LDS word outside the staged bytes (the block-wide "bad" flag)
 //
-// The 16-byte chunks of a thread are fetched kStageBatch at a time, all in
-// flight together before any is narrowed: a one-wave block stages a
-// 64 x 200 tile (25 chunks per lane) in two memory round trips instead of
-// one per four chunks.  The ring registers of the recursion are not live
-// yet, so the batch costs no occupancy.
+// The 16-byte chunks of a thread are fetched BATCH at a time, all in
+// flight together before any is narrowed: with 16 a one-wave block stages
+// a 64 x 200 tile (25 chunks per lane) in two memory round trips instead of
+// one per four chunks, with 28 in one.  The ring registers of the recursion
+// are not live yet, so a batch costs occupancy only where its registers
+// exceed the recursion's (the main tile kernel: 142-152 VGPRs at 28, still
+// three waves per SIMD, its LDS limit).
 // ---------------------------------------------------------------------------
 constexpr int kStageBatch = 16;
 
@@ -69,6 +71,7 @@ __device__ __forceinline__ uint2 narrow_chunk(const u32x4 v, uint32_t &bad)
     return o;
 }
 
+template <int BATCH = kStageBatch>
 __device__ __forceinline__ bool stage_tile_u8(const int16_t *__restrict__ src, uint8_t *lds,
                                               int64_t elems, int tid, int nthreads, int &s_bad)
 {
@@ -80,14 +83,14 @@ __device__ __forceinline__ bool stage_tile_u8(const int16_t *__restrict__ src, u
     GU32x4 *src4 = (GU32x4 *)reinterpret_cast<const u32x4 *>(src);
     GI16 *gsrc = (GI16 *)src;
     uint2 *dst8 = reinterpret_cast<uint2 *>(lds);
-    for (int64_t i = tid; i < chunks; i += (int64_t)kStageBatch * nthreads) {
-        u32x4 v[kStageBatch];
+    for (int64_t i = tid; i < chunks; i += (int64_t)BATCH * nthreads) {
+        u32x4 v[BATCH];
 #pragma unroll
-        for (int r = 0; r < kStageBatch; ++r)
+        for (int r = 0; r < BATCH; ++r)
             if (i + (int64_t)r * nthreads < chunks)
                 v[r] = __builtin_nontemporal_load(&src4[i + (int64_t)r * nthreads]);
 #pragma unroll
-        for (int r = 0; r < kStageBatch; ++r)
+        for (int r = 0; r < BATCH; ++r)
             if (i + (int64_t)r * nthreads < chunks)
                 dst8[i + (int64_t)r * nthreads] = narrow_chunk(v[r], bad);
     }

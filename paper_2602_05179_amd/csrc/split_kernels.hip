@@ -244,8 +244,14 @@ __global__ __launch_bounds__(kPrepThreads) void prep_kernel(
 // LDS: 64 x N demand bytes
 // ---------------------------------------------------------------------------
 constexpr int kMaxWavesPerGroup = 8;
+// 16-byte chunks per thread in flight while a one-wave workgroup stages its
+// tile: a 64 x 224 tile in one memory round trip (n = N = 200, S = 10^6,
+// Q = 150: 253 -> 245 us against batches of 16).  Its registers (142-152
+// VGPRs) allow three waves per SIMD, so it is used only where the tile's
+// LDS already allows no more; multi-wave workgroups keep kStageBatch.
+constexpr int kTileStageBatch = 28;
 
-template <int R, int F, int G, int E>
+template <int R, int F, int G, int E, int SB>
 __global__ __launch_bounds__(kWave *kMaxWavesPerGroup) void split_tile_kernel(
     const int16_t *__restrict__ demands, int32_t N, int64_t S, int32_t Q, int32_t T,
     int32_t *__restrict__ costs, Workspace ws, int32_t use_lds, int32_t by_length)
@@ -280,8 +286,8 @@ __global__ __launch_bounds__(kWave *kMaxWavesPerGroup) void split_tile_kernel(
     bool ok = false;
     if (use_lds) {
         int &s_bad = *reinterpret_cast<int *>(lds + (((size_t)kWave * N + 15) & ~(size_t)15));
-        ok = stage_tile_u8(demands + s0 * N, lds, (int64_t)rows * N, threadIdx.x, blockDim.x,
-                           s_bad);
+        ok = stage_tile_u8<SB>(demands + s0 * N, lds, (int64_t)rows * N, threadIdx.x, blockDim.x,
+                               s_bad);
         __syncthreads();
     }
     if (t >= T)
@@ -795,8 +801,12 @@ static hipError_t launch_tiles(const int16_t *demands, int32_t N, int64_t S, int
             return e;
         lim = lim < kLdsLimit ? lim : kLdsLimit;
         e = hipFuncSetAttribute(
-            reinterpret_cast<const void *>(&split_tile_kernel<R, F, G, E>),
+            reinterpret_cast<const void *>(&split_tile_kernel<R, F, G, E, kStageBatch>),
             hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(
+                reinterpret_cast<const void *>(&split_tile_kernel<R, F, G, E, kTileStageBatch>),
+                hipFuncAttributeMaxDynamicSharedMemorySize, lim);
         if (e != hipSuccess)
             return e;
         lds_limit = lim;
@@ -817,9 +827,17 @@ static hipError_t launch_tiles(const int16_t *demands, int32_t N, int64_t S, int
         if (e != hipSuccess)
             return e;
     }
-    hipLaunchKernelGGL((split_tile_kernel<R, F, G, E>), dim3((unsigned)groups),
-                       dim3(kWave * W), lds_bytes, stream, demands, N, S, Q, T, costs, ws,
-                       use_lds, by_length);
+    // the larger staging batch where LDS caps a CU at 12 one-wave
+    // workgroups (three per SIMD) anyway
+    const bool wide_stage = W == 1 && use_lds && (size_t)kLdsLimit / lds <= 12;
+    if (wide_stage)
+        hipLaunchKernelGGL((split_tile_kernel<R, F, G, E, kTileStageBatch>), dim3((unsigned)groups),
+                           dim3(kWave * W), lds_bytes, stream, demands, N, S, Q, T, costs, ws,
+                           use_lds, by_length);
+    else
+        hipLaunchKernelGGL((split_tile_kernel<R, F, G, E, kStageBatch>), dim3((unsigned)groups),
+                           dim3(kWave * W), lds_bytes, stream, demands, N, S, Q, T, costs, ws,
+                           use_lds, by_length);
     return hipGetLastError();
 }
 
