@@ -496,8 +496,9 @@ def served(torch, binding, W, num_requests, pool_size, budget_gb, seed=5):
     instances (n ~ U{50..1000} customers, S ~ 10^U(3,5) scenarios,
     Normal(mu,0.3mu) demands), continuous batching at tile granularity
     under an HBM budget small enough that admission queues.  Saturation
-    (every request queued at once), then Poisson arrivals at 0.5, 0.8 and
-    0.95 of the saturated rate; latency from submission to the result."""
+    (every request queued at once; the median of three passes after a
+    warm-up pass), then Poisson arrivals at 0.5, 0.8 and 0.95 of the
+    saturated rate; latency from submission to the result."""
     import threading
 
     import numpy as np
@@ -560,9 +561,16 @@ def served(torch, binding, W, num_requests, pool_size, budget_gb, seed=5):
     log("served: %d resident instances, %.0f MB of demands, %.3g cells per request" % (
         len(pool), resident / 1e6, float(cells.mean())))
     run(None)  # warm-up pass (drain kernels, caches, host threads)
-    sat = run(None)
-    log("served saturated: %.0f requests/s, %.3g cells/s, p50 %.2f ms, p99 %.2f ms" % (
-        sat["req_per_s"], sat["cells_per_s"], sat["p50_ms"], sat["p99_ms"]))
+    # three saturated passes; the one with the median rate is reported (a
+    # single pass varies by several percent from run to run), all three
+    # rates beside it
+    passes = sorted((run(None) for _ in range(3)), key=lambda r: r["cells_per_s"])
+    sat = dict(passes[1])
+    sat["basis"] = "median of 3 saturated passes"
+    sat["cells_per_s_passes"] = [p["cells_per_s"] for p in passes]
+    log("served saturated: %.0f requests/s, %.3g cells/s (passes %s), p50 %.2f ms, p99 %.2f ms" % (
+        sat["req_per_s"], sat["cells_per_s"], ", ".join("%.3g" % p["cells_per_s"] for p in passes),
+        sat["p50_ms"], sat["p99_ms"]))
     out = {"workload": "%d requests over %d resident instances: n~U{50..1000}, S~10^U(3,5), "
                        "Q in {80,150,300}, Normal(mu,0.3mu) demands, a fresh tour per request"
                        % (num_requests, len(pool)),
